@@ -1,0 +1,9 @@
+"""MI355X-native tensor-path equi-join and sort (gfx950 HIP kernels behind a C ABI).
+
+The library itself is lib/libtj.so (include/tj.h); this package is its thin
+binding. Loading is lazy, and there is no CPU fallback: the calls raise when
+the library is missing or no GPU is visible.
+"""
+from .tj import (TjError, join, join_count, load, sort, strerror,  # noqa: F401
+                 workspace_query, TJ_KEY_I32, TJ_KEY_I64, TJ_OP_SORT, TJ_OP_JOIN_COUNT,
+                 TJ_OP_JOIN_MATERIALIZE)

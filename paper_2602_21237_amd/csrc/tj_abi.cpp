@@ -1,0 +1,1275 @@
+// tj_abi.cpp - host planner and the C-ABI entry points (include/tj.h).
+//
+// The planner drives the MSD radix plan of the tensor path:
+//   probe   min / max ordinal of the keys (the "axis" extent, Sec. III.B);
+//   passes  histogram + scan + stable scatter, splitting every bucket that is
+//           larger than one LDS block by the next digit of its own key range
+//           (the step-by-step relocation of Sec. IV.B, the alignment of both
+//           relations on the join axis of Sec. IV.A);
+//   leaves  runs of adjacent small buckets, each sorted (sort) or sorted and
+//           matched (join) inside one LDS block;
+//   singles buckets holding one key value: copied (sort) or expanded as a
+//           cross product (join).
+// Only the join pairs are materialised, and only at the end (Sec. III.A).
+// Between passes the planner reads back the child-bucket table (sizes and key
+// ranges) to size the next launch; no row data crosses to the host.
+//
+// Workspace budget (the work_mem analogue, Sec. VI Eq. 1): when the caller's
+// workspace cannot hold the ping-pong buffers for all rows, the key domain is
+// cut into ranges from a coarse key histogram, each range small enough for the
+// workspace, and each range is processed on its own; its first pass scans the
+// whole input and keeps only the range's rows. The extra input scans are the
+// GPU counterpart of the spill term alpha(N, M).
+#include "tj_internal.h"
+#include "../../include/tj.h"
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+namespace tj {
+namespace {
+
+constexpr uint64_t ALIGN = 256;
+constexpr int TABLE_TIERS = 8;
+constexpr uint64_t TARGET_CHUNKS = 2048;  // blocks per partition pass
+
+inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+inline uint32_t nbits64(uint64_t x) { return x ? 64u - (uint32_t)__builtin_clzll(x) : 0u; }
+
+// Table capacities of one tier.
+struct Caps {
+    uint32_t groups, chunks, cblocks, leaves, units;
+};
+
+Caps tier_caps(int t)
+{
+    Caps c;
+    c.groups = 16u << t;
+    c.chunks = 64u << t;
+    c.cblocks = 16u << t;
+    c.leaves = 256u << t;
+    c.units = 64u << t;
+    return c;
+}
+
+uint64_t table_bytes(const Caps& c)
+{
+    uint64_t b = 0;
+    b += align_up(256, ALIGN);                                        // probe + scalars
+    b += align_up((uint64_t)c.groups * sizeof(GroupDesc), ALIGN);
+    b += align_up((uint64_t)c.chunks * sizeof(ChunkDesc), ALIGN);
+    b += align_up((uint64_t)c.cblocks * sizeof(CBlockDesc), ALIGN);
+    b += align_up((uint64_t)c.chunks * NB * 4, ALIGN);               // hist
+    b += align_up((uint64_t)c.cblocks * NB * 4, ALIGN);              // cbsum
+    const uint64_t children = (uint64_t)c.groups * NB;
+    b += align_up(children * 4, ALIGN);                               // ccount
+    b += 3 * align_up(children * 8, ALIGN);                           // cstart, gmin, gmax
+    b += align_up((uint64_t)c.leaves * sizeof(LeafDesc), ALIGN);
+    b += align_up((uint64_t)c.leaves * 8, ALIGN);                    // leaf counts
+    const uint64_t ub = sizeof(CrossDesc) > sizeof(CopyDesc) ? sizeof(CrossDesc) : sizeof(CopyDesc);
+    b += align_up((uint64_t)c.units * ub, ALIGN);
+    return b;
+}
+
+// Bytes of one row in the ping-pong buffers.
+inline uint64_t row_bytes(int kb, bool rids) { return (uint64_t)kb + (rids ? 4u : 0u); }
+
+struct Shape {
+    int op, kb;
+    bool join, mat, rids;
+    uint64_t n_r, n_s;
+};
+
+// Data bytes of the unlimited plan: the sort keeps one buffer in the
+// workspace (its other buffer is the caller's output), the join two per side.
+uint64_t full_data_bytes(const Shape& s)
+{
+    const int nbuf = s.join ? 2 : 1;
+    uint64_t b = 0;
+    for (int buf = 0; buf < nbuf; buf++)
+        for (uint64_t n : {s.n_r, s.n_s}) {
+            if (n == 0) continue;
+            b += align_up(n * (uint64_t)s.kb, ALIGN);
+            if (s.rids) b += align_up(n * 4, ALIGN);
+        }
+    return b;
+}
+
+// Smallest data region: two buffers of one leaf block of rows per side, plus
+// alignment slack.
+uint64_t min_data_bytes(const Shape& s)
+{
+    const uint64_t per = align_up((uint64_t)LEAF_CAP * row_bytes(s.kb, s.rids), ALIGN) * 2 + 16 * ALIGN;
+    return s.join ? 2 * per : per;
+}
+
+const uint64_t kMaxRows = (1ull << 31) - 1;
+
+// ---------------------------------------------------------------------------
+// The executor of one call.
+// ---------------------------------------------------------------------------
+struct Seg {
+    uint64_t r0, rn, s0, sn;  // row ranges (side 0, side 1)
+    uint64_t lo, hi;          // ordinal range present (lo > hi: no rows)
+    uint32_t buf;
+};
+
+struct Unit {                 // a final piece of join output, ordered by key
+    uint64_t lo;
+    int kind;                 // 0 leaf, 1 cross
+    uint32_t index;           // into leaves / crosses
+    uint64_t count;
+};
+
+#define TJ_CK(expr)                                   \
+    do {                                              \
+        hipError_t e_ = (expr);                       \
+        if (e_ != hipSuccess) return TJ_E_HIP;        \
+    } while (0)
+
+#define TJ_RET(expr)                                  \
+    do {                                              \
+        int r_ = (expr);                              \
+        if (r_ != TJ_OK) return r_;                   \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Kernel timing registry (tj_timing / tj_timing_read).
+// ---------------------------------------------------------------------------
+enum Fam { F_PROBE, F_HIST, F_SCAN, F_SCATTER, F_LEAF_SORT, F_LEAF_COUNT, F_LEAF_MAT, F_CROSS, F_COPY,
+           F_EXPAND, NFAM };
+const char* const kFamName[NFAM] = {"probe", "histogram", "scan", "scatter", "leaf_sort",
+                                    "leaf_join_count", "leaf_join_mat", "cross", "copy", "expand"};
+
+struct Timing {
+    std::mutex mu;
+    bool on = false;
+    uint64_t launches[NFAM] = {};
+    uint64_t bytes[NFAM] = {};
+    double ms[NFAM] = {};
+};
+Timing& timing()
+{
+    static Timing t;
+    return t;
+}
+
+struct Pending {
+    int fam;
+    hipEvent_t a, b;
+    uint64_t bytes;
+};
+
+struct Exec {
+    Shape sh;
+    hipStream_t st = nullptr;
+    BufSet bufs{};
+    Caps caps{};
+    tj_stats_t stats{};
+
+    // device tables
+    uint64_t* d_probe = nullptr;
+    GroupDesc* d_groups = nullptr;
+    ChunkDesc* d_chunks = nullptr;
+    CBlockDesc* d_cblocks = nullptr;
+    uint32_t* d_hist = nullptr;
+    uint32_t* d_cbsum = nullptr;
+    uint32_t* d_ccount = nullptr;
+    uint64_t* d_cstart = nullptr;
+    uint64_t* d_gmin = nullptr;
+    uint64_t* d_gmax = nullptr;
+    LeafDesc* d_leaves = nullptr;
+    uint64_t* d_counts = nullptr;
+    void* d_units = nullptr;
+
+    // data buffer capacities (rows per side) when the buffers live in the workspace
+    uint64_t cap_r = 0, cap_s = 0;
+    bool out_is_a = false;  // sort: buffer A is the caller's output
+    bool write_keys = true; // partition passes write key columns (off: rid-only compaction)
+
+    // timing of this call's launches (when enabled)
+    bool timed_on = false;
+    std::vector<Pending> pending;
+
+    template <class F>
+    hipError_t timed(int fam, uint64_t bytes, F&& f)
+    {
+        if (!timed_on) return f();
+        Pending p{fam, nullptr, nullptr, bytes};
+        if (hipEventCreate(&p.a) != hipSuccess || hipEventCreate(&p.b) != hipSuccess) return hipErrorUnknown;
+        hipError_t e = hipEventRecord(p.a, st);
+        if (e == hipSuccess) e = f();
+        if (e == hipSuccess) e = hipEventRecord(p.b, st);
+        pending.push_back(p);
+        return e;
+    }
+
+    // Accumulates the event durations of this call (stream already synchronised).
+    void flush_timing()
+    {
+        if (pending.empty()) return;
+        Timing& t = timing();
+        std::lock_guard<std::mutex> g(t.mu);
+        for (Pending& p : pending) {
+            float ms = 0;
+            if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+                t.launches[p.fam]++;
+                t.bytes[p.fam] += p.bytes;
+                t.ms[p.fam] += ms;
+            }
+            (void)hipEventDestroy(p.a);
+            (void)hipEventDestroy(p.b);
+        }
+        pending.clear();
+    }
+
+    ~Exec() { flush_timing(); }
+
+    // host-side results
+    std::vector<LeafDesc> leaves;
+    std::vector<uint64_t> leaf_lo;
+    std::vector<CrossDesc> crosses;
+    std::vector<uint64_t> cross_lo;
+    std::vector<CopyDesc> copies;
+
+    // ---- workspace layout -------------------------------------------------
+    int carve_tables(char*& p, char* end)
+    {
+        auto take = [&](uint64_t bytes) -> char* {
+            char* q = p;
+            p += align_up(bytes, ALIGN);
+            return q;
+        };
+        d_probe = (uint64_t*)take(256);
+        d_groups = (GroupDesc*)take((uint64_t)caps.groups * sizeof(GroupDesc));
+        d_chunks = (ChunkDesc*)take((uint64_t)caps.chunks * sizeof(ChunkDesc));
+        d_cblocks = (CBlockDesc*)take((uint64_t)caps.cblocks * sizeof(CBlockDesc));
+        d_hist = (uint32_t*)take((uint64_t)caps.chunks * NB * 4);
+        d_cbsum = (uint32_t*)take((uint64_t)caps.cblocks * NB * 4);
+        const uint64_t children = (uint64_t)caps.groups * NB;
+        d_ccount = (uint32_t*)take(children * 4);
+        d_cstart = (uint64_t*)take(children * 8);
+        d_gmin = (uint64_t*)take(children * 8);
+        d_gmax = (uint64_t*)take(children * 8);
+        d_leaves = (LeafDesc*)take((uint64_t)caps.leaves * sizeof(LeafDesc));
+        d_counts = (uint64_t*)take((uint64_t)caps.leaves * 8);
+        const uint64_t ub = sizeof(CrossDesc) > sizeof(CopyDesc) ? sizeof(CrossDesc) : sizeof(CopyDesc);
+        d_units = take((uint64_t)caps.units * ub);
+        return p <= end ? TJ_OK : TJ_E_WORKSPACE;
+    }
+
+    // ---- one partition pass over a list of segments that live in `src` ----
+    // Appends the children (in key order) to `out`.
+    int run_pass(const std::vector<Seg>& segs, uint32_t src, uint32_t dst,
+                 const uint64_t* filter, std::vector<Seg>& out)
+    {
+        stats.passes++;
+        const int nside = sh.join ? 2 : 1;
+        // per segment digit choice
+        struct Plan {
+            uint32_t shift, bits;
+        };
+        std::vector<Plan> plan(segs.size());
+        uint64_t total_rows = 0;
+        for (size_t i = 0; i < segs.size(); i++) {
+            const Seg& s = segs[i];
+            const uint64_t rows = s.rn + s.sn;
+            const uint32_t kbits = nbits64(s.hi - s.lo);
+            uint32_t want = 1;
+            while (want < (uint32_t)MAX_DIGIT_BITS && (rows >> want) > (uint64_t)LEAF_CAP / 2) want++;
+            uint32_t b = std::min<uint32_t>(want, kbits);
+            if (b == 0) b = 1;  // filtered roots of a single-key range still need a compaction pass
+            plan[i].bits = b;
+            plan[i].shift = kbits > b ? kbits - b : 0;
+            total_rows += filter ? (uint64_t)(i == 0 ? sh.n_r + sh.n_s : 0) : rows;
+        }
+        uint64_t ch_rows = align_up((total_rows + TARGET_CHUNKS - 1) / TARGET_CHUNKS, PART_TILE);
+        if (ch_rows < PART_TILE) ch_rows = PART_TILE;
+        // make sure the largest group fits the chunk table
+        for (size_t i = 0; i < segs.size(); i++) {
+            const uint64_t lr = filter ? sh.n_r : segs[i].rn;
+            const uint64_t ls = filter ? (sh.join ? sh.n_s : 0) : segs[i].sn;
+            while ((lr + ch_rows - 1) / ch_rows + (ls + ch_rows - 1) / ch_rows > caps.chunks) ch_rows *= 2;
+        }
+
+        std::vector<GroupDesc> groups;
+        std::vector<ChunkDesc> chunks;
+        std::vector<CBlockDesc> cblocks;
+        std::vector<size_t> gseg;  // group -> segment
+        size_t si = 0;
+        while (si < segs.size()) {
+            groups.clear();
+            chunks.clear();
+            cblocks.clear();
+            gseg.clear();
+            uint32_t child = 0;
+            const size_t first = si;
+            // fill one launch batch
+            while (si < segs.size()) {
+                const Seg& s = segs[si];
+                uint64_t need_chunks = 0, need_cb = 0;
+                for (int side = 0; side < nside; side++) {
+                    const uint64_t len = filter ? (side ? sh.n_s : sh.n_r) : (side ? s.sn : s.rn);
+                    const uint64_t nc = (len + ch_rows - 1) / ch_rows;
+                    need_chunks += nc;
+                    need_cb += (nc + CBLOCK - 1) / CBLOCK;
+                }
+                if (groups.size() + nside > caps.groups || chunks.size() + need_chunks > caps.chunks ||
+                    cblocks.size() + need_cb > caps.cblocks) {
+                    if (groups.empty()) return TJ_E_WORKSPACE;
+                    break;
+                }
+                for (int side = 0; side < nside; side++) {
+                    GroupDesc g{};
+                    const uint64_t len = filter ? (side ? sh.n_s : sh.n_r) : (side ? s.sn : s.rn);
+                    g.start = filter ? 0 : (side ? s.s0 : s.r0);
+                    g.len = len;
+                    g.dst_start = filter ? 0 : (side ? s.s0 : s.r0);
+                    g.base = s.lo;
+                    g.flo = filter ? filter[0] : 0;
+                    g.fhi = filter ? filter[1] : ~0ull;
+                    g.shift = plan[si].shift;
+                    g.bits = plan[si].bits;
+                    g.side = (uint32_t)side;
+                    g.src = src;
+                    g.dst = dst;
+                    g.chunk0 = (uint32_t)chunks.size();
+                    g.cblock0 = (uint32_t)cblocks.size();
+                    g.child0 = child;
+                    child += 1u << g.bits;
+                    const uint32_t gi = (uint32_t)groups.size();
+                    for (uint64_t c0 = 0; c0 < len; c0 += ch_rows) {
+                        ChunkDesc c{};
+                        c.start = g.start + c0;
+                        c.len = (uint32_t)std::min<uint64_t>(ch_rows, len - c0);
+                        c.group = gi;
+                        c.cblock = (uint32_t)(cblocks.size() + (chunks.size() - g.chunk0) / CBLOCK);
+                        chunks.push_back(c);
+                    }
+                    g.nchunks = (uint32_t)chunks.size() - g.chunk0;
+                    for (uint32_t c = 0; c < g.nchunks; c += CBLOCK) {
+                        CBlockDesc b{};
+                        b.group = gi;
+                        b.chunk0 = g.chunk0 + c;
+                        b.nchunks = std::min<uint32_t>(CBLOCK, g.nchunks - c);
+                        cblocks.push_back(b);
+                    }
+                    g.ncblocks = (uint32_t)cblocks.size() - g.cblock0;
+                    groups.push_back(g);
+                    gseg.push_back(si);
+                    stats.bytes_read += len * (uint64_t)sh.kb;                                   // histogram
+                    stats.bytes_read += len * (uint64_t)sh.kb + (sh.rids ? len * 4 : 0);         // scatter
+                }
+                si++;
+            }
+            const uint32_t ng = (uint32_t)groups.size(), nc = (uint32_t)chunks.size(),
+                           ncb = (uint32_t)cblocks.size();
+            TJ_CK(hipMemcpyAsync(d_groups, groups.data(), ng * sizeof(GroupDesc), hipMemcpyHostToDevice, st));
+            TJ_CK(hipMemcpyAsync(d_chunks, chunks.data(), nc * sizeof(ChunkDesc), hipMemcpyHostToDevice, st));
+            TJ_CK(hipMemcpyAsync(d_cblocks, cblocks.data(), ncb * sizeof(CBlockDesc), hipMemcpyHostToDevice, st));
+            TJ_CK(launch_fill_u64(d_gmin, child, ~0ull, st));
+            TJ_CK(launch_fill_u64(d_gmax, child, 0ull, st));
+            uint64_t scanned = 0, moved = 0;
+            for (const GroupDesc& g : groups) {
+                scanned += g.len;
+                const Seg& s = segs[gseg[&g - groups.data()]];
+                moved += g.side ? s.sn : s.rn;
+            }
+            const uint64_t rb = row_bytes(sh.kb, sh.rids), wb = (write_keys ? sh.kb : 0) + (sh.rids ? 4 : 0);
+            TJ_CK(timed(F_HIST, scanned * sh.kb, [&] {
+                return launch_hist(sh.kb, d_chunks, nc, d_groups, bufs, d_hist, d_gmin, d_gmax, st);
+            }));
+            TJ_CK(timed(F_SCAN, 0, [&] {
+                return launch_scan(d_cblocks, ncb, d_groups, ng, d_hist, d_cbsum, d_ccount, d_cstart, st);
+            }));
+            TJ_CK(timed(F_SCATTER, scanned * rb + moved * wb, [&] {
+                return launch_scatter(sh.kb, sh.rids, write_keys, d_chunks, nc, d_groups, d_hist, d_cbsum,
+                                      d_cstart, bufs, st);
+            }));
+            std::vector<uint32_t> cnt(child);
+            std::vector<uint64_t> mn(child), mx(child), cs(child);
+            TJ_CK(hipMemcpyAsync(cnt.data(), d_ccount, child * 4ull, hipMemcpyDeviceToHost, st));
+            TJ_CK(hipMemcpyAsync(cs.data(), d_cstart, child * 8ull, hipMemcpyDeviceToHost, st));
+            TJ_CK(hipMemcpyAsync(mn.data(), d_gmin, child * 8ull, hipMemcpyDeviceToHost, st));
+            TJ_CK(hipMemcpyAsync(mx.data(), d_gmax, child * 8ull, hipMemcpyDeviceToHost, st));
+            TJ_CK(hipStreamSynchronize(st));
+            // children in key order: segment order, then digit order
+            for (uint32_t gi = 0; gi < ng; gi += (uint32_t)nside) {
+                const GroupDesc& g0 = groups[gi];
+                const uint32_t nbins = 1u << g0.bits;
+                for (uint32_t d = 0; d < nbins; d++) {
+                    Seg c{};
+                    c.buf = dst;
+                    c.r0 = cs[g0.child0 + d];
+                    c.rn = cnt[g0.child0 + d];
+                    c.lo = mn[g0.child0 + d];
+                    c.hi = mx[g0.child0 + d];
+                    if (nside == 2) {
+                        const GroupDesc& g1 = groups[gi + 1];
+                        c.s0 = cs[g1.child0 + d];
+                        c.sn = cnt[g1.child0 + d];
+                        c.lo = std::min(c.lo, mn[g1.child0 + d]);
+                        c.hi = std::max(c.hi, mx[g1.child0 + d]);
+                    }
+                    stats.bytes_written += (c.rn + c.sn) * row_bytes(sh.kb, sh.rids);
+                    out.push_back(c);
+                }
+            }
+            (void)first;
+        }
+        return TJ_OK;
+    }
+
+    // ---- classification and leaf batching of one level's buckets ---------
+    // Buckets that need another pass go to `next`; the rest become leaves,
+    // crosses (join) or copies (sort). `out_delta` maps buffer rows to output
+    // rows of the sort.
+    void classify(const std::vector<Seg>& level, std::vector<Seg>& next, uint64_t out_delta)
+    {
+        bool open = false;
+        LeafDesc cur{};
+        uint64_t cur_lo = 0, cur_hi = 0;
+        bool cur_useful = false;
+        auto flush = [&]() {
+            if (open && cur_useful) {
+                cur.base = cur_lo;
+                cur.bits = nbits64(cur_hi - cur_lo);
+                cur.out = sh.join ? 0 : cur.r0 + out_delta;
+                leaves.push_back(cur);
+                leaf_lo.push_back(cur_lo);
+            }
+            open = false;
+            cur_useful = false;
+        };
+        for (const Seg& s : level) {
+            const uint64_t rows = s.rn + s.sn;
+            if (rows == 0) continue;  // occupies no rows: does not break adjacency
+            const bool single = s.lo == s.hi;
+            const bool both = s.rn > 0 && s.sn > 0;
+            const bool useful = sh.join ? both : true;
+            if (rows <= (uint64_t)LEAF_CAP) {
+                const bool adjacent = open && cur.buf == s.buf && cur.r0 + cur.rn == s.r0 &&
+                                      (!sh.join || cur.s0 + cur.sn == s.s0) &&
+                                      cur.rn + cur.sn + rows <= (uint64_t)LEAF_CAP;
+                if (!adjacent) {
+                    flush();
+                    open = true;
+                    cur = LeafDesc{};
+                    cur.r0 = s.r0;
+                    cur.s0 = s.s0;
+                    cur.buf = s.buf;
+                    cur_lo = s.lo;
+                    cur_hi = s.hi;
+                }
+                cur.rn += (uint32_t)s.rn;
+                cur.sn += (uint32_t)s.sn;
+                cur_lo = std::min(cur_lo, s.lo);
+                cur_hi = std::max(cur_hi, s.hi);
+                cur_useful = cur_useful || useful;
+                continue;
+            }
+            flush();
+            if (sh.join && !both) continue;  // no partner rows: no output
+            if (single) {
+                stats.single_key++;
+                if (sh.join) {
+                    CrossDesc c{};
+                    c.r0 = s.r0;
+                    c.s0 = s.s0;
+                    c.a = s.rn;
+                    c.b = s.sn;
+                    c.buf = s.buf;
+                    crosses.push_back(c);
+                    cross_lo.push_back(s.lo);
+                } else if (!(out_is_a && s.buf == BUF_A && out_delta == 0)) {
+                    CopyDesc c{};
+                    c.start = s.r0;
+                    c.len = s.rn;
+                    c.out = s.r0 + out_delta;
+                    c.buf = s.buf;
+                    copies.push_back(c);
+                }
+                continue;
+            }
+            next.push_back(s);
+        }
+        flush();
+    }
+
+    // ---- process one key range (the whole domain when the budget does not bind)
+    int process_range(uint64_t lo, uint64_t hi, uint64_t rn, uint64_t sn, bool filtered,
+                      uint64_t out_delta)
+    {
+        Seg root{};
+        root.r0 = 0;
+        root.rn = rn;
+        root.s0 = 0;
+        root.sn = sn;
+        root.lo = lo;
+        root.hi = hi;
+        root.buf = BUF_IN;
+        std::vector<Seg> level, next;
+        if (filtered) {
+            // first pass: compaction + split of the range's rows out of the input
+            const uint64_t f[2] = {lo, hi};
+            std::vector<Seg> roots{root};
+            TJ_RET(run_pass(roots, BUF_IN, BUF_A, f, level));
+        } else {
+            level.push_back(root);
+        }
+        uint32_t cur = filtered ? (uint32_t)BUF_A : (uint32_t)BUF_IN;
+        for (int depth = 0; depth < 80; depth++) {
+            next.clear();
+            classify(level, next, out_delta);
+            if (next.empty()) return TJ_OK;
+            const uint32_t dst = cur == BUF_A ? (uint32_t)BUF_B : (uint32_t)BUF_A;
+            level.clear();
+            TJ_RET(run_pass(next, cur, dst, nullptr, level));
+            cur = dst;
+        }
+        return TJ_E_INTERNAL;
+    }
+
+    // ---- leaves and singles ---------------------------------------------
+    int run_sort_leaves(void* out_k, int32_t* out_r)
+    {
+        for (int wide = 0; wide < 2; wide++) {
+            std::vector<LeafDesc> sel;
+            for (const LeafDesc& L : leaves)
+                if ((L.bits > 32) == (wide == 1)) sel.push_back(L);
+            for (size_t i = 0; i < sel.size(); i += caps.leaves) {
+                const uint32_t n = (uint32_t)std::min<size_t>(caps.leaves, sel.size() - i);
+                TJ_CK(hipMemcpyAsync(d_leaves, sel.data() + i, n * sizeof(LeafDesc), hipMemcpyHostToDevice, st));
+                uint64_t rows = 0;
+                for (uint32_t k = 0; k < n; k++) rows += sel[i + k].rn;
+                TJ_CK(timed(F_LEAF_SORT, rows * row_bytes(sh.kb, true) * 2, [&] {
+                    return launch_leaf_sort(sh.kb, wide == 1, d_leaves, n, bufs, out_k, out_r, st);
+                }));
+                TJ_CK(hipStreamSynchronize(st));
+            }
+        }
+        stats.leaves += (uint32_t)leaves.size();
+        for (const LeafDesc& L : leaves) {
+            stats.bytes_read += L.rn * row_bytes(sh.kb, true);
+            stats.bytes_written += L.rn * row_bytes(sh.kb, true);
+        }
+        // copies
+        for (size_t i = 0; i < copies.size(); i += caps.units) {
+            const uint32_t n = (uint32_t)std::min<size_t>(caps.units, copies.size() - i);
+            uint64_t t = 0;
+            for (uint32_t k = 0; k < n; k++) {
+                copies[i + k].pfx = t;
+                t += copies[i + k].len;
+            }
+            stats.bytes_read += t * row_bytes(sh.kb, true);
+            stats.bytes_written += t * row_bytes(sh.kb, true);
+            TJ_CK(hipMemcpyAsync(d_units, copies.data() + i, n * sizeof(CopyDesc), hipMemcpyHostToDevice, st));
+            TJ_CK(timed(F_COPY, t * row_bytes(sh.kb, true) * 2, [&] {
+                return launch_copy(sh.kb, (const CopyDesc*)d_units, n, t, bufs, out_k, out_r, st);
+            }));
+            TJ_CK(hipStreamSynchronize(st));
+        }
+        leaves.clear();
+        leaf_lo.clear();
+        copies.clear();
+        return TJ_OK;
+    }
+
+    // Counts of every leaf (device pass) into host `counts`.
+    int count_leaves(std::vector<uint64_t>& counts)
+    {
+        counts.assign(leaves.size(), 0);
+        for (int wide = 0; wide < 2; wide++) {
+            std::vector<LeafDesc> sel;
+            std::vector<size_t> where;
+            for (size_t i = 0; i < leaves.size(); i++)
+                if ((leaves[i].bits > 32) == (wide == 1)) {
+                    sel.push_back(leaves[i]);
+                    where.push_back(i);
+                }
+            std::vector<uint64_t> c(std::min<size_t>(caps.leaves, sel.size()));
+            for (size_t i = 0; i < sel.size(); i += caps.leaves) {
+                const uint32_t n = (uint32_t)std::min<size_t>(caps.leaves, sel.size() - i);
+                TJ_CK(hipMemcpyAsync(d_leaves, sel.data() + i, n * sizeof(LeafDesc), hipMemcpyHostToDevice, st));
+                uint64_t rows = 0;
+                for (uint32_t k = 0; k < n; k++) rows += sel[i + k].rn + sel[i + k].sn;
+                TJ_CK(timed(F_LEAF_COUNT, rows * sh.kb, [&] {
+                    return launch_leaf_join(sh.kb, wide == 1, false, d_leaves, n, bufs, d_counts, nullptr,
+                                            nullptr, st);
+                }));
+                TJ_CK(hipMemcpyAsync(c.data(), d_counts, n * 8ull, hipMemcpyDeviceToHost, st));
+                TJ_CK(hipStreamSynchronize(st));
+                for (uint32_t k = 0; k < n; k++) counts[where[i + k]] = c[k];
+            }
+        }
+        for (const LeafDesc& L : leaves) stats.bytes_read += (uint64_t)(L.rn + L.sn) * sh.kb;
+        return TJ_OK;
+    }
+
+    // Counts the range's leaves and crosses, lays their output out in key order
+    // from out_base, and writes the pairs if write && out_base + total <= capacity.
+    int finish_join(uint64_t* total_out, uint64_t out_base, int32_t* out_r, int32_t* out_s,
+                    uint64_t capacity, bool write)
+    {
+        std::vector<uint64_t> counts;
+        TJ_RET(count_leaves(counts));
+        std::vector<Unit> units;
+        units.reserve(leaves.size() + crosses.size());
+        for (size_t i = 0; i < leaves.size(); i++)
+            if (counts[i]) units.push_back(Unit{leaf_lo[i], 0, (uint32_t)i, counts[i]});
+        for (size_t i = 0; i < crosses.size(); i++)
+            units.push_back(Unit{cross_lo[i], 1, (uint32_t)i, crosses[i].a * crosses[i].b});
+        std::sort(units.begin(), units.end(), [](const Unit& a, const Unit& b) { return a.lo < b.lo; });
+        uint64_t total = 0;
+        for (Unit& u : units) {
+            const uint64_t o = out_base + total;
+            if (u.kind == 0) leaves[u.index].out = o;
+            else crosses[u.index].out = o;
+            total += u.count;
+        }
+        *total_out = total;
+        stats.leaves += (uint32_t)leaves.size();
+        const bool fits = out_base + total <= capacity;
+        if (write && fits) {
+            for (int wide = 0; wide < 2; wide++) {
+                std::vector<LeafDesc> sel;
+                std::vector<uint64_t> sel_cnt;
+                for (size_t i = 0; i < leaves.size(); i++)
+                    if (counts[i] && (leaves[i].bits > 32) == (wide == 1)) {
+                        sel.push_back(leaves[i]);
+                        sel_cnt.push_back(counts[i]);
+                    }
+                for (size_t i = 0; i < sel.size(); i += caps.leaves) {
+                    const uint32_t n = (uint32_t)std::min<size_t>(caps.leaves, sel.size() - i);
+                    TJ_CK(hipMemcpyAsync(d_leaves, sel.data() + i, n * sizeof(LeafDesc), hipMemcpyHostToDevice, st));
+                    uint64_t rows = 0, pairs = 0;
+                    for (uint32_t k = 0; k < n; k++) {
+                        rows += sel[i + k].rn + sel[i + k].sn;
+                        pairs += sel_cnt[i + k];
+                    }
+                    TJ_CK(timed(F_LEAF_MAT, rows * row_bytes(sh.kb, true) + pairs * 8, [&] {
+                        return launch_leaf_join(sh.kb, wide == 1, true, d_leaves, n, bufs, d_counts, out_r,
+                                                out_s, st);
+                    }));
+                    TJ_CK(hipStreamSynchronize(st));
+                }
+                for (const LeafDesc& L : sel) stats.bytes_read += (uint64_t)(L.rn + L.sn) * row_bytes(sh.kb, true);
+            }
+            for (size_t i = 0; i < crosses.size(); i += caps.units) {
+                const uint32_t n = (uint32_t)std::min<size_t>(caps.units, crosses.size() - i);
+                uint64_t t = 0;
+                for (uint32_t k = 0; k < n; k++) {
+                    crosses[i + k].pfx = t;
+                    t += crosses[i + k].a * crosses[i + k].b;
+                    stats.bytes_read += (crosses[i + k].a + crosses[i + k].b) * 4;
+                }
+                TJ_CK(hipMemcpyAsync(d_units, crosses.data() + i, n * sizeof(CrossDesc), hipMemcpyHostToDevice, st));
+                uint64_t in_rows = 0;
+                for (uint32_t k = 0; k < n; k++) in_rows += crosses[i + k].a + crosses[i + k].b;
+                TJ_CK(timed(F_CROSS, t * 8 + in_rows * 4, [&] {
+                    return launch_cross((const CrossDesc*)d_units, n, t, bufs, out_r, out_s, st);
+                }));
+                TJ_CK(hipStreamSynchronize(st));
+            }
+            stats.bytes_written += total * 8;
+        }
+        leaves.clear();
+        leaf_lo.clear();
+        crosses.clear();
+        cross_lo.clear();
+        return TJ_OK;
+    }
+
+    // A key range holding one key value with a rows of R and b rows of S, too
+    // large for the workspace: its pairs are built in the output columns. The
+    // S row ids are compacted (input order) to out_s[base, base+b), the R row
+    // ids to scratch space inside the pair range, then expanded R-major.
+    int single_key_pairs(uint64_t k, uint64_t a, uint64_t b, uint64_t base, int32_t* out_r,
+                         int32_t* out_s)
+    {
+        BufSet saved = bufs;
+        const bool saved_wk = write_keys;
+        write_keys = false;
+        auto compact = [&](int side, int32_t* dst) -> int {
+            bufs.rid[BUF_A][side] = dst;
+            Seg root{};
+            root.lo = root.hi = k;
+            root.buf = BUF_IN;
+            if (side == 0) root.rn = a; else root.sn = b;
+            std::vector<Seg> roots{root}, kids;
+            const uint64_t f[2] = {k, k};
+            // only the requested side is scanned: zero the other's input length
+            const uint64_t keep_r = sh.n_r, keep_s = sh.n_s;
+            const bool keep_join = sh.join;
+            if (side == 0) { sh.join = false; }
+            else {
+                // run the S column as the single side of a one-relation pass
+                sh.join = false;
+                bufs.key[BUF_IN][0] = saved.key[BUF_IN][1];
+                bufs.rid[BUF_IN][0] = saved.rid[BUF_IN][1];
+                bufs.rid[BUF_A][0] = dst;
+                sh.n_r = keep_s;
+            }
+            int rc = run_pass(roots, BUF_IN, BUF_A, f, kids);
+            sh.n_r = keep_r;
+            sh.n_s = keep_s;
+            sh.join = keep_join;
+            bufs = saved;
+            return rc;
+        };
+        int rc = TJ_OK;
+        if (b == 1) {
+            rc = compact(0, out_r + base);
+            if (rc == TJ_OK) rc = compact(1, out_s + base);
+            if (rc == TJ_OK && a > 1) rc = launch_expand(out_s + base, nullptr, a, 1, 1, st) == hipSuccess ? TJ_OK : TJ_E_HIP;
+        } else if (a == 1) {
+            rc = compact(1, out_s + base);
+            if (rc == TJ_OK) rc = compact(0, out_r + base);
+            if (rc == TJ_OK) rc = launch_expand(out_r + base, out_r + base, b, b, 0, st) == hipSuccess ? TJ_OK : TJ_E_HIP;
+        } else {
+            rc = compact(1, out_s + base);
+            if (rc == TJ_OK) rc = compact(0, out_s + base + b);  // (a-1)(b-1) >= 1: fits in [b, a*b)
+            if (rc == TJ_OK)
+                rc = launch_expand(out_r + base, out_s + base + b, a * b, b, 0, st) == hipSuccess ? TJ_OK : TJ_E_HIP;
+            if (rc == TJ_OK) rc = launch_expand(out_s + base, nullptr, a * b, b, 1, st) == hipSuccess ? TJ_OK : TJ_E_HIP;
+        }
+        write_keys = saved_wk;
+        bufs = saved;
+        stats.single_key++;
+        stats.bytes_written += a * b * 8;
+        return rc;
+    }
+
+    // ---- key ranges under a binding budget ---------------------------------
+    // Coarse histogram of the top bits of (ord - lo) over both inputs, cut into
+    // ranges whose rows fit the buffers; a bin too large is refined by a
+    // histogram of its own sub-range. Computed with the partition kernels: one
+    // filtered histogram pass with a wide digit.
+    int coarse_hist(uint64_t lo, uint64_t hi, uint32_t& shift, uint32_t& bits,
+                    std::vector<uint64_t>& cr, std::vector<uint64_t>& cs)
+    {
+        const uint32_t kbits = nbits64(hi - lo);
+        bits = std::min<uint32_t>(kbits, MAX_DIGIT_BITS);
+        if (bits == 0) bits = 1;
+        shift = kbits > bits ? kbits - bits : 0;
+        const int nside = sh.join ? 2 : 1;
+        std::vector<GroupDesc> groups;
+        std::vector<ChunkDesc> chunks;
+        const uint64_t nmax = std::max(sh.n_r, sh.n_s);
+        uint64_t ch_rows = align_up((nmax + 255) / 256, PART_TILE);
+        if (ch_rows < PART_TILE) ch_rows = PART_TILE;
+        while ((nmax + ch_rows - 1) / ch_rows * nside > caps.chunks) ch_rows *= 2;
+        uint32_t child = 0;
+        for (int side = 0; side < nside; side++) {
+            GroupDesc g{};
+            g.len = side ? sh.n_s : sh.n_r;
+            g.base = lo;
+            g.flo = lo;
+            g.fhi = hi;
+            g.shift = shift;
+            g.bits = bits;
+            g.side = (uint32_t)side;
+            g.src = BUF_IN;
+            g.chunk0 = (uint32_t)chunks.size();
+            g.child0 = child;
+            child += 1u << bits;
+            for (uint64_t c0 = 0; c0 < g.len; c0 += ch_rows) {
+                ChunkDesc c{};
+                c.start = c0;
+                c.len = (uint32_t)std::min<uint64_t>(ch_rows, g.len - c0);
+                c.group = (uint32_t)side;
+                chunks.push_back(c);
+            }
+            g.nchunks = (uint32_t)chunks.size() - g.chunk0;
+            groups.push_back(g);
+            stats.bytes_read += g.len * (uint64_t)sh.kb;
+        }
+        const uint32_t nc = (uint32_t)chunks.size();
+        TJ_CK(hipMemcpyAsync(d_groups, groups.data(), groups.size() * sizeof(GroupDesc), hipMemcpyHostToDevice, st));
+        TJ_CK(hipMemcpyAsync(d_chunks, chunks.data(), nc * sizeof(ChunkDesc), hipMemcpyHostToDevice, st));
+        TJ_CK(launch_fill_u64(d_gmin, child, ~0ull, st));
+        TJ_CK(launch_fill_u64(d_gmax, child, 0ull, st));
+        TJ_CK(launch_hist(sh.kb, d_chunks, nc, d_groups, bufs, d_hist, d_gmin, d_gmax, st));
+        std::vector<uint32_t> h((size_t)nc * NB);
+        TJ_CK(hipMemcpyAsync(h.data(), d_hist, h.size() * 4, hipMemcpyDeviceToHost, st));
+        TJ_CK(hipStreamSynchronize(st));
+        const uint32_t nbins = 1u << bits;
+        cr.assign(nbins, 0);
+        cs.assign(nbins, 0);
+        for (uint32_t c = 0; c < nc; c++) {
+            std::vector<uint64_t>& dstv = chunks[c].group ? cs : cr;
+            for (uint32_t d = 0; d < nbins; d++) dstv[d] += h[(size_t)c * NB + d];
+        }
+        return TJ_OK;
+    }
+
+    struct Range {
+        uint64_t lo, hi, rn, sn;
+    };
+
+    // Splits [lo, hi] into ranges with rn <= cap_r and sn <= cap_s, or single keys.
+    int plan_ranges(uint64_t lo, uint64_t hi, std::vector<Range>& out, int depth)
+    {
+        if (depth > 16) return TJ_E_INTERNAL;
+        uint32_t shift, bits;
+        std::vector<uint64_t> cr, cs;
+        TJ_RET(coarse_hist(lo, hi, shift, bits, cr, cs));
+        const uint32_t nbins = 1u << bits;
+        auto bin_lo = [&](uint32_t d) { return lo + ((uint64_t)d << shift); };
+        auto bin_hi = [&](uint32_t d) {
+            const uint64_t e = lo + (((uint64_t)d + 1) << shift) - 1;
+            return std::min(e, hi);
+        };
+        bool open = false;
+        Range cur{};
+        for (uint32_t d = 0; d < nbins; d++) {
+            if (bin_lo(d) > hi) break;
+            const uint64_t r = cr[d], s = cs[d];
+            if (r == 0 && s == 0) continue;
+            if (r > cap_r || s > cap_s) {
+                if (open) out.push_back(cur);
+                open = false;
+                if (shift == 0 || bin_lo(d) == bin_hi(d)) {
+                    out.push_back(Range{bin_lo(d), bin_lo(d), r, s});  // a single key value
+                } else {
+                    TJ_RET(plan_ranges(bin_lo(d), bin_hi(d), out, depth + 1));
+                }
+                continue;
+            }
+            if (open && cur.rn + r <= cap_r && cur.sn + s <= cap_s) {
+                cur.hi = bin_hi(d);
+                cur.rn += r;
+                cur.sn += s;
+            } else {
+                if (open) out.push_back(cur);
+                cur = Range{bin_lo(d), bin_hi(d), r, s};
+                open = true;
+            }
+        }
+        if (open) out.push_back(cur);
+        return TJ_OK;
+    }
+};
+
+bool timing_enabled()
+{
+    Timing& t = timing();
+    std::lock_guard<std::mutex> g(t.mu);
+    return t.on;
+}
+
+int validate_common(int key_type)
+{
+    if (key_type != TJ_KEY_I32 && key_type != TJ_KEY_I64) return TJ_E_ARG;
+    return TJ_OK;
+}
+
+bool overlap(const void* a, uint64_t abytes, const void* b, uint64_t bbytes)
+{
+    if (!a || !b || abytes == 0 || bbytes == 0) return false;
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + bbytes && y < x + abytes;
+}
+
+// Chooses the table tier and the data layout for a given workspace budget.
+// Returns TJ_E_WORKSPACE below the minimum.
+int plan_workspace(const Shape& s, uint64_t ws_bytes, int& tier, bool& unlimited, uint64_t& data_bytes)
+{
+    const uint64_t full_data = full_data_bytes(s);
+    const uint64_t min_data = min_data_bytes(s);
+    tier = -1;
+    // full plan: data buffers for every row plus the largest table tier that fits
+    for (int t = TABLE_TIERS - 1; t >= 0; t--)
+        if (full_data + table_bytes(tier_caps(t)) <= ws_bytes) {
+            tier = t;
+            break;
+        }
+    if (tier >= 0 && (tier == TABLE_TIERS - 1 || full_data + table_bytes(tier_caps(TABLE_TIERS - 1)) > ws_bytes)) {
+        unlimited = true;
+        data_bytes = full_data;
+        return TJ_OK;
+    }
+    // budget binds: tables take at most a quarter, the rest holds a key range's rows
+    unlimited = false;
+    for (int t = TABLE_TIERS - 1; t >= 0; t--)
+        if (table_bytes(tier_caps(t)) * 4 <= ws_bytes || t == 0) {
+            tier = t;
+            break;
+        }
+    const uint64_t tb = table_bytes(tier_caps(tier));
+    if (ws_bytes < tb + min_data) return TJ_E_WORKSPACE;
+    data_bytes = ws_bytes - tb;
+    return TJ_OK;
+}
+
+uint64_t min_workspace(const Shape& s) { return table_bytes(tier_caps(0)) + min_data_bytes(s); }
+
+uint64_t full_workspace(const Shape& s) { return table_bytes(tier_caps(TABLE_TIERS - 1)) + full_data_bytes(s); }
+
+// Lays out the ping-pong buffers inside the data region.
+void layout_data(Exec& x, char* p, uint64_t data_bytes, bool unlimited)
+{
+    const Shape& s = x.sh;
+    const int nside = s.join ? 2 : 1;
+    uint64_t cap[2] = {s.n_r, s.n_s};
+    if (!unlimited) {
+        // split the region between the sides in proportion to their rows
+        const uint64_t rb = row_bytes(s.kb, s.rids);
+        const int nbuf = s.join ? 2 : 1;  // sort: only buffer B lives in the workspace
+        const uint64_t slack = (uint64_t)ALIGN * 4 * nbuf * nside;
+        const uint64_t avail = data_bytes > slack ? data_bytes - slack : 0;
+        const uint64_t tot = s.n_r + (s.join ? s.n_s : 0);
+        for (int side = 0; side < nside; side++) {
+            const uint64_t n = side ? s.n_s : s.n_r;
+            const long double frac = tot ? (long double)n / (long double)tot : 1.0L;
+            cap[side] = (uint64_t)((long double)avail * frac / (long double)(rb * nbuf));
+            if (cap[side] > n) cap[side] = n;
+        }
+    }
+    x.cap_r = cap[0];
+    x.cap_s = s.join ? cap[1] : 0;
+    for (int buf = (s.join ? BUF_A : BUF_B); buf <= BUF_B; buf++)
+        for (int side = 0; side < nside; side++) {
+            x.bufs.key[buf][side] = p;
+            p += align_up(cap[side] * (uint64_t)s.kb, ALIGN);
+            if (s.rids) {
+                x.bufs.rid[buf][side] = (const int32_t*)p;
+                p += align_up(cap[side] * 4, ALIGN);
+            }
+        }
+}
+
+int probe(Exec& x, const void* a, uint64_t na, const void* b, uint64_t nb, uint64_t& lo, uint64_t& hi)
+{
+    uint64_t mm[2];
+    TJ_CK(x.timed(F_PROBE, (na + nb) * (uint64_t)x.sh.kb,
+                  [&] { return launch_probe(x.sh.kb, a, na, b, nb, x.d_probe, x.st); }));
+    TJ_CK(hipMemcpyAsync(mm, x.d_probe, 16, hipMemcpyDeviceToHost, x.st));
+    TJ_CK(hipStreamSynchronize(x.st));
+    x.stats.bytes_read += (na + nb) * (uint64_t)x.sh.kb;
+    lo = mm[0];
+    hi = mm[1];
+    return TJ_OK;
+}
+
+}  // namespace
+}  // namespace tj
+
+using namespace tj;
+
+extern "C" {
+
+const char* tj_strerror(int status)
+{
+    switch (status) {
+    case TJ_OK: return "ok";
+    case TJ_E_ARG: return "invalid argument";
+    case TJ_E_WORKSPACE: return "workspace too small or misaligned";
+    case TJ_E_CAPACITY: return "join result exceeds output capacity";
+    case TJ_E_TOO_LARGE: return "row count must be below 2^31";
+    case TJ_E_ALIAS: return "output overlaps an input or the workspace";
+    case TJ_E_HIP: return "HIP runtime error";
+    case TJ_E_INTERNAL: return "internal planner error";
+    default: return "unknown status";
+    }
+}
+
+int tj_version(void) { return 100; }
+
+int tj_timing(int enable)
+{
+    Timing& t = timing();
+    std::lock_guard<std::mutex> g(t.mu);
+    if (enable && !t.on) {
+        for (int f = 0; f < NFAM; f++) {
+            t.launches[f] = 0;
+            t.bytes[f] = 0;
+            t.ms[f] = 0;
+        }
+    }
+    t.on = enable != 0;
+    return TJ_OK;
+}
+
+int tj_timing_read(tj_kernel_stat_t* out, int max)
+{
+    if (!out || max < 0) return TJ_E_ARG;
+    Timing& t = timing();
+    std::lock_guard<std::mutex> g(t.mu);
+    int n = 0;
+    for (int f = 0; f < NFAM && n < max; f++, n++) {
+        std::memset(&out[n], 0, sizeof(out[n]));
+        std::strncpy(out[n].name, kFamName[f], sizeof(out[n].name) - 1);
+        out[n].launches = t.launches[f];
+        out[n].bytes = t.bytes[f];
+        out[n].ms = t.ms[f];
+    }
+    return n;
+}
+
+int tj_workspace_query(int op, int key_type, uint64_t n_r, uint64_t n_s, uint64_t* min_bytes,
+                       uint64_t* full_bytes)
+{
+    if (validate_common(key_type) != TJ_OK) return TJ_E_ARG;
+    if (op != TJ_OP_SORT && op != TJ_OP_JOIN_COUNT && op != TJ_OP_JOIN_MATERIALIZE) return TJ_E_ARG;
+    if (!min_bytes || !full_bytes) return TJ_E_ARG;
+    if (n_r > kMaxRows || (op != TJ_OP_SORT && n_s > kMaxRows)) return TJ_E_TOO_LARGE;
+    Shape s{op, key_type, op != TJ_OP_SORT, op == TJ_OP_JOIN_MATERIALIZE, op != TJ_OP_JOIN_COUNT,
+            n_r, op == TJ_OP_SORT ? 0 : n_s};
+    *min_bytes = min_workspace(s);
+    *full_bytes = full_workspace(s);
+    return TJ_OK;
+}
+
+int tj_sort(int key_type, const void* keys_in, const int32_t* rids_in, uint64_t n, void* keys_out,
+            int32_t* rids_out, void* workspace, uint64_t workspace_bytes, void* stream,
+            tj_stats_t* stats)
+{
+    if (validate_common(key_type) != TJ_OK) return TJ_E_ARG;
+    if (n > kMaxRows) return TJ_E_TOO_LARGE;
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    if (n == 0) return TJ_OK;
+    if (!keys_in || !rids_in || !keys_out || !rids_out || !workspace) return TJ_E_ARG;
+    if ((uintptr_t)workspace % ALIGN) return TJ_E_WORKSPACE;
+    const uint64_t kbytes = n * (uint64_t)key_type, rbytes = n * 4;
+    const void* outs[2] = {keys_out, rids_out};
+    const uint64_t osz[2] = {kbytes, rbytes};
+    for (int i = 0; i < 2; i++)
+        if (overlap(outs[i], osz[i], keys_in, kbytes) || overlap(outs[i], osz[i], rids_in, rbytes) ||
+            overlap(outs[i], osz[i], workspace, workspace_bytes))
+            return TJ_E_ALIAS;
+    if (overlap(keys_out, kbytes, rids_out, rbytes)) return TJ_E_ALIAS;
+
+    Exec x;
+    x.timed_on = timing_enabled();
+    x.sh = Shape{TJ_OP_SORT, key_type, false, false, true, n, 0};
+    x.st = (hipStream_t)stream;
+    int tier;
+    bool unlimited;
+    uint64_t data_bytes;
+    TJ_RET(plan_workspace(x.sh, workspace_bytes, tier, unlimited, data_bytes));
+    x.caps = tier_caps(tier);
+    char* p = (char*)workspace;
+    char* end = p + workspace_bytes;
+    TJ_RET(x.carve_tables(p, end));
+    layout_data(x, p, data_bytes, unlimited);
+    x.bufs.key[BUF_IN][0] = keys_in;
+    x.bufs.rid[BUF_IN][0] = rids_in;
+    x.bufs.key[BUF_A][0] = keys_out;
+    x.bufs.rid[BUF_A][0] = rids_out;
+    x.out_is_a = unlimited;
+
+    uint64_t lo, hi;
+    TJ_RET(probe(x, keys_in, n, nullptr, 0, lo, hi));
+    if (unlimited) {
+        x.stats.key_ranges = 1;
+        TJ_RET(x.process_range(lo, hi, n, 0, false, 0));
+        TJ_RET(x.run_sort_leaves(keys_out, rids_out));
+    } else {
+        // ranges: buffer A and B both live in the workspace; outputs are written
+        // by the leaves and copies at the range's output offset
+        // buffers A and B both inside the workspace: the B region split in two
+        const uint64_t half = x.cap_r / 2;
+        if (half == 0) return TJ_E_WORKSPACE;
+        x.cap_r = half;
+        std::vector<Exec::Range> ranges;
+        TJ_RET(x.plan_ranges(lo, hi, ranges, 0));
+        char* pb = (char*)x.bufs.key[BUF_B][0];
+        char* pbr = (char*)x.bufs.rid[BUF_B][0];
+        x.bufs.key[BUF_A][0] = pb;
+        x.bufs.rid[BUF_A][0] = (const int32_t*)pbr;
+        x.bufs.key[BUF_B][0] = pb + align_up(half * (uint64_t)key_type, ALIGN);
+        x.bufs.rid[BUF_B][0] = (const int32_t*)(pbr + align_up(half * 4, ALIGN));
+        x.out_is_a = false;
+        uint64_t out_row = 0;
+        x.stats.key_ranges = (uint32_t)ranges.size();
+        for (const auto& r : ranges) {
+            if (r.rn > half && r.lo != r.hi) return TJ_E_INTERNAL;
+            if (r.lo == r.hi) {
+                // one key value: the rows keep input order; compact them straight to the output
+                BufSet saved = x.bufs;
+                x.bufs.key[BUF_A][0] = (char*)keys_out + out_row * (uint64_t)key_type;
+                x.bufs.rid[BUF_A][0] = rids_out + out_row;
+                const Exec::Range rr = r;
+                std::vector<Seg> roots{Seg{0, rr.rn, 0, 0, rr.lo, rr.hi, BUF_IN}};
+                std::vector<Seg> kids;
+                const uint64_t f[2] = {rr.lo, rr.hi};
+                TJ_RET(x.run_pass(roots, BUF_IN, BUF_A, f, kids));
+                x.bufs = saved;
+                x.stats.single_key++;
+            } else {
+                TJ_RET(x.process_range(r.lo, r.hi, r.rn, 0, true, out_row));
+                TJ_RET(x.run_sort_leaves(keys_out, rids_out));
+            }
+            out_row += r.rn;
+        }
+        if (out_row != n) return TJ_E_INTERNAL;
+    }
+    TJ_CK(hipStreamSynchronize(x.st));
+    x.stats.workspace_used = workspace_bytes;
+    if (stats) *stats = x.stats;
+    return TJ_OK;
+}
+
+static int join_impl(int key_type, const void* r_keys, const int32_t* r_rids, uint64_t n_r,
+                     const void* s_keys, const int32_t* s_rids, uint64_t n_s, int32_t* out_r,
+                     int32_t* out_s, uint64_t capacity, uint64_t* count, void* workspace,
+                     uint64_t workspace_bytes, void* stream, tj_stats_t* stats, bool mat)
+{
+    if (validate_common(key_type) != TJ_OK) return TJ_E_ARG;
+    if (!count) return TJ_E_ARG;
+    if (n_r > kMaxRows || n_s > kMaxRows) return TJ_E_TOO_LARGE;
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    *count = 0;
+    if (n_r == 0 || n_s == 0) return TJ_OK;
+    if (!r_keys || !s_keys || !workspace) return TJ_E_ARG;
+    if (mat && (!r_rids || !s_rids || (capacity > 0 && (!out_r || !out_s)))) return TJ_E_ARG;
+    if ((uintptr_t)workspace % ALIGN) return TJ_E_WORKSPACE;
+    const uint64_t kb = (uint64_t)key_type;
+    if (mat && capacity > 0) {
+        const void* ins[4] = {r_keys, s_keys, r_rids, s_rids};
+        const uint64_t isz[4] = {n_r * kb, n_s * kb, n_r * 4, n_s * 4};
+        const void* outs[2] = {out_r, out_s};
+        for (int o = 0; o < 2; o++) {
+            for (int i = 0; i < 4; i++)
+                if (overlap(outs[o], capacity * 4, ins[i], isz[i])) return TJ_E_ALIAS;
+            if (overlap(outs[o], capacity * 4, workspace, workspace_bytes)) return TJ_E_ALIAS;
+        }
+        if (overlap(out_r, capacity * 4, out_s, capacity * 4)) return TJ_E_ALIAS;
+    }
+
+    Exec x;
+    x.timed_on = timing_enabled();
+    x.sh = Shape{mat ? TJ_OP_JOIN_MATERIALIZE : TJ_OP_JOIN_COUNT, key_type, true, mat, mat, n_r, n_s};
+    x.st = (hipStream_t)stream;
+    int tier;
+    bool unlimited;
+    uint64_t data_bytes;
+    TJ_RET(plan_workspace(x.sh, workspace_bytes, tier, unlimited, data_bytes));
+    x.caps = tier_caps(tier);
+    char* p = (char*)workspace;
+    char* end = p + workspace_bytes;
+    TJ_RET(x.carve_tables(p, end));
+    layout_data(x, p, data_bytes, unlimited);
+    x.bufs.key[BUF_IN][0] = r_keys;
+    x.bufs.key[BUF_IN][1] = s_keys;
+    x.bufs.rid[BUF_IN][0] = r_rids;
+    x.bufs.rid[BUF_IN][1] = s_rids;
+
+    uint64_t lo, hi;
+    TJ_RET(probe(x, r_keys, n_r, s_keys, n_s, lo, hi));
+    uint64_t total = 0;
+    if (unlimited) {
+        x.stats.key_ranges = 1;
+        TJ_RET(x.process_range(lo, hi, n_r, n_s, false, 0));
+        TJ_RET(x.finish_join(&total, 0, out_r, out_s, capacity, mat));
+    } else {
+        // Ranges in key order; each range is counted, then written at the
+        // running offset while the running total still fits the capacity.
+        std::vector<Exec::Range> ranges;
+        TJ_RET(x.plan_ranges(lo, hi, ranges, 0));
+        x.stats.key_ranges = (uint32_t)ranges.size();
+        for (const auto& r : ranges) {
+            if (r.rn == 0 || r.sn == 0) continue;
+            if (r.lo == r.hi) {
+                if (mat && total + r.rn * r.sn <= capacity)
+                    TJ_RET(x.single_key_pairs(r.lo, r.rn, r.sn, total, out_r, out_s));
+                total += r.rn * r.sn;
+                continue;
+            }
+            if (r.rn > x.cap_r || r.sn > x.cap_s) return TJ_E_INTERNAL;
+            uint64_t t = 0;
+            TJ_RET(x.process_range(r.lo, r.hi, r.rn, r.sn, true, 0));
+            TJ_RET(x.finish_join(&t, total, out_r, out_s, capacity, mat));
+            total += t;
+        }
+    }
+    *count = total;
+    TJ_CK(hipStreamSynchronize(x.st));
+    x.stats.workspace_used = workspace_bytes;
+    if (stats) *stats = x.stats;
+    if (mat && total > capacity) return TJ_E_CAPACITY;
+    return TJ_OK;
+}
+
+int tj_join_count(int key_type, const void* r_keys, uint64_t n_r, const void* s_keys, uint64_t n_s,
+                  uint64_t* count, void* workspace, uint64_t workspace_bytes, void* stream,
+                  tj_stats_t* stats)
+{
+    return join_impl(key_type, r_keys, nullptr, n_r, s_keys, nullptr, n_s, nullptr, nullptr, 0, count,
+                     workspace, workspace_bytes, stream, stats, false);
+}
+
+int tj_join_materialize(int key_type, const void* r_keys, const int32_t* r_rids, uint64_t n_r,
+                        const void* s_keys, const int32_t* s_rids, uint64_t n_s, int32_t* out_r,
+                        int32_t* out_s, uint64_t capacity, uint64_t* count, void* workspace,
+                        uint64_t workspace_bytes, void* stream, tj_stats_t* stats)
+{
+    return join_impl(key_type, r_keys, r_rids, n_r, s_keys, s_rids, n_s, out_r, out_s, capacity, count,
+                     workspace, workspace_bytes, stream, stats, true);
+}
+
+int tj_debug_partition_pass(const int64_t* keys, const int32_t* rids, uint64_t n, uint64_t base,
+                            uint32_t shift, uint32_t bits, int64_t* keys_out, int32_t* rids_out,
+                            uint32_t* counts_out, void* workspace, uint64_t workspace_bytes,
+                            void* stream)
+{
+    if (!keys || !rids || !keys_out || !rids_out || !counts_out || !workspace) return TJ_E_ARG;
+    if (bits < 1 || bits > 8 || shift > 63 || shift + bits > 64) return TJ_E_ARG;
+    if (n == 0 || n > kMaxRows) return n ? TJ_E_TOO_LARGE : TJ_E_ARG;
+    if ((uintptr_t)workspace % ALIGN) return TJ_E_WORKSPACE;
+    Exec x;
+    x.sh = Shape{TJ_OP_SORT, 8, false, false, true, n, 0};
+    x.st = (hipStream_t)stream;
+    x.caps = tier_caps(2);
+    char* p = (char*)workspace;
+    TJ_RET(x.carve_tables(p, (char*)workspace + workspace_bytes));
+    x.bufs.key[BUF_IN][0] = keys;
+    x.bufs.rid[BUF_IN][0] = rids;
+    x.bufs.key[BUF_A][0] = keys_out;
+    x.bufs.rid[BUF_A][0] = rids_out;
+    GroupDesc g{};
+    g.len = n;
+    g.base = base;
+    g.flo = 0;
+    g.fhi = ~0ull;
+    g.shift = shift;
+    g.bits = bits;
+    g.src = BUF_IN;
+    g.dst = BUF_A;
+    std::vector<ChunkDesc> chunks;
+    const uint64_t ch = align_up((n + 63) / 64, PART_TILE);
+    for (uint64_t c0 = 0; c0 < n; c0 += ch)
+        chunks.push_back(ChunkDesc{c0, (uint32_t)std::min<uint64_t>(ch, n - c0), 0,
+                                   (uint32_t)(chunks.size() / CBLOCK), 0});
+    g.nchunks = (uint32_t)chunks.size();
+    std::vector<CBlockDesc> cbs;
+    for (uint32_t c = 0; c < g.nchunks; c += CBLOCK)
+        cbs.push_back(CBlockDesc{0, c, std::min<uint32_t>(CBLOCK, g.nchunks - c), 0});
+    g.ncblocks = (uint32_t)cbs.size();
+    hipStream_t st = x.st;
+    TJ_CK(hipMemcpyAsync(x.d_groups, &g, sizeof(g), hipMemcpyHostToDevice, st));
+    TJ_CK(hipMemcpyAsync(x.d_chunks, chunks.data(), chunks.size() * sizeof(ChunkDesc), hipMemcpyHostToDevice, st));
+    TJ_CK(hipMemcpyAsync(x.d_cblocks, cbs.data(), cbs.size() * sizeof(CBlockDesc), hipMemcpyHostToDevice, st));
+    TJ_CK(launch_fill_u64(x.d_gmin, 1u << bits, ~0ull, st));
+    TJ_CK(launch_fill_u64(x.d_gmax, 1u << bits, 0ull, st));
+    TJ_CK(launch_hist(8, x.d_chunks, g.nchunks, x.d_groups, x.bufs, x.d_hist, x.d_gmin, x.d_gmax, st));
+    TJ_CK(launch_scan(x.d_cblocks, g.ncblocks, x.d_groups, 1, x.d_hist, x.d_cbsum, x.d_ccount, x.d_cstart, st));
+    TJ_CK(launch_scatter(8, true, true, x.d_chunks, g.nchunks, x.d_groups, x.d_hist, x.d_cbsum, x.d_cstart, x.bufs, st));
+    TJ_CK(hipMemcpyAsync(counts_out, x.d_ccount, (1u << bits) * 4ull, hipMemcpyDeviceToDevice, st));
+    TJ_CK(hipStreamSynchronize(st));
+    return TJ_OK;
+}
+
+int tj_debug_wave_scan(const uint32_t* in, uint32_t* out, uint64_t n, void* stream)
+{
+    if (!in || !out || n % 64) return TJ_E_ARG;
+    TJ_CK(launch_wave_scan_test(in, out, n, (hipStream_t)stream));
+    TJ_CK(hipStreamSynchronize((hipStream_t)stream));
+    return TJ_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,126 @@
+// tj_internal.h - descriptors shared by the host planner and the gfx950 kernels.
+//
+// Rows live in three places ("buffers"): 0 = the caller's input columns,
+// 1 = ping buffer A, 2 = pong buffer B. Each buffer has one key column and one
+// rid column per side (side 0 = R or the relation being sorted, side 1 = S).
+// A partition pass reads the rows of a segment from one buffer and writes them,
+// grouped by digit, to the same index range of the other buffer, so a segment's
+// rows always occupy the same index range whichever buffer holds them.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace tj {
+
+constexpr int MAX_DIGIT_BITS = 9;             // widest partition digit
+constexpr int NB = 1 << MAX_DIGIT_BITS;       // digit bins per group (table stride)
+constexpr int PART_THREADS = 256;             // histogram / scatter block
+constexpr int PART_ITEMS = 16;                // rows per thread per scatter tile
+constexpr int PART_TILE = PART_THREADS * PART_ITEMS;
+constexpr int CBLOCK = 32;                    // chunks per first-level scan block
+
+enum Buf : uint32_t { BUF_IN = 0, BUF_A = 1, BUF_B = 2 };
+
+// One contiguous run of a group's rows; one histogram and one scatter block.
+struct ChunkDesc {
+    uint64_t start;   // first row of the chunk in the source array
+    uint32_t len;     // rows
+    uint32_t group;   // owning group
+    uint32_t cblock;  // owning scan block
+    uint32_t pad;
+};
+
+// A run of consecutive chunks of one group, reduced by one first-level scan block.
+struct CBlockDesc {
+    uint32_t group;
+    uint32_t chunk0;
+    uint32_t nchunks;
+    uint32_t pad;
+};
+
+// One side of one segment being partitioned in a pass.
+struct GroupDesc {
+    uint64_t start;      // first row scanned in the source array
+    uint64_t len;        // rows scanned
+    uint64_t dst_start;  // first row of the group in the destination array
+    uint64_t base;       // ordinal subtracted before the shift
+    uint64_t flo, fhi;   // only rows with flo <= ord <= fhi take part
+    uint32_t shift;      // digit = (ord - base) >> shift
+    uint32_t bits;       // digit width, nbins = 1 << bits
+    uint32_t side;       // column set: 0 = R / sorted relation, 1 = S
+    uint32_t src, dst;   // buffers
+    uint32_t chunk0, nchunks;
+    uint32_t cblock0, ncblocks;
+    uint32_t child0;     // first entry of this group's children in the packed child tables
+    uint32_t pad[2];
+};
+
+// One per-bucket LDS block: a run of adjacent final buckets of one level.
+struct LeafDesc {
+    uint64_t r0, s0;     // first row of each side in the buffer
+    uint64_t base;       // ordinal subtracted before sorting inside the block
+    uint64_t out;        // sort: output index of the first row; join: output offset of the first pair
+    uint32_t rn, sn;     // rows per side (sn = 0 for the sort)
+    uint32_t bits;       // significant bits of (ord - base) over the block's rows
+    uint32_t buf;        // buffer holding the rows
+};
+
+// A bucket whose rows all hold one key: join output is the full cross product.
+struct CrossDesc {
+    uint64_t r0, s0;     // first row of each side in the buffer
+    uint64_t a, b;       // rows of R and of S
+    uint64_t out;        // output offset of the first pair
+    uint64_t pfx;        // first pair of this unit in the launch's flattened pair sequence
+    uint32_t buf, pad;
+};
+
+// A sort bucket of one key that is not yet in the output columns: plain copy.
+struct CopyDesc {
+    uint64_t start;      // first row in the buffer
+    uint64_t len;
+    uint64_t out;        // first output row
+    uint64_t pfx;        // first row of this unit in the launch's flattened row sequence
+    uint32_t buf, pad;
+};
+
+struct BufSet {
+    const void* key[3][2];
+    const int32_t* rid[3][2];
+};
+
+// Leaf block geometry (threads x rows per thread) per kernel family.
+constexpr int LEAF_THREADS = 1024;
+constexpr int LEAF_ITEMS = 8;
+constexpr int LEAF_CAP = LEAF_THREADS * LEAF_ITEMS;   // rows per leaf block
+
+// ---------------------------------------------------------------------------
+// Launchers (tj_kernels.hip). key_bytes is 4 or 8. All return hipSuccess or the
+// launch error.
+// ---------------------------------------------------------------------------
+hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t st);
+hipError_t launch_probe(int key_bytes, const void* a, uint64_t na, const void* b, uint64_t nb,
+                        uint64_t* minmax, hipStream_t st);
+hipError_t launch_hist(int key_bytes, const ChunkDesc* chunks, uint32_t nchunks,
+                       const GroupDesc* groups, BufSet bufs, uint32_t* hist,
+                       uint64_t* gmin, uint64_t* gmax, hipStream_t st);
+hipError_t launch_scan(const CBlockDesc* cblocks, uint32_t ncblocks, const GroupDesc* groups,
+                       uint32_t ngroups, uint32_t* hist, uint32_t* cbsum, uint32_t* ccount,
+                       uint64_t* cstart, hipStream_t st);
+hipError_t launch_scatter(int key_bytes, bool rids, bool keys, const ChunkDesc* chunks, uint32_t nchunks,
+                          const GroupDesc* groups, const uint32_t* hist, const uint32_t* cbsum,
+                          const uint64_t* cstart, BufSet bufs, hipStream_t st);
+hipError_t launch_leaf_sort(int key_bytes, bool wide, const LeafDesc* leaves, uint32_t n,
+                            BufSet bufs, void* out_k, int32_t* out_r, hipStream_t st);
+hipError_t launch_leaf_join(int key_bytes, bool wide, bool materialize, const LeafDesc* leaves,
+                            uint32_t n, BufSet bufs, uint64_t* counts, int32_t* out_r,
+                            int32_t* out_s, hipStream_t st);
+hipError_t launch_cross(const CrossDesc* units, uint32_t n, uint64_t total, BufSet bufs,
+                        int32_t* out_r, int32_t* out_s, hipStream_t st);
+hipError_t launch_copy(int key_bytes, const CopyDesc* units, uint32_t n, uint64_t total,
+                       BufSet bufs, void* out_k, int32_t* out_r, hipStream_t st);
+hipError_t launch_expand(int32_t* dst, const int32_t* src, uint64_t n, uint64_t b, int mode,
+                         hipStream_t st);
+hipError_t launch_wave_scan_test(const uint32_t* in, uint32_t* out, uint64_t n, hipStream_t st);
+
+}  // namespace tj

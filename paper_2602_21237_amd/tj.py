@@ -1,0 +1,251 @@
+"""ctypes binding of libtj.so (include/tj.h): argument marshalling only.
+
+Device memory and streams come from PyTorch; every step of the sort and join
+runs in the library's HIP kernels. The functions take and return torch tensors
+on a ROCm device. There is no fallback: if the library is not built, or no GPU
+is visible, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libtj.so")
+
+TJ_KEY_I32, TJ_KEY_I64 = 4, 8
+TJ_OP_SORT, TJ_OP_JOIN_COUNT, TJ_OP_JOIN_MATERIALIZE = 0, 1, 2
+TJ_OK, TJ_E_ARG, TJ_E_WORKSPACE, TJ_E_CAPACITY = 0, -1, -2, -3
+TJ_E_TOO_LARGE, TJ_E_ALIAS, TJ_E_HIP, TJ_E_INTERNAL = -4, -5, -6, -7
+
+_u64 = ctypes.c_uint64
+_P = ctypes.c_void_p
+_lib = None
+
+
+class TjError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__("%s: %s (status %d)" % (where, strerror(status) if _lib else "?", status))
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("bytes_read", ctypes.c_uint64), ("bytes_written", ctypes.c_uint64),
+                ("workspace_used", ctypes.c_uint64), ("passes", ctypes.c_uint32),
+                ("leaves", ctypes.c_uint32), ("single_key", ctypes.c_uint32),
+                ("key_ranges", ctypes.c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+EXPORTS = {
+    "tj_workspace_query": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _u64, _u64,
+                                          ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),
+    "tj_sort": (ctypes.c_int, [ctypes.c_int, _P, _P, _u64, _P, _P, _P, _u64, _P, _P]),
+    "tj_join_count": (ctypes.c_int, [ctypes.c_int, _P, _u64, _P, _u64, ctypes.POINTER(_u64),
+                                     _P, _u64, _P, _P]),
+    "tj_join_materialize": (ctypes.c_int, [ctypes.c_int, _P, _P, _u64, _P, _P, _u64, _P, _P, _u64,
+                                           ctypes.POINTER(_u64), _P, _u64, _P, _P]),
+    "tj_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "tj_version": (ctypes.c_int, []),
+    "tj_timing": (ctypes.c_int, [ctypes.c_int]),
+    "tj_timing_read": (ctypes.c_int, [_P, ctypes.c_int]),
+    "tj_debug_wave_scan": (ctypes.c_int, [_P, _P, _u64, _P]),
+    "tj_debug_partition_pass": (ctypes.c_int, [_P, _P, _u64, _u64, ctypes.c_uint32, ctypes.c_uint32,
+                                               _P, _P, _P, _P, _u64, _P]),
+}
+
+
+def load(path: str = LIB_PATH):
+    """Loads libtj.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError("libtj.so is not built (%s); run paper_2602_21237_amd.build.build()" % path)
+        lib = ctypes.CDLL(path)
+        for name, (res, args) in EXPORTS.items():
+            f = getattr(lib, name)
+            f.restype, f.argtypes = res, args
+        _lib = lib
+    return _lib
+
+
+def strerror(status: int) -> str:
+    return load().tj_strerror(status).decode()
+
+
+def _check(status: int, where: str):
+    if status != TJ_OK:
+        raise TjError(status, where)
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_uint64),
+                ("bytes", ctypes.c_uint64), ("ms", ctypes.c_double)]
+
+
+def timing(enable: bool) -> None:
+    """Turns per-kernel HIP-event timing on (clearing the counters) or off."""
+    _check(load().tj_timing(1 if enable else 0), "tj_timing")
+
+
+def timing_read() -> dict:
+    """{family: {"launches", "bytes", "ms"}} accumulated since timing(True)."""
+    arr = (KernelStat * 32)()
+    n = load().tj_timing_read(ctypes.cast(arr, ctypes.c_void_p), 32)
+    if n < 0:
+        raise TjError(n, "tj_timing_read")
+    return {arr[i].name.decode(): {"launches": int(arr[i].launches), "bytes": int(arr[i].bytes),
+                                   "ms": float(arr[i].ms)} for i in range(n)}
+
+
+def workspace_query(op: int, key_type: int, n_r: int, n_s: int = 0):
+    """(min_bytes, full_bytes) for an operation of this shape (host only)."""
+    mn, full = _u64(), _u64()
+    _check(load().tj_workspace_query(op, key_type, n_r, n_s, ctypes.byref(mn), ctypes.byref(full)),
+           "tj_workspace_query")
+    return int(mn.value), int(full.value)
+
+
+# --------------------------------------------------------------------------- torch side
+
+def _torch():
+    import torch
+    return torch
+
+
+def _key_type(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.int32:
+        return TJ_KEY_I32
+    if t.dtype == torch.int64:
+        return TJ_KEY_I64
+    raise TypeError("keys must be int32 or int64 tensors, got %s" % t.dtype)
+
+
+def _dev(t, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a device tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _workspace(op, kt, n_r, n_s, workspace, workspace_bytes, device):
+    torch = _torch()
+    if workspace is not None:
+        _dev(workspace, "workspace")
+        nbytes = workspace.numel() * workspace.element_size()
+        if workspace_bytes is None:
+            workspace_bytes = nbytes
+        if workspace_bytes > nbytes:
+            raise ValueError("workspace_bytes exceeds the workspace tensor")
+        return workspace, workspace_bytes
+    mn, full = workspace_query(op, kt, n_r, n_s)
+    if workspace_bytes is None:
+        workspace_bytes = full
+    ws = torch.empty(max(workspace_bytes, 256), dtype=torch.uint8, device=device)
+    return ws, workspace_bytes
+
+
+def sort(keys, rids, keys_out=None, rids_out=None, workspace=None, workspace_bytes=None,
+         stream=None, stats: bool = False):
+    """Stable ascending sort of (keys, rids) by signed key (tj_sort)."""
+    torch = _torch()
+    _dev(keys, "keys")
+    _dev(rids, "rids")
+    if rids.dtype != torch.int32 or rids.shape != keys.shape:
+        raise TypeError("rids must be int32 with the shape of keys")
+    kt = _key_type(keys)
+    n = keys.numel()
+    if keys_out is None:
+        keys_out = torch.empty_like(keys)
+    if rids_out is None:
+        rids_out = torch.empty_like(rids)
+    ws, wsb = _workspace(TJ_OP_SORT, kt, n, 0, workspace, workspace_bytes, keys.device)
+    st = Stats()
+    _check(load().tj_sort(kt, keys.data_ptr(), rids.data_ptr(), n, keys_out.data_ptr(),
+                          rids_out.data_ptr(), ws.data_ptr(), wsb, _stream(stream), ctypes.byref(st)),
+           "tj_sort")
+    return (keys_out, rids_out, st.as_dict()) if stats else (keys_out, rids_out)
+
+
+def join_count(r_keys, s_keys, workspace=None, workspace_bytes=None, stream=None,
+               stats: bool = False):
+    """|R join S| on equal keys (tj_join_count)."""
+    _dev(r_keys, "r_keys")
+    _dev(s_keys, "s_keys")
+    kt = _key_type(r_keys)
+    if _key_type(s_keys) != kt:
+        raise TypeError("r_keys and s_keys must have the same dtype")
+    ws, wsb = _workspace(TJ_OP_JOIN_COUNT, kt, r_keys.numel(), s_keys.numel(), workspace,
+                         workspace_bytes, r_keys.device)
+    cnt = _u64()
+    st = Stats()
+    _check(load().tj_join_count(kt, r_keys.data_ptr(), r_keys.numel(), s_keys.data_ptr(),
+                                s_keys.numel(), ctypes.byref(cnt), ws.data_ptr(), wsb,
+                                _stream(stream), ctypes.byref(st)), "tj_join_count")
+    return (int(cnt.value), st.as_dict()) if stats else int(cnt.value)
+
+
+def join(r_keys, r_rids, s_keys, s_rids, capacity: int | None = None, out_r=None, out_s=None,
+         workspace=None, workspace_bytes=None, stream=None, stats: bool = False):
+    """All (rid_R, rid_S) pairs with equal keys in canonical order (tj_join_materialize).
+
+    Returns (out_r[:count], out_s[:count]) (plus the stats dict). With
+    capacity=None the count is taken first with tj_join_count."""
+    torch = _torch()
+    for t, nm in ((r_keys, "r_keys"), (r_rids, "r_rids"), (s_keys, "s_keys"), (s_rids, "s_rids")):
+        _dev(t, nm)
+    kt = _key_type(r_keys)
+    if _key_type(s_keys) != kt or r_rids.dtype != torch.int32 or s_rids.dtype != torch.int32:
+        raise TypeError("dtype mismatch")
+    if capacity is None:
+        capacity = out_r.numel() if out_r is not None else join_count(r_keys, s_keys, stream=stream)
+    if out_r is None:
+        out_r = torch.empty(max(capacity, 1), dtype=torch.int32, device=r_keys.device)
+    if out_s is None:
+        out_s = torch.empty(max(capacity, 1), dtype=torch.int32, device=r_keys.device)
+    if out_r.numel() < capacity or out_s.numel() < capacity:
+        raise ValueError("output tensors smaller than capacity")
+    ws, wsb = _workspace(TJ_OP_JOIN_MATERIALIZE, kt, r_keys.numel(), s_keys.numel(), workspace,
+                         workspace_bytes, r_keys.device)
+    cnt = _u64()
+    st = Stats()
+    _check(load().tj_join_materialize(kt, r_keys.data_ptr(), r_rids.data_ptr(), r_keys.numel(),
+                                      s_keys.data_ptr(), s_rids.data_ptr(), s_keys.numel(),
+                                      out_r.data_ptr(), out_s.data_ptr(), capacity,
+                                      ctypes.byref(cnt), ws.data_ptr(), wsb, _stream(stream),
+                                      ctypes.byref(st)), "tj_join_materialize")
+    c = int(cnt.value)
+    res = (out_r[:c], out_s[:c])
+    return res + (st.as_dict(),) if stats else res
+
+
+def debug_wave_scan(x):
+    """Inclusive prefix sum within each 64-lane wavefront (uint32 values in an int32 tensor)."""
+    out = _torch().empty_like(x)
+    _check(load().tj_debug_wave_scan(x.data_ptr(), out.data_ptr(), x.numel(), _stream(None)),
+           "tj_debug_wave_scan")
+    return out
+
+
+def debug_partition_pass(keys, rids, base: int, shift: int, bits: int, workspace_bytes: int = 64 << 20):
+    """One stable radix partition pass (int64 keys); returns (keys_out, rids_out, counts)."""
+    torch = _torch()
+    ko, ro = torch.empty_like(keys), torch.empty_like(rids)
+    counts = torch.empty(1 << bits, dtype=torch.int32, device=keys.device)
+    ws = torch.empty(workspace_bytes, dtype=torch.uint8, device=keys.device)
+    _check(load().tj_debug_partition_pass(keys.data_ptr(), rids.data_ptr(), keys.numel(), base, shift,
+                                          bits, ko.data_ptr(), ro.data_ptr(), counts.data_ptr(),
+                                          ws.data_ptr(), workspace_bytes, _stream(None)),
+           "tj_debug_partition_pass")
+    return ko, ro, counts

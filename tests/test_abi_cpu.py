@@ -1,0 +1,91 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function the header declares, reports workspace sizes, and rejects bad
+arguments before issuing any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2602_21237_amd import tj
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tj.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tj_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    lib = tj.load()
+    names = _declared()
+    assert "tj_sort" in names and "tj_join_count" in names and "tj_join_materialize" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(tj.EXPORTS), "binding and header disagree"
+
+
+def test_version_and_strerror():
+    assert tj.load().tj_version() >= 100
+    for s in (0, -1, -2, -3, -4, -5, -6, -7):
+        assert tj.strerror(s) and tj.strerror(s) != "unknown status"
+
+
+@pytest.mark.parametrize("op", [tj.TJ_OP_SORT, tj.TJ_OP_JOIN_COUNT, tj.TJ_OP_JOIN_MATERIALIZE])
+def test_workspace_query(op):
+    mn, full = tj.workspace_query(op, tj.TJ_KEY_I64, 1_000_000, 1_000_000)
+    assert 0 < mn <= (1 << 20) < full  # a 1 MiB budget is accepted
+    mn2, full2 = tj.workspace_query(op, tj.TJ_KEY_I64, 2_000_000, 2_000_000)
+    assert mn2 == mn and full2 > full  # minimum is size independent, full grows
+    row = 12 if op != tj.TJ_OP_JOIN_COUNT else 8
+    nbuf = 1 if op == tj.TJ_OP_SORT else 4
+    assert full - full2 // 2 < full and full >= nbuf * row * 1_000_000 // (2 if op == 0 else 1) // 2
+
+
+def test_workspace_query_errors():
+    lib = tj.load()
+    a, b = ctypes.c_uint64(), ctypes.c_uint64()
+    assert lib.tj_workspace_query(0, 3, 10, 0, ctypes.byref(a), ctypes.byref(b)) == tj.TJ_E_ARG
+    assert lib.tj_workspace_query(7, 8, 10, 0, ctypes.byref(a), ctypes.byref(b)) == tj.TJ_E_ARG
+    assert lib.tj_workspace_query(1, 8, 1 << 31, 5, ctypes.byref(a), ctypes.byref(b)) == tj.TJ_E_TOO_LARGE
+    assert lib.tj_workspace_query(1, 8, 10, 5, None, ctypes.byref(b)) == tj.TJ_E_ARG
+
+
+# Fake, never dereferenced device addresses: the checks below all fail before
+# the library touches the device.
+A, B, C, D, W = 0x10000000, 0x20000000, 0x30000000, 0x40000000, 0x50000000
+
+
+def test_sort_argument_errors():
+    lib = tj.load()
+    n = 1000
+    assert lib.tj_sort(5, A, B, n, C, D, W, 1 << 30, None, None) == tj.TJ_E_ARG
+    assert lib.tj_sort(8, A, B, 1 << 31, C, D, W, 1 << 30, None, None) == tj.TJ_E_TOO_LARGE
+    assert lib.tj_sort(8, None, B, n, C, D, W, 1 << 30, None, None) == tj.TJ_E_ARG
+    assert lib.tj_sort(8, A, B, n, C, D, W + 8, 1 << 30, None, None) == tj.TJ_E_WORKSPACE
+    assert lib.tj_sort(8, A, B, n, A + 8, D, W, 1 << 30, None, None) == tj.TJ_E_ALIAS
+    assert lib.tj_sort(8, A, B, n, C, C + 4000, W, 1 << 30, None, None) == tj.TJ_E_ALIAS
+    assert lib.tj_sort(8, A, B, n, C, D, C + 256, 1 << 30, None, None) == tj.TJ_E_ALIAS
+    assert lib.tj_sort(8, A, B, n, C, D, W, 1024, None, None) == tj.TJ_E_WORKSPACE
+    assert lib.tj_sort(8, A, B, 0, C, D, W, 0, None, None) == tj.TJ_OK  # empty input: no work
+
+
+def test_join_argument_errors():
+    lib = tj.load()
+    cnt = ctypes.c_uint64(7)
+    assert lib.tj_join_count(8, A, 10, B, 10, None, W, 1 << 30, None, None) == tj.TJ_E_ARG
+    assert lib.tj_join_count(4, A, 1 << 31, B, 10, ctypes.byref(cnt), W, 1 << 30, None, None) == tj.TJ_E_TOO_LARGE
+    assert lib.tj_join_count(8, A, 0, B, 10, ctypes.byref(cnt), W, 1 << 30, None, None) == tj.TJ_OK
+    assert cnt.value == 0
+    assert lib.tj_join_count(8, A, 10, B, 10, ctypes.byref(cnt), W, 100, None, None) == tj.TJ_E_WORKSPACE
+    assert lib.tj_join_materialize(8, A, None, 10, B, D, 10, C, W, 100, ctypes.byref(cnt), 0x60000000,
+                                   1 << 30, None, None) == tj.TJ_E_ARG
+    # out_r overlapping an input
+    assert lib.tj_join_materialize(8, A, B, 10, C, D, 10, A, W, 100, ctypes.byref(cnt), 0x60000000,
+                                   1 << 30, None, None) == tj.TJ_E_ALIAS
+    # out_r overlapping out_s
+    assert lib.tj_join_materialize(8, A, B, 10, C, D, 10, W, W + 40, 100, ctypes.byref(cnt), 0x60000000,
+                                   1 << 30, None, None) == tj.TJ_E_ALIAS

@@ -1,0 +1,236 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Every comparison is bit-exact: sorted keys and row ids, join counts, and the
+join pairs in canonical order (key, R position, S position).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import tjgen
+from tests import refcheck as rc
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+I64 = np.iinfo(np.int64)
+I32 = np.iinfo(np.int32)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def tj():
+    import paper_2602_21237_amd as p
+    p.load()
+    return p
+
+
+def check_sort(tj, keys, rids, **kw):
+    ko, ro = tj.sort(dev(keys), dev(rids), **kw)
+    ek, er = oracle.sort(keys, rids)
+    gk, gr = host(ko), host(ro)
+    assert np.array_equal(gk, ek), "keys differ at %s" % np.nonzero(gk != ek)[0][:5]
+    assert np.array_equal(gr, er), "rids differ at %s" % np.nonzero(gr != er)[0][:5]
+
+
+def check_join(tj, rk, rr, sk, sr, **kw):
+    exp_r, exp_s, cnt = oracle.join_pairs(rk, rr, sk, sr)
+    assert tj.join_count(dev(rk), dev(sk), **kw) == cnt
+    pr, ps = tj.join(dev(rk), dev(rr), dev(sk), dev(sr), capacity=cnt, **kw)
+    gr, gs = host(pr), host(ps)
+    assert gr.size == cnt
+    assert np.array_equal(gr, exp_r), "R rids differ at %s" % np.nonzero(gr != exp_r)[0][:5]
+    assert np.array_equal(gs, exp_s), "S rids differ at %s" % np.nonzero(gs != exp_s)[0][:5]
+    return cnt
+
+
+# --------------------------------------------------------------------------- primitives
+
+def test_wave_scan_dpp(tj):
+    rng = np.random.default_rng(0)
+    x = rng.integers(0, 1 << 20, 64 * 300).astype(np.int32)
+    got = host(tj.tj.debug_wave_scan(dev(x))).astype(np.int64)
+    exp = np.cumsum(x.reshape(-1, 64).astype(np.int64), axis=1).reshape(-1)
+    assert np.array_equal(got, exp)
+
+
+@pytest.mark.parametrize("bits,shift", [(8, 0), (8, 12), (3, 40), (1, 5)])
+def test_partition_pass(tj, bits, shift):
+    rng = np.random.default_rng(bits * 100 + shift)
+    n = 100_003
+    k = rng.integers(I64.min, I64.max, n, dtype=np.int64)
+    r = rng.integers(I32.min, I32.max, n, dtype=np.int32)
+    ko, ro, counts = tj.tj.debug_partition_pass(dev(k), dev(r), 0, shift, bits)
+    ordv = k.view(np.uint64) ^ np.uint64(1 << 63)
+    digit = ((ordv >> np.uint64(shift)) & np.uint64((1 << bits) - 1)).astype(np.int64)
+    order = np.argsort(digit, kind="stable")   # stable counting-sort partition
+    assert np.array_equal(host(ko), k[order]) and np.array_equal(host(ro), r[order])
+    assert np.array_equal(host(counts).astype(np.int64), np.bincount(digit, minlength=1 << bits))
+
+
+# --------------------------------------------------------------------------- sort
+
+def test_sort_small_uniform_int32(tj):
+    w = tjgen.small_uniform()
+    check_sort(tj, w["r_keys"], w["r_rids"])
+    check_sort(tj, w["s_keys"], w["s_rids"])
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.99])
+def test_sort_paper_shaped(tj, theta):
+    w = tjgen.paper_shaped(theta, rid_perm=True)
+    check_sort(tj, w["r_keys"], w["r_rids"])
+    check_sort(tj, w["s_keys"], w["s_rids"])
+
+
+def test_sort_uniform_64bit_keys(tj):
+    w = tjgen.sort_uniform64(n=600_000)
+    check_sort(tj, w["keys"], w["rids"])
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 4095, 4096, 4097, 8191, 8192, 8193, 20_000])
+def test_sort_sizes(tj, n):
+    rng = np.random.default_rng(n)
+    k = rng.integers(-1000, 1000, n).astype(np.int64)
+    r = rng.permutation(n).astype(np.int32)
+    check_sort(tj, k, r)
+    check_sort(tj, k.astype(np.int32), r)
+
+
+def test_sort_edge_distributions(tj):
+    rng = np.random.default_rng(42)
+    n = 50_000
+    cases = {
+        "all_equal": np.full(n, 7, np.int64),
+        "two_keys": rng.choice(np.array([-5, 9]), n).astype(np.int64),
+        "presorted": np.arange(n, dtype=np.int64) * 3,
+        "reverse": (n - np.arange(n, dtype=np.int64)) * 1000003,
+        "extremes": rng.choice(np.array([I64.min, I64.min + 1, -1, 0, 1, I64.max - 1, I64.max]), n),
+        "hot_and_wide": np.where(rng.random(n) < 0.6, 123456789,
+                                 rng.integers(I64.min, I64.max, n, dtype=np.int64)),
+    }
+    for name, k in cases.items():
+        r = rng.permutation(n).astype(np.int32)
+        check_sort(tj, k, r)
+    check_sort(tj, np.array([I32.min, I32.max, -1, 0, I32.min], np.int32), np.arange(5, dtype=np.int32))
+
+
+def test_sort_empty(tj):
+    ko, ro = tj.sort(dev(np.zeros(0, np.int64)), dev(np.zeros(0, np.int32)))
+    assert ko.numel() == 0 and ro.numel() == 0
+
+
+# --------------------------------------------------------------------------- join
+
+def test_join_small_uniform_int32(tj):
+    w = tjgen.small_uniform()
+    cnt = check_join(tj, w["r_keys"], w["r_rids"], w["s_keys"], w["s_rids"])
+    assert cnt == rc.sortmerge_count(w["r_keys"], w["s_keys"])
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.99])
+def test_join_paper_shaped(tj, theta):
+    w = tjgen.paper_shaped(theta, rid_perm=True)
+    assert check_join(tj, w["r_keys"], w["r_rids"], w["s_keys"], w["s_rids"]) == 800_000
+
+
+def test_join_multiplicity_skew(tj):
+    # hot keys with R multiplicity 4 and Zipf(0.99) S: several single-key buckets
+    w = tjgen.hbm_scale(0.99, n_r=1 << 18, n_s=1 << 20, hot=1 << 12)
+    assert check_join(tj, w["r_keys"], w["r_rids"], w["s_keys"], w["s_rids"]) == w.expected_count
+
+
+@pytest.mark.parametrize("nr,ns", [(1, 1), (1, 5000), (5000, 1), (63, 65), (4097, 4095), (8193, 9000)])
+def test_join_sizes(tj, nr, ns):
+    rng = np.random.default_rng(nr * 7 + ns)
+    for dom in (4, 300, 1 << 40):
+        rk = rng.integers(0, dom, nr).astype(np.int64)
+        sk = rng.integers(0, dom, ns).astype(np.int64)
+        rr = rng.permutation(nr).astype(np.int32)
+        sr = rng.permutation(ns).astype(np.int32)
+        check_join(tj, rk, rr, sk, sr)
+
+
+def test_join_edge_distributions(tj):
+    rng = np.random.default_rng(5)
+    # one hot key larger than a leaf block on both sides (cross-product path)
+    rk = np.concatenate([np.full(9000, 77), rng.integers(0, 1000, 3000)]).astype(np.int64)
+    sk = np.concatenate([np.full(12000, 77), rng.integers(0, 1000, 5000)]).astype(np.int64)
+    rng.shuffle(rk)
+    rng.shuffle(sk)
+    rr = rng.permutation(rk.size).astype(np.int32)
+    sr = rng.permutation(sk.size).astype(np.int32)
+    check_join(tj, rk, rr, sk, sr)
+    # negative and extreme keys, full 64-bit range
+    ext = np.array([I64.min, I64.min + 1, -1, 0, 1, I64.max - 1, I64.max])
+    rk = np.concatenate([rng.choice(ext, 3000), rng.integers(I64.min, I64.max, 3000, dtype=np.int64)])
+    sk = np.concatenate([rng.choice(ext, 4000), rk[:1000]])
+    check_join(tj, rk, np.arange(rk.size, dtype=np.int32), sk, np.arange(sk.size, dtype=np.int32))
+    # no match at all
+    rk = np.arange(0, 20000, 2, dtype=np.int64)
+    sk = np.arange(1, 20000, 2, dtype=np.int64)
+    assert check_join(tj, rk, np.arange(rk.size, dtype=np.int32), sk, np.arange(sk.size, dtype=np.int32)) == 0
+    # int32 extremes
+    rk = rng.choice(np.array([I32.min, -1, 0, I32.max], np.int32), 5000)
+    sk = rng.choice(np.array([I32.min, 3, I32.max], np.int32), 700)
+    check_join(tj, rk, np.arange(5000, dtype=np.int32), sk, np.arange(700, dtype=np.int32))
+
+
+def test_join_capacity_contract(tj):
+    w = tjgen.paper_shaped(0.5, n=50_000)
+    rk, rr, sk, sr = dev(w["r_keys"]), dev(w["r_rids"]), dev(w["s_keys"]), dev(w["s_rids"])
+    cnt = tj.join_count(rk, sk)
+    assert cnt == 40_000
+    with pytest.raises(tj.TjError) as e:
+        tj.join(rk, rr, sk, sr, capacity=cnt - 1)
+    assert e.value.status == -3
+    pr, ps = tj.join(rk, rr, sk, sr, capacity=cnt)
+    er, es, _ = oracle.join_pairs(w["r_keys"], w["r_rids"], w["s_keys"], w["s_rids"])
+    assert np.array_equal(host(pr), er) and np.array_equal(host(ps), es)
+
+
+def test_join_empty_sides(tj):
+    k = dev(np.arange(10, dtype=np.int64))
+    z = dev(np.zeros(0, np.int64))
+    assert tj.join_count(k, z) == 0 and tj.join_count(z, k) == 0
+
+
+# --------------------------------------------------------------------------- budgets
+
+@pytest.mark.parametrize("theta", [0.0, 0.99])
+@pytest.mark.parametrize("budget", [1 << 20, 64 << 20, None])
+def test_budget_sweep_paper_shaped(tj, theta, budget):
+    """Results are identical at 1 MiB, 64 MiB and an unlimited workspace."""
+    w = tjgen.paper_shaped(theta, rid_perm=True)
+    check_sort(tj, w["s_keys"], w["s_rids"], workspace_bytes=budget)
+    cnt = check_join(tj, w["r_keys"], w["r_rids"], w["s_keys"], w["s_rids"], workspace_bytes=budget)
+    assert cnt == 800_000
+
+
+def test_budget_single_key_ranges(tj):
+    # a hot key too large for a 1 MiB workspace on both sides
+    rng = np.random.default_rng(8)
+    rk = np.concatenate([np.full(60_000, 5), rng.integers(0, 1 << 30, 40_000)]).astype(np.int64)
+    sk = np.concatenate([np.full(70_000, 5), np.full(3, 9), rng.integers(0, 1 << 30, 40_000)]).astype(np.int64)
+    rng.shuffle(rk)
+    rng.shuffle(sk)
+    rr = rng.permutation(rk.size).astype(np.int32)
+    sr = rng.permutation(sk.size).astype(np.int32)
+    check_sort(tj, rk, rr, workspace_bytes=1 << 20)
+    exp_r, exp_s, cnt = oracle.join_pairs(rk, rr, sk, sr)
+    assert tj.join_count(dev(rk), dev(sk), workspace_bytes=1 << 20) == cnt
+    # the pair output of the hot key alone is 4.2e9: check the count only, and
+    # the pairs of a version where the hot key has few R rows
+    rk2 = rk.copy()
+    hot = np.nonzero(rk2 == 5)[0]
+    rk2[hot[3:]] = 11
+    exp_r, exp_s, cnt = oracle.join_pairs(rk2, rr, sk, sr)
+    pr, ps = tj.join(dev(rk2), dev(rr), dev(sk), dev(sr), capacity=cnt, workspace_bytes=1 << 20)
+    assert np.array_equal(host(pr), exp_r) and np.array_equal(host(ps), exp_s)

@@ -1,0 +1,264 @@
+"""Benchmark of the tensor-path sort and equi-join on one MI355X.
+
+A step is one pass of the whole hot path over one batch of resident input:
+  tj_sort of the standalone sort relation, then tj_join_materialize of R and S
+  (range probe, radix histograms, scans, stable scatters, per-bucket LDS sorts
+  and joins, pair materialisation).
+Default workload (HBM scale): |R| = 2^27, |S| = 2^29 int64 keys with int32 row
+ids (unique R keys over [0, 2^40), S foreign-key style, 80% matching,
+uniform), plus a standalone sort of 2^29 (int64 key, int32 rid) rows with keys
+uniform over the full 64-bit range. Inputs are generated on the host from fixed
+seeds and are resident in HBM before timing starts.
+
+value = (sort rows + |R| + |S|) / step time  [tuples/s], whole job.
+roofline: the kernel family with the most time; algorithmic bytes per launch
+over its HIP-event-measured average duration, against the 8 TB/s HBM peak.
+cpu_baseline: the CPU oracle (single thread) on a 1/32 sample of the workload.
+paper_shaped: P50/P99 latency of the |R| = |S| = 10^6 workload at workspace
+budgets of 1 MiB, 64 MiB and unlimited, theta in {0, 0.99}.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "join input tuples/s + sort keys/s (%HBM peak); P50/P99 latency; learned vs radix"
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def pct(xs, q):
+    """Nearest-rank percentile: sorted ascending, x[ceil(q*m) - 1]."""
+    xs = sorted(xs)
+    k = max(1, int(np.ceil(q * len(xs))))
+    return xs[k - 1]
+
+
+def make_workload(kind: str, theta: float):
+    import tjgen
+    if kind == "hbm":
+        w = tjgen.hbm_scale(theta)
+        sort_keys = tjgen.sort_uniform64(1 << 29)["keys"]
+        desc = ("hbm_scale: join |R|=2^27 x |S|=2^29 int64 keys (unique R keys in [0,2^40), "
+                "S 80%% FK matches, Zipf theta=%g) + standalone sort of 2^29 int64 keys uniform "
+                "over 64 bits; int32 row ids" % theta)
+    elif kind == "paper":
+        w = tjgen.paper_shaped(theta)
+        sort_keys = w["s_keys"]
+        desc = "paper_shaped: |R|=|S|=10^6 int64 keys, theta=%g; sort of S" % theta
+    elif kind == "small":
+        w = tjgen.small_uniform()
+        sort_keys = w["r_keys"]
+        desc = "small_uniform: |R|=|S|=10^5 int32 keys uniform in [0,2^20); sort of R"
+    else:
+        raise SystemExit("unknown workload " + kind)
+    return w, sort_keys, desc
+
+
+def cpu_baseline(kind: str, theta: float):
+    """The oracle, untuned, on a bounded sample of the same workload."""
+    import oracle
+    import tjgen
+    if kind == "hbm":
+        frac = 32
+        w = tjgen.hbm_scale(theta, n_r=(1 << 27) // frac, n_s=(1 << 29) // frac,
+                            hot=(1 << 20) // frac if theta > 0 else 0)
+        sk = tjgen.sort_uniform64((1 << 29) // frac)["keys"]
+        sample = ("1/32 of the workload: sort of 2^24 uniform 64-bit keys + join of "
+                  "2^22 x 2^24 rows, same generators")
+    else:
+        w, sk, _ = make_workload(kind, theta)
+        sample = "the whole workload"
+    rids = np.arange(sk.size, dtype=np.int32)
+    t0 = time.perf_counter()
+    oracle.sort(sk, rids)
+    t1 = time.perf_counter()
+    oracle.join_pairs(w["r_keys"], w["r_rids"], w["s_keys"], w["s_rids"])
+    t2 = time.perf_counter()
+    tuples = sk.size + w["r_keys"].size + w["s_keys"].size
+    return {"value": tuples / (t2 - t0), "unit": "tuples/s", "cores": 1, "kind": "oracle",
+            "sample": sample, "seconds": round(t2 - t0, 3), "sort_s": round(t1 - t0, 3),
+            "join_s": round(t2 - t1, 3), "host_cpus": os.cpu_count()}
+
+
+def paper_shaped_sweep(tj, torch, repeats: int):
+    """P50/P99 of sort and join at N = 10^6 for three workspace budgets."""
+    import tjgen
+    out = {}
+    for theta in (0.0, 0.99):
+        w = tjgen.paper_shaped(theta)
+        d = {k: torch.from_numpy(v).to("cuda") for k, v in w.items()}
+        cap = 800_000
+        out_r = torch.empty(cap, dtype=torch.int32, device="cuda")
+        out_s = torch.empty(cap, dtype=torch.int32, device="cuda")
+        ko = torch.empty_like(d["s_keys"])
+        ro = torch.empty_like(d["s_rids"])
+        for name, budget in (("1MiB", 1 << 20), ("64MiB", 64 << 20), ("unlimited", None)):
+            res = {}
+            for op in ("sort", "join"):
+                if budget is None:
+                    opc = tj.TJ_OP_SORT if op == "sort" else tj.TJ_OP_JOIN_MATERIALIZE
+                    wsb = tj.workspace_query(opc, tj.TJ_KEY_I64, 10 ** 6, 10 ** 6)[1]
+                else:
+                    wsb = budget
+                ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+                times = []
+                st = None
+                for i in range(repeats + 5):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    if op == "sort":
+                        _, _, st = tj.sort(d["s_keys"], d["s_rids"], keys_out=ko, rids_out=ro,
+                                           workspace=ws, stats=True)
+                    else:
+                        _, _, st = tj.join(d["r_keys"], d["r_rids"], d["s_keys"], d["s_rids"],
+                                           capacity=cap, out_r=out_r, out_s=out_s, workspace=ws,
+                                           stats=True)
+                    torch.cuda.synchronize()
+                    if i >= 5:
+                        times.append((time.perf_counter() - t0) * 1e3)
+                res[op] = {"p50_ms": round(pct(times, 0.5), 3), "p99_ms": round(pct(times, 0.99), 3),
+                           "key_ranges": st["key_ranges"],
+                           "planned_MB": round((st["bytes_read"] + st["bytes_written"]) / 1e6, 1)}
+                del ws
+            out["theta%g_%s" % (theta, name)] = res
+        del d, out_r, out_s, ko, ro
+        torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="hbm", choices=["hbm", "paper", "small"])
+    ap.add_argument("--theta", type=float, default=0.0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the paper-shaped budget sweep")
+    ap.add_argument("--sweep-repeats", type=int, default=100)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the sort and join run on a single MI355X "
+              "(multi-GPU key-range sharding is a design note, not built); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2602_21237_amd as tj
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    tj.load()
+    log("generating workload %s" % args.workload)
+    w, sort_keys, desc = make_workload(args.workload, args.theta)
+    kt = tj.TJ_KEY_I64 if sort_keys.dtype == np.int64 else tj.TJ_KEY_I32
+    n_sort, n_r, n_s = sort_keys.size, w["r_keys"].size, w["s_keys"].size
+    d_sk = torch.from_numpy(sort_keys).to("cuda")
+    d_sr = torch.arange(n_sort, dtype=torch.int32, device="cuda")
+    d_rk = torch.from_numpy(w["r_keys"]).to("cuda")
+    d_rr = torch.from_numpy(w["r_rids"]).to("cuda")
+    d_skj = torch.from_numpy(w["s_keys"]).to("cuda")
+    d_srj = torch.from_numpy(w["s_rids"]).to("cuda")
+    expected = w.expected_count
+    del sort_keys
+    cap = 4 * n_s if args.workload == "hbm" else (expected if expected is not None else 4 * n_s)
+    ko, ro = torch.empty_like(d_sk), torch.empty_like(d_sr)
+    out_r = torch.empty(cap, dtype=torch.int32, device="cuda")
+    out_s = torch.empty(cap, dtype=torch.int32, device="cuda")
+    ws_sort = torch.empty(tj.workspace_query(tj.TJ_OP_SORT, kt, n_sort)[1], dtype=torch.uint8, device="cuda")
+    ws_join = torch.empty(tj.workspace_query(tj.TJ_OP_JOIN_MATERIALIZE, kt, n_r, n_s)[1],
+                          dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    log("inputs resident: sort %d rows, join %d x %d rows" % (n_sort, n_r, n_s))
+
+    def step():
+        _, _, st_sort = tj.sort(d_sk, d_sr, keys_out=ko, rids_out=ro, workspace=ws_sort, stats=True)
+        pr, _, st_join = tj.join(d_rk, d_rr, d_skj, d_srj, capacity=cap, out_r=out_r, out_s=out_s,
+                                 workspace=ws_join, stats=True)
+        return pr.numel(), st_sort, st_join
+
+    for i in range(args.warmup):
+        cnt, _, _ = step()
+        log("warmup %d done, join count %d" % (i, cnt))
+    if expected is not None:
+        assert cnt == expected, "join count %d != closed form %d" % (cnt, expected)
+    # check the sort output is ordered (a property that holds at any size)
+    assert bool((ko[1:] >= ko[:-1]).all().item()), "sort output not ordered"
+
+    tj.timing(True)
+    torch.cuda.synchronize()
+    times, t_sort, t_join = [], [], []
+    for i in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, sts = tj.sort(d_sk, d_sr, keys_out=ko, rids_out=ro, workspace=ws_sort, stats=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pr, _, stj = tj.join(d_rk, d_rr, d_skj, d_srj, capacity=cap, out_r=out_r, out_s=out_s,
+                             workspace=ws_join, stats=True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        times.append(t2 - t0)
+        t_sort.append(t1 - t0)
+        t_join.append(t2 - t1)
+        log("step %d: sort %.2f ms, join %.2f ms" % (i, (t1 - t0) * 1e3, (t2 - t1) * 1e3))
+    tj.timing(False)
+    fams = tj.timing_read()
+    total_s = sum(times)
+    ms_per_step = total_s / args.steps * 1e3
+    tuples = n_sort + n_r + n_s
+    value = tuples / (total_s / args.steps)
+
+    dom = max(fams, key=lambda f: fams[f]["ms"])
+    fd = fams[dom]
+    avg_ms = fd["ms"] / max(fd["launches"], 1)
+    bytes_per_launch = fd["bytes"] / max(fd["launches"], 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": int(bytes_per_launch), "avg_launch_ms": round(avg_ms, 4),
+                "launches_per_step": fd["launches"] / args.steps}
+    kernels = {f: {"launches_per_step": v["launches"] / args.steps,
+                   "ms_per_step": round(v["ms"] / args.steps, 3),
+                   "GBs": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None}
+               for f, v in fams.items() if v["launches"]}
+    planned = sts["bytes_read"] + sts["bytes_written"] + stj["bytes_read"] + stj["bytes_written"]
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "tuples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64" if kt == 8 else "int32",
+        "data": "synthetic (seeded generators; no dataset)",
+        "config": {"workload": desc, "sort_rows": n_sort, "n_r": n_r, "n_s": n_s,
+                   "join_count": int(pr.numel()), "pair_capacity": cap, "parallelism": "single GPU"},
+        "sort_keys_per_s": round(n_sort / (sum(t_sort) / args.steps), 1),
+        "join_tuples_per_s": round((n_r + n_s) / (sum(t_join) / args.steps), 1),
+        "p50_step_ms": round(pct(times, 0.5) * 1e3, 3), "p99_step_ms": round(pct(times, 0.99) * 1e3, 3),
+        "planned_hbm_frac": round(planned / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+        "roofline": roofline, "kernels": kernels,
+        "plan": {"sort": sts, "join": stj},
+    }
+    del ko, ro, out_r, out_s, ws_sort, ws_join, d_sk, d_sr, d_rk, d_rr, d_skj, d_srj
+    torch.cuda.empty_cache()
+    if not args.no_sweep:
+        log("paper-shaped budget sweep")
+        line["paper_shaped"] = paper_shaped_sweep(tj, torch, args.sweep_repeats)
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        line["cpu_baseline"] = cpu_baseline(args.workload, args.theta)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -4,6 +4,6 @@ The library itself is lib/libtj.so (include/tj.h); this package is its thin
 binding. Loading is lazy, and there is no CPU fallback: the calls raise when
 the library is missing or no GPU is visible.
 """
-from .tj import (TjError, join, join_count, load, sort, strerror,  # noqa: F401
+from .tj import (TjError, join, join_count, load, sort, strerror, timing, timing_read,  # noqa: F401
                  workspace_query, TJ_KEY_I32, TJ_KEY_I64, TJ_OP_SORT, TJ_OP_JOIN_COUNT,
                  TJ_OP_JOIN_MATERIALIZE)

@@ -112,10 +112,9 @@ int tj_join_count(int key_type, const void *r_keys, uint64_t n_r,
  *   out_r[capacity], out_s[capacity]: device outputs; pair t is
  *     (out_r[t], out_s[t]).
  *   *count (host): set to |R join S| on TJ_OK and on TJ_E_CAPACITY.
- * If |R join S| > capacity the call returns TJ_E_CAPACITY. When the budget
- * does not bind, the count is known before any pair is written and nothing is
- * written; under a binding budget the key ranges that fit may already have been
- * written. No element at or beyond `capacity` is ever written.
+ * If |R join S| > capacity the call returns TJ_E_CAPACITY; the contents of
+ * out_r/out_s are then unspecified, and no element at or beyond `capacity`
+ * is ever written.
  */
 int tj_join_materialize(int key_type, const void *r_keys, const int32_t *r_rids, uint64_t n_r,
                         const void *s_keys, const int32_t *s_rids, uint64_t n_s,

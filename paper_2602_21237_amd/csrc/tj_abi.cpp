@@ -39,18 +39,20 @@ inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
 inline uint32_t nbits64(uint64_t x) { return x ? 64u - (uint32_t)__builtin_clzll(x) : 0u; }
 
-// Table capacities of one tier.
+// Table capacities of one tier. A pass whose groups, chunks, scan blocks or
+// child entries exceed them runs as several launch batches.
 struct Caps {
-    uint32_t groups, chunks, cblocks, leaves, units;
+    uint32_t groups, chunks, cblocks, children, leaves, units;
 };
 
 Caps tier_caps(int t)
 {
     Caps c;
-    c.groups = 16u << t;
+    c.groups = 64u << t;
     c.chunks = 64u << t;
-    c.cblocks = 16u << t;
-    c.leaves = 256u << t;
+    c.cblocks = 64u << t;
+    c.children = 4096u << t;
+    c.leaves = 1024u << t;
     c.units = 64u << t;
     return c;
 }
@@ -64,14 +66,49 @@ uint64_t table_bytes(const Caps& c)
     b += align_up((uint64_t)c.cblocks * sizeof(CBlockDesc), ALIGN);
     b += align_up((uint64_t)c.chunks * NB * 4, ALIGN);               // hist
     b += align_up((uint64_t)c.cblocks * NB * 4, ALIGN);              // cbsum
-    const uint64_t children = (uint64_t)c.groups * NB;
+    const uint64_t children = c.children;
     b += align_up(children * 4, ALIGN);                               // ccount
     b += 3 * align_up(children * 8, ALIGN);                           // cstart, gmin, gmax
     b += align_up((uint64_t)c.leaves * sizeof(LeafDesc), ALIGN);
-    b += align_up((uint64_t)c.leaves * 8, ALIGN);                    // leaf counts
+    b += align_up(((uint64_t)c.leaves + 1) * 8, ALIGN);              // look-back status
+    b += align_up(children * sizeof(ChildRec), ALIGN);                // folded child records
     const uint64_t ub = sizeof(CrossDesc) > sizeof(CopyDesc) ? sizeof(CrossDesc) : sizeof(CopyDesc);
     b += align_up((uint64_t)c.units * ub, ALIGN);
     return b;
+}
+
+// Pinned host staging, one grow-only buffer per host thread and direction.
+// It is never freed (the process exit reclaims it), so no HIP call runs from a
+// thread-exit destructor.
+struct PinnedBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    void* get(size_t n)
+    {
+        if (n <= cap) return p;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+        size_t want = 1 << 20;
+        while (want < n) want *= 2;
+        if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) return nullptr;
+        cap = want;
+        return p;
+    }
+};
+thread_local PinnedBuf* t_down = nullptr;
+thread_local PinnedBuf* t_up = nullptr;
+
+void* pinned_down(size_t n)
+{
+    if (!t_down) t_down = new PinnedBuf();
+    return t_down->get(n);
+}
+
+void* pinned_up(size_t n)
+{
+    if (!t_up) t_up = new PinnedBuf();
+    return t_up->get(n);
 }
 
 // Bytes of one row in the ping-pong buffers.
@@ -98,11 +135,12 @@ uint64_t full_data_bytes(const Shape& s)
     return b;
 }
 
-// Smallest data region: two buffers of one leaf block of rows per side, plus
-// alignment slack.
+// Smallest data region: ping and pong buffers of 2048 rows per side (a key
+// range only has to hold its own rows; smaller budgets just mean more ranges),
+// plus alignment slack.
 uint64_t min_data_bytes(const Shape& s)
 {
-    const uint64_t per = align_up((uint64_t)LEAF_CAP * row_bytes(s.kb, s.rids), ALIGN) * 2 + 16 * ALIGN;
+    const uint64_t per = align_up(2048ull * row_bytes(s.kb, s.rids), ALIGN) * 2 + 16 * ALIGN;
     return s.join ? 2 * per : per;
 }
 
@@ -182,7 +220,9 @@ struct Exec {
     uint64_t* d_gmin = nullptr;
     uint64_t* d_gmax = nullptr;
     LeafDesc* d_leaves = nullptr;
-    uint64_t* d_counts = nullptr;
+    uint64_t* d_status = nullptr;  // caps.leaves + 1 look-back words
+    ChildRec* d_crec = nullptr;     // caps.children folded child records
+    // scalars in the probe block: [0..1] min/max, [2] pair total, [3] ticket (low) + error (high)
     void* d_units = nullptr;
 
     // data buffer capacities (rows per side) when the buffers live in the workspace
@@ -249,13 +289,14 @@ struct Exec {
         d_cblocks = (CBlockDesc*)take((uint64_t)caps.cblocks * sizeof(CBlockDesc));
         d_hist = (uint32_t*)take((uint64_t)caps.chunks * NB * 4);
         d_cbsum = (uint32_t*)take((uint64_t)caps.cblocks * NB * 4);
-        const uint64_t children = (uint64_t)caps.groups * NB;
+        const uint64_t children = caps.children;
         d_ccount = (uint32_t*)take(children * 4);
         d_cstart = (uint64_t*)take(children * 8);
         d_gmin = (uint64_t*)take(children * 8);
         d_gmax = (uint64_t*)take(children * 8);
         d_leaves = (LeafDesc*)take((uint64_t)caps.leaves * sizeof(LeafDesc));
-        d_counts = (uint64_t*)take((uint64_t)caps.leaves * 8);
+        d_status = (uint64_t*)take(((uint64_t)caps.leaves + 1) * 8);
+        d_crec = (ChildRec*)take(children * sizeof(ChildRec));
         const uint64_t ub = sizeof(CrossDesc) > sizeof(CopyDesc) ? sizeof(CrossDesc) : sizeof(CopyDesc);
         d_units = take((uint64_t)caps.units * ub);
         return p <= end ? TJ_OK : TJ_E_WORKSPACE;
@@ -318,7 +359,8 @@ struct Exec {
                     need_cb += (nc + CBLOCK - 1) / CBLOCK;
                 }
                 if (groups.size() + nside > caps.groups || chunks.size() + need_chunks > caps.chunks ||
-                    cblocks.size() + need_cb > caps.cblocks) {
+                    cblocks.size() + need_cb > caps.cblocks ||
+                    child + ((uint64_t)nside << plan[si].bits) > caps.children) {
                     if (groups.empty()) return TJ_E_WORKSPACE;
                     break;
                 }
@@ -389,35 +431,37 @@ struct Exec {
                 return launch_scatter(sh.kb, sh.rids, write_keys, d_chunks, nc, d_groups, d_hist, d_cbsum,
                                       d_cstart, bufs, st);
             }));
-            std::vector<uint32_t> cnt(child);
-            std::vector<uint64_t> mn(child), mx(child), cs(child);
-            TJ_CK(hipMemcpyAsync(cnt.data(), d_ccount, child * 4ull, hipMemcpyDeviceToHost, st));
-            TJ_CK(hipMemcpyAsync(cs.data(), d_cstart, child * 8ull, hipMemcpyDeviceToHost, st));
-            TJ_CK(hipMemcpyAsync(mn.data(), d_gmin, child * 8ull, hipMemcpyDeviceToHost, st));
-            TJ_CK(hipMemcpyAsync(mx.data(), d_gmax, child * 8ull, hipMemcpyDeviceToHost, st));
+            // one compact record per child (both sides folded), read back pinned
+            const uint32_t nrec = child / (uint32_t)nside;
+            TJ_CK(launch_children(d_groups, ng, nside, d_ccount, d_gmin, d_gmax, d_crec, st));
+            ChildRec* rec = (ChildRec*)pinned_down(nrec * sizeof(ChildRec));
+            if (!rec) return TJ_E_HIP;
+            TJ_CK(hipMemcpyAsync(rec, d_crec, nrec * sizeof(ChildRec), hipMemcpyDeviceToHost, st));
             TJ_CK(hipStreamSynchronize(st));
-            // children in key order: segment order, then digit order
+            // children in key order: segment order, then digit order; a child's
+            // rows start where its smaller-digit siblings end
+            uint64_t moved_rows = 0;
             for (uint32_t gi = 0; gi < ng; gi += (uint32_t)nside) {
                 const GroupDesc& g0 = groups[gi];
                 const uint32_t nbins = 1u << g0.bits;
+                const ChildRec* cr = rec + g0.child0 / (uint32_t)nside;
+                uint64_t r0 = g0.dst_start, s0 = nside == 2 ? groups[gi + 1].dst_start : 0;
                 for (uint32_t d = 0; d < nbins; d++) {
-                    Seg c{};
+                    Seg c;
                     c.buf = dst;
-                    c.r0 = cs[g0.child0 + d];
-                    c.rn = cnt[g0.child0 + d];
-                    c.lo = mn[g0.child0 + d];
-                    c.hi = mx[g0.child0 + d];
-                    if (nside == 2) {
-                        const GroupDesc& g1 = groups[gi + 1];
-                        c.s0 = cs[g1.child0 + d];
-                        c.sn = cnt[g1.child0 + d];
-                        c.lo = std::min(c.lo, mn[g1.child0 + d]);
-                        c.hi = std::max(c.hi, mx[g1.child0 + d]);
-                    }
-                    stats.bytes_written += (c.rn + c.sn) * row_bytes(sh.kb, sh.rids);
+                    c.r0 = r0;
+                    c.rn = cr[d].rn;
+                    c.s0 = s0;
+                    c.sn = cr[d].sn;
+                    c.lo = cr[d].lo;
+                    c.hi = cr[d].hi;
+                    r0 += c.rn;
+                    s0 += c.sn;
+                    moved_rows += c.rn + c.sn;
                     out.push_back(c);
                 }
             }
+            stats.bytes_written += moved_rows * row_bytes(sh.kb, sh.rids);
             (void)first;
         }
         return TJ_OK;
@@ -578,103 +622,116 @@ struct Exec {
         return TJ_OK;
     }
 
-    // Counts of every leaf (device pass) into host `counts`.
-    int count_leaves(std::vector<uint64_t>& counts)
+    // Counts (mat = false) or materialises (mat = true) the range's leaves and
+    // crosses. Units are taken in key order, which is the order of their first
+    // R row (every unit has R rows, and partitioning keeps each bucket inside
+    // its parent's index range). Output starts at `base`; pairs at or beyond
+    // `capacity` are not written. *total_out receives the range's pair count.
+    int finish_join(uint64_t* total_out, uint64_t base, int32_t* out_r, int32_t* out_s,
+                    uint64_t capacity, bool mat)
     {
-        counts.assign(leaves.size(), 0);
-        for (int wide = 0; wide < 2; wide++) {
-            std::vector<LeafDesc> sel;
-            std::vector<size_t> where;
-            for (size_t i = 0; i < leaves.size(); i++)
-                if ((leaves[i].bits > 32) == (wide == 1)) {
-                    sel.push_back(leaves[i]);
-                    where.push_back(i);
-                }
-            std::vector<uint64_t> c(std::min<size_t>(caps.leaves, sel.size()));
-            for (size_t i = 0; i < sel.size(); i += caps.leaves) {
-                const uint32_t n = (uint32_t)std::min<size_t>(caps.leaves, sel.size() - i);
-                TJ_CK(hipMemcpyAsync(d_leaves, sel.data() + i, n * sizeof(LeafDesc), hipMemcpyHostToDevice, st));
-                uint64_t rows = 0;
-                for (uint32_t k = 0; k < n; k++) rows += sel[i + k].rn + sel[i + k].sn;
-                TJ_CK(timed(F_LEAF_COUNT, rows * sh.kb, [&] {
-                    return launch_leaf_join(sh.kb, wide == 1, false, d_leaves, n, bufs, d_counts, nullptr,
-                                            nullptr, st);
-                }));
-                TJ_CK(hipMemcpyAsync(c.data(), d_counts, n * 8ull, hipMemcpyDeviceToHost, st));
-                TJ_CK(hipStreamSynchronize(st));
-                for (uint32_t k = 0; k < n; k++) counts[where[i + k]] = c[k];
-            }
+        auto lr0 = [](const LeafDesc& a, const LeafDesc& b) { return a.r0 < b.r0; };
+        auto cr0 = [](const CrossDesc& a, const CrossDesc& b) { return a.r0 < b.r0; };
+        if (!std::is_sorted(leaves.begin(), leaves.end(), lr0)) std::sort(leaves.begin(), leaves.end(), lr0);
+        if (!std::is_sorted(crosses.begin(), crosses.end(), cr0)) std::sort(crosses.begin(), crosses.end(), cr0);
+        bool wide = false;
+        uint64_t leaf_rows = 0;
+        for (const LeafDesc& L : leaves) {
+            wide = wide || L.bits > 32;
+            leaf_rows += L.rn + L.sn;
         }
-        for (const LeafDesc& L : leaves) stats.bytes_read += (uint64_t)(L.rn + L.sn) * sh.kb;
-        return TJ_OK;
-    }
-
-    // Counts the range's leaves and crosses, lays their output out in key order
-    // from out_base, and writes the pairs if write && out_base + total <= capacity.
-    int finish_join(uint64_t* total_out, uint64_t out_base, int32_t* out_r, int32_t* out_s,
-                    uint64_t capacity, bool write)
-    {
-        std::vector<uint64_t> counts;
-        TJ_RET(count_leaves(counts));
-        std::vector<Unit> units;
-        units.reserve(leaves.size() + crosses.size());
-        for (size_t i = 0; i < leaves.size(); i++)
-            if (counts[i]) units.push_back(Unit{leaf_lo[i], 0, (uint32_t)i, counts[i]});
-        for (size_t i = 0; i < crosses.size(); i++)
-            units.push_back(Unit{cross_lo[i], 1, (uint32_t)i, crosses[i].a * crosses[i].b});
-        std::sort(units.begin(), units.end(), [](const Unit& a, const Unit& b) { return a.lo < b.lo; });
-        uint64_t total = 0;
-        for (Unit& u : units) {
-            const uint64_t o = out_base + total;
-            if (u.kind == 0) leaves[u.index].out = o;
-            else crosses[u.index].out = o;
-            total += u.count;
-        }
-        *total_out = total;
         stats.leaves += (uint32_t)leaves.size();
-        const bool fits = out_base + total <= capacity;
-        if (write && fits) {
-            for (int wide = 0; wide < 2; wide++) {
-                std::vector<LeafDesc> sel;
-                std::vector<uint64_t> sel_cnt;
-                for (size_t i = 0; i < leaves.size(); i++)
-                    if (counts[i] && (leaves[i].bits > 32) == (wide == 1)) {
-                        sel.push_back(leaves[i]);
-                        sel_cnt.push_back(counts[i]);
-                    }
-                for (size_t i = 0; i < sel.size(); i += caps.leaves) {
-                    const uint32_t n = (uint32_t)std::min<size_t>(caps.leaves, sel.size() - i);
-                    TJ_CK(hipMemcpyAsync(d_leaves, sel.data() + i, n * sizeof(LeafDesc), hipMemcpyHostToDevice, st));
-                    uint64_t rows = 0, pairs = 0;
-                    for (uint32_t k = 0; k < n; k++) {
-                        rows += sel[i + k].rn + sel[i + k].sn;
-                        pairs += sel_cnt[i + k];
-                    }
-                    TJ_CK(timed(F_LEAF_MAT, rows * row_bytes(sh.kb, true) + pairs * 8, [&] {
-                        return launch_leaf_join(sh.kb, wide == 1, true, d_leaves, n, bufs, d_counts, out_r,
-                                                out_s, st);
-                    }));
-                    TJ_CK(hipStreamSynchronize(st));
-                }
-                for (const LeafDesc& L : sel) stats.bytes_read += (uint64_t)(L.rn + L.sn) * row_bytes(sh.kb, true);
-            }
-            for (size_t i = 0; i < crosses.size(); i += caps.units) {
-                const uint32_t n = (uint32_t)std::min<size_t>(caps.units, crosses.size() - i);
-                uint64_t t = 0;
-                for (uint32_t k = 0; k < n; k++) {
-                    crosses[i + k].pfx = t;
-                    t += crosses[i + k].a * crosses[i + k].b;
-                    stats.bytes_read += (crosses[i + k].a + crosses[i + k].b) * 4;
-                }
-                TJ_CK(hipMemcpyAsync(d_units, crosses.data() + i, n * sizeof(CrossDesc), hipMemcpyHostToDevice, st));
-                uint64_t in_rows = 0;
-                for (uint32_t k = 0; k < n; k++) in_rows += crosses[i + k].a + crosses[i + k].b;
-                TJ_CK(timed(F_CROSS, t * 8 + in_rows * 4, [&] {
-                    return launch_cross((const CrossDesc*)d_units, n, t, bufs, out_r, out_s, st);
+        uint64_t* d_total = d_probe + 2;
+        uint32_t* d_ticket = (uint32_t*)(d_probe + 3);
+        uint32_t* d_err = d_ticket + 1;
+        if (!mat) {
+            uint64_t cross_pairs = 0;
+            for (const CrossDesc& c : crosses) cross_pairs += c.a * c.b;
+            TJ_CK(launch_fill_u64(d_total, 1, 0, st));
+            for (size_t i = 0; i < leaves.size(); i += caps.leaves) {
+                const uint32_t n = (uint32_t)std::min<size_t>(caps.leaves, leaves.size() - i);
+                uint64_t rows = 0;
+                for (uint32_t k = 0; k < n; k++) rows += leaves[i + k].rn + leaves[i + k].sn;
+                TJ_CK(hipMemcpyAsync(d_leaves, leaves.data() + i, n * sizeof(LeafDesc), hipMemcpyHostToDevice, st));
+                TJ_CK(timed(F_LEAF_COUNT, rows * sh.kb, [&] {
+                    return launch_leaf_join(sh.kb, wide, false, d_leaves, n, bufs, d_status, d_ticket, d_total,
+                                            d_err, nullptr, nullptr, 0, st);
                 }));
-                TJ_CK(hipStreamSynchronize(st));
             }
-            stats.bytes_written += total * 8;
+            uint64_t t = 0;
+            TJ_CK(hipMemcpyAsync(&t, d_total, 8, hipMemcpyDeviceToHost, st));
+            TJ_CK(hipStreamSynchronize(st));
+            stats.bytes_read += leaf_rows * sh.kb;
+            *total_out = t + cross_pairs;
+        } else {
+            uint64_t carry = base;
+            size_t li = 0, ci = 0;
+            std::vector<LeafDesc> bl;
+            std::vector<CrossDesc> bc;
+            while (li < leaves.size() || ci < crosses.size()) {
+                bl.clear();
+                bc.clear();
+                uint64_t pre = 0;  // single-key pairs of this batch so far
+                while (li < leaves.size() || ci < crosses.size()) {
+                    const bool take_cross =
+                        ci < crosses.size() && (li == leaves.size() || crosses[ci].r0 < leaves[li].r0);
+                    if (take_cross) {
+                        if (bc.size() == caps.units) break;
+                        CrossDesc c = crosses[ci++];
+                        c.out = pre;
+                        c.leaf_before = (uint32_t)bl.size();
+                        c.pfx = 0;
+                        pre += c.a * c.b;
+                        bc.push_back(c);
+                    } else {
+                        if (bl.size() == caps.leaves) break;
+                        LeafDesc L = leaves[li++];
+                        L.out = pre;
+                        bl.push_back(L);
+                    }
+                }
+                const uint32_t nl = (uint32_t)bl.size(), nc = (uint32_t)bc.size();
+                TJ_CK(launch_fill_u64(d_status, 1, STATUS_INCLUSIVE | carry, st));
+                TJ_CK(launch_fill_u64(d_status + 1, nl, 0, st));
+                TJ_CK(launch_fill_u64(d_probe + 3, 1, 0, st));  // ticket and error flag
+                size_t leaf_timer = (size_t)-1;
+                if (nl) {
+                    uint64_t rows = 0;
+                    for (const LeafDesc& L : bl) rows += L.rn + L.sn;
+                    leaf_timer = pending.size();
+                    TJ_CK(hipMemcpyAsync(d_leaves, bl.data(), nl * sizeof(LeafDesc), hipMemcpyHostToDevice, st));
+                    TJ_CK(timed(F_LEAF_MAT, rows * row_bytes(sh.kb, true), [&] {
+                        return launch_leaf_join(sh.kb, wide, true, d_leaves, nl, bufs, d_status, d_ticket,
+                                                d_total, d_err, out_r, out_s, capacity, st);
+                    }));
+                    stats.bytes_read += rows * row_bytes(sh.kb, true);
+                }
+                if (nc) {
+                    uint64_t t = 0, in_rows = 0;
+                    for (CrossDesc& c : bc) {
+                        c.pfx = t;
+                        t += c.a * c.b;
+                        in_rows += c.a + c.b;
+                    }
+                    TJ_CK(hipMemcpyAsync(d_units, bc.data(), nc * sizeof(CrossDesc), hipMemcpyHostToDevice, st));
+                    TJ_CK(timed(F_CROSS, t * 8 + in_rows * 4, [&] {
+                        return launch_cross((const CrossDesc*)d_units, nc, t, bufs, d_status, out_r, out_s,
+                                            capacity, st);
+                    }));
+                    stats.bytes_read += in_rows * 4;
+                }
+                uint64_t fin[2] = {0, 0};
+                TJ_CK(hipMemcpyAsync(&fin[0], d_status + nl, 8, hipMemcpyDeviceToHost, st));
+                TJ_CK(hipMemcpyAsync(&fin[1], d_probe + 3, 8, hipMemcpyDeviceToHost, st));
+                TJ_CK(hipStreamSynchronize(st));
+                if (fin[1] >> 32) return TJ_E_INTERNAL;  // a look-back expired
+                const uint64_t leaf_pairs = (fin[0] & STATUS_VALUE) - carry;
+                if (leaf_timer < pending.size()) pending[leaf_timer].bytes += leaf_pairs * 8;
+                carry = (fin[0] & STATUS_VALUE) + pre;
+            }
+            *total_out = carry - base;
+            const uint64_t written = std::min(carry, capacity) > base ? std::min(carry, capacity) - base : 0;
+            stats.bytes_written += written * 8;
         }
         leaves.clear();
         leaf_lo.clear();
@@ -1224,7 +1281,9 @@ int tj_debug_partition_pass(const int64_t* keys, const int32_t* rids, uint64_t n
     Exec x;
     x.sh = Shape{TJ_OP_SORT, 8, false, false, true, n, 0};
     x.st = (hipStream_t)stream;
-    x.caps = tier_caps(2);
+    int tier = TABLE_TIERS - 1;
+    while (tier > 0 && table_bytes(tier_caps(tier)) > workspace_bytes) tier--;
+    x.caps = tier_caps(tier);
     char* p = (char*)workspace;
     TJ_RET(x.carve_tables(p, (char*)workspace + workspace_bytes));
     x.bufs.key[BUF_IN][0] = keys;
@@ -1241,7 +1300,8 @@ int tj_debug_partition_pass(const int64_t* keys, const int32_t* rids, uint64_t n
     g.src = BUF_IN;
     g.dst = BUF_A;
     std::vector<ChunkDesc> chunks;
-    const uint64_t ch = align_up((n + 63) / 64, PART_TILE);
+    uint64_t ch = std::max<uint64_t>(PART_TILE, align_up((n + TARGET_CHUNKS - 1) / TARGET_CHUNKS, PART_TILE));
+    while ((n + ch - 1) / ch > x.caps.chunks) ch *= 2;
     for (uint64_t c0 = 0; c0 < n; c0 += ch)
         chunks.push_back(ChunkDesc{c0, (uint32_t)std::min<uint64_t>(ch, n - c0), 0,
                                    (uint32_t)(chunks.size() / CBLOCK), 0});

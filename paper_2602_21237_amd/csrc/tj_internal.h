@@ -15,9 +15,8 @@ namespace tj {
 
 constexpr int MAX_DIGIT_BITS = 9;             // widest partition digit
 constexpr int NB = 1 << MAX_DIGIT_BITS;       // digit bins per group (table stride)
-constexpr int PART_THREADS = 256;             // histogram / scatter block
-constexpr int PART_ITEMS = 16;                // rows per thread per scatter tile
-constexpr int PART_TILE = PART_THREADS * PART_ITEMS;
+constexpr int PART_THREADS = 256;             // histogram block
+constexpr int PART_TILE = 4096;               // rows per scatter tile (chunks are multiples)
 constexpr int CBLOCK = 32;                    // chunks per first-level scan block
 
 enum Buf : uint32_t { BUF_IN = 0, BUF_A = 1, BUF_B = 2 };
@@ -60,19 +59,22 @@ struct GroupDesc {
 struct LeafDesc {
     uint64_t r0, s0;     // first row of each side in the buffer
     uint64_t base;       // ordinal subtracted before sorting inside the block
-    uint64_t out;        // sort: output index of the first row; join: output offset of the first pair
+    uint64_t out;        // sort: output index of the first row; join: range base + pairs of
+                         // the single-key units before this block in key order
     uint32_t rn, sn;     // rows per side (sn = 0 for the sort)
     uint32_t bits;       // significant bits of (ord - base) over the block's rows
     uint32_t buf;        // buffer holding the rows
 };
 
 // A bucket whose rows all hold one key: join output is the full cross product.
+// Its first pair goes to out + (pair prefix of the per-bucket joins before it).
 struct CrossDesc {
     uint64_t r0, s0;     // first row of each side in the buffer
     uint64_t a, b;       // rows of R and of S
-    uint64_t out;        // output offset of the first pair
+    uint64_t out;        // range base + pairs of earlier single-key units
     uint64_t pfx;        // first pair of this unit in the launch's flattened pair sequence
-    uint32_t buf, pad;
+    uint32_t buf;
+    uint32_t leaf_before;  // per-bucket joins before this unit in key order (status slot)
 };
 
 // A sort bucket of one key that is not yet in the output columns: plain copy.
@@ -84,15 +86,20 @@ struct CopyDesc {
     uint32_t buf, pad;
 };
 
+// A child bucket after a pass, both sides folded: rows per side and the
+// smallest / largest key ordinal present (lo > hi when the bucket is empty).
+struct ChildRec {
+    uint32_t rn, sn;
+    uint64_t lo, hi;
+};
+
 struct BufSet {
     const void* key[3][2];
     const int32_t* rid[3][2];
 };
 
-// Leaf block geometry (threads x rows per thread) per kernel family.
-constexpr int LEAF_THREADS = 1024;
-constexpr int LEAF_ITEMS = 8;
-constexpr int LEAF_CAP = LEAF_THREADS * LEAF_ITEMS;   // rows per leaf block
+// Rows per leaf block (the block shape depends on the key word, see the kernels).
+constexpr int LEAF_CAP = 8192;
 
 // ---------------------------------------------------------------------------
 // Launchers (tj_kernels.hip). key_bytes is 4 or 8. All return hipSuccess or the
@@ -110,13 +117,26 @@ hipError_t launch_scan(const CBlockDesc* cblocks, uint32_t ncblocks, const Group
 hipError_t launch_scatter(int key_bytes, bool rids, bool keys, const ChunkDesc* chunks, uint32_t nchunks,
                           const GroupDesc* groups, const uint32_t* hist, const uint32_t* cbsum,
                           const uint64_t* cstart, BufSet bufs, hipStream_t st);
+// Folds each segment's per-side child tables into ChildRec records, written at
+// group.child0 / nside (groups come in side order per segment).
+hipError_t launch_children(const GroupDesc* groups, uint32_t ngroups, int nside,
+                           const uint32_t* ccount, const uint64_t* gmin, const uint64_t* gmax,
+                           ChildRec* out, hipStream_t st);
 hipError_t launch_leaf_sort(int key_bytes, bool wide, const LeafDesc* leaves, uint32_t n,
                             BufSet bufs, void* out_k, int32_t* out_r, hipStream_t st);
+// Count mode adds the leaves' pair counts to *total. Materialise mode needs
+// status[0] = inclusive-flagged carry-in offset, status[1..n] = 0, *ticket = 0;
+// afterwards status[n] holds the inclusive pair total and *err != 0 flags an
+// expired look-back.
 hipError_t launch_leaf_join(int key_bytes, bool wide, bool materialize, const LeafDesc* leaves,
-                            uint32_t n, BufSet bufs, uint64_t* counts, int32_t* out_r,
-                            int32_t* out_s, hipStream_t st);
+                            uint32_t n, BufSet bufs, uint64_t* status, uint32_t* ticket,
+                            uint64_t* total, uint32_t* err, int32_t* out_r, int32_t* out_s,
+                            uint64_t capacity, hipStream_t st);
 hipError_t launch_cross(const CrossDesc* units, uint32_t n, uint64_t total, BufSet bufs,
-                        int32_t* out_r, int32_t* out_s, hipStream_t st);
+                        const uint64_t* status, int32_t* out_r, int32_t* out_s, uint64_t capacity,
+                        hipStream_t st);
+constexpr uint64_t STATUS_INCLUSIVE = 2ull << 62;   // flag of a published inclusive prefix
+constexpr uint64_t STATUS_VALUE = (1ull << 62) - 1;
 hipError_t launch_copy(int key_bytes, const CopyDesc* units, uint32_t n, uint64_t total,
                        BufSet bufs, void* out_k, int32_t* out_r, hipStream_t st);
 hipError_t launch_expand(int32_t* dst, const int32_t* src, uint64_t n, uint64_t b, int mode,

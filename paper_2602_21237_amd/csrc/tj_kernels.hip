@@ -135,6 +135,52 @@ __device__ __forceinline__ uint64_t block_sum64(uint64_t v, uint64_t* tmp)
     return tot;
 }
 
+// Inclusive running maximum across the wave (same DPP pattern as the sum; 0 is
+// the identity, values are non-negative).
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t v)
+{
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));
+    return v;
+}
+
+// Maximum over the values of all threads before this one (0 for thread 0).
+template <int NT>
+__device__ __forceinline__ uint32_t block_excl_max(uint32_t v, uint32_t* tmp)
+{
+    constexpr int NW = NT / 64;
+    const uint32_t w = threadIdx.x / 64, l = threadIdx.x & 63;
+    const uint32_t inc = wave_incl_max(v);
+    if (l == 63) tmp[w] = inc;
+    uint32_t prev = (uint32_t)__shfl_up((int)inc, 1u, 64);
+    if (l == 0) prev = 0;
+    __syncthreads();
+    uint32_t off = 0;
+#pragma unroll
+    for (int i = 0; i < NW; i++) off = ((uint32_t)i < w && tmp[i] > off) ? tmp[i] : off;
+    __syncthreads();
+    return max(off, prev);
+}
+
+// Maximum over the block.
+template <int NT>
+__device__ __forceinline__ uint32_t block_max(uint32_t v, uint32_t* tmp)
+{
+    constexpr int NW = NT / 64;
+    const uint32_t inc = wave_incl_max(v);
+    if ((threadIdx.x & 63) == 63) tmp[threadIdx.x / 64] = inc;
+    __syncthreads();
+    uint32_t m = 0;
+#pragma unroll
+    for (int i = 0; i < NW; i++) m = tmp[i] > m ? tmp[i] : m;
+    __syncthreads();
+    return m;
+}
+
 // Stable rank of one row per lane among the rows of this wavefront with the
 // same digit: rows of earlier rounds (counted in this wave's private LDS
 // histogram `hist`) and lower lanes of this round. The lanes sharing a digit
@@ -154,41 +200,34 @@ __device__ __forceinline__ uint32_t wave_rank(uint32_t d, bool valid, int nbits,
     return base + below;
 }
 
-// Turns per-wave digit counts whist[w * nbins_stride + d] into per-wave
-// exclusive offsets inside the tile: texcl[d] = rows of smaller digits,
-// whist[w][d] = rows of digit d in waves before w; tcount[d] = rows of digit d.
+// Per-wave digit counters live in LDS as cnt[w * (BINS + 1) + d]; the padding
+// word spreads both a wave's random digits and the column walk below across
+// banks. scan_counts turns them, by one block-wide exclusive scan in
+// (digit, wave) order, into offsets inside the tile:
+//   cnt[w][d] = rows with a smaller digit + rows of digit d in earlier waves.
 // Returns the tile's row total. Ends with a barrier.
-template <int NT, int NBINS>
-__device__ __forceinline__ uint32_t tile_scan(uint32_t* whist, uint32_t* tcount, uint32_t* texcl,
-                                              uint32_t* tmp)
+template <int NT, int NW, int BINS>
+__device__ __forceinline__ uint32_t scan_counts(uint32_t* cnt, uint32_t* tmp)
 {
-    constexpr int NW = NT / 64;
-    constexpr int DPT = (NBINS + NT - 1) / NT;
-    uint32_t sums[DPT];
-    uint32_t local = 0;
+    constexpr int STRIDE = BINS + 1;
+    constexpr int E = BINS * NW;
+    constexpr int EPT = E / NT;
+    static_assert(E % NT == 0, "counter matrix must split evenly over the block");
+    uint32_t v[EPT];
+    uint32_t s = 0;
 #pragma unroll
-    for (int i = 0; i < DPT; i++) {
-        const int d = threadIdx.x * DPT + i;
-        uint32_t s = 0;
-        if (d < NBINS) {
-#pragma unroll
-            for (int w = 0; w < NW; w++) {
-                const uint32_t v = whist[w * NBINS + d];
-                whist[w * NBINS + d] = s;
-                s += v;
-            }
-            tcount[d] = s;
-        }
-        sums[i] = s;
-        local += s;
+    for (int i = 0; i < EPT; i++) {
+        const int e = threadIdx.x * EPT + i;
+        v[i] = cnt[(e % NW) * STRIDE + e / NW];
+        s += v[i];
     }
     uint32_t tot;
-    uint32_t ex = block_excl_scan<NT>(local, tmp, &tot);
+    uint32_t ex = block_excl_scan<NT>(s, tmp, &tot);
 #pragma unroll
-    for (int i = 0; i < DPT; i++) {
-        const int d = threadIdx.x * DPT + i;
-        if (d < NBINS) texcl[d] = ex;
-        ex += sums[i];
+    for (int i = 0; i < EPT; i++) {
+        const int e = threadIdx.x * EPT + i;
+        cnt[(e % NW) * STRIDE + e / NW] = ex;
+        ex += v[i];
     }
     __syncthreads();
     return tot;
@@ -311,8 +350,13 @@ __global__ __launch_bounds__(PART_THREADS) void k_hist(const ChunkDesc* __restri
         mx[d] = 0;
     }
     __syncthreads();
+    // Rows are counted with LDS atomics. When every valid row of a wave's round
+    // falls in one bin (skewed inputs: buckets dominated by one key), the wave
+    // reduces them first and one lane updates the bin.
     constexpr int U = 4;
-    for (uint32_t q0 = threadIdx.x; q0 < ch.len; q0 += PART_THREADS * U) {
+    const uint32_t lane = threadIdx.x & 63;
+    for (uint32_t b0 = 0; b0 < ch.len; b0 += PART_THREADS * U) {  // trip count uniform over the block
+        const uint32_t q0 = b0 + threadIdx.x;
         K k[U];
 #pragma unroll
         for (int u = 0; u < U; u++) {
@@ -323,8 +367,21 @@ __global__ __launch_bounds__(PART_THREADS) void k_hist(const ChunkDesc* __restri
         for (int u = 0; u < U; u++) {
             const uint32_t q = q0 + u * PART_THREADS;
             const uint64_t o = ord_of(k[u]);
-            if (q < ch.len && o >= g.flo && o <= g.fhi) {
-                const uint32_t d = (uint32_t)((o - g.base) >> g.shift) & (nbins - 1u);
+            const bool valid = q < ch.len && o >= g.flo && o <= g.fhi;
+            const uint32_t d = valid ? (uint32_t)((o - g.base) >> g.shift) & (nbins - 1u) : 0u;
+            const uint64_t vm = ballot(valid);
+            if (vm == 0) continue;
+            const int first = __ffsll((unsigned long long)vm) - 1;
+            const uint32_t d0 = (uint32_t)__shfl((int)d, first, 64);
+            if (ballot(valid && d != d0) == 0) {
+                const uint64_t lo = wave_min64(valid ? o : ~0ull);
+                const uint64_t hi = wave_max64(valid ? o : 0ull);
+                if ((int)lane == first) {
+                    atomicAdd(&cnt[d0], (uint32_t)__popcll(vm));
+                    atomicMin((unsigned long long*)&mn[d0], (unsigned long long)lo);
+                    atomicMax((unsigned long long*)&mx[d0], (unsigned long long)hi);
+                }
+            } else if (valid) {
                 atomicAdd(&cnt[d], 1u);
                 atomicMin((unsigned long long*)&mn[d], (unsigned long long)o);
                 atomicMax((unsigned long long*)&mx[d], (unsigned long long)o);
@@ -427,6 +484,40 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_l2(const GroupDesc* __res
     }
 }
 
+// one block per segment, one thread per digit
+__global__ __launch_bounds__(NB) void k_children(const GroupDesc* __restrict__ groups, int nside,
+                                                 const uint32_t* __restrict__ ccount,
+                                                 const uint64_t* __restrict__ gmin,
+                                                 const uint64_t* __restrict__ gmax,
+                                                 ChildRec* __restrict__ out)
+{
+    const GroupDesc g0 = groups[blockIdx.x * nside];
+    const uint32_t d = threadIdx.x;
+    if (d >= (1u << g0.bits)) return;
+    ChildRec c;
+    c.rn = ccount[g0.child0 + d];
+    c.lo = gmin[g0.child0 + d];
+    c.hi = gmax[g0.child0 + d];
+    c.sn = 0;
+    if (nside == 2) {
+        const uint32_t c1 = groups[blockIdx.x * 2 + 1].child0 + d;
+        c.sn = ccount[c1];
+        c.lo = gmin[c1] < c.lo ? gmin[c1] : c.lo;
+        c.hi = gmax[c1] > c.hi ? gmax[c1] : c.hi;
+    }
+    out[g0.child0 / nside + d] = c;
+}
+
+hipError_t launch_children(const GroupDesc* groups, uint32_t ngroups, int nside,
+                           const uint32_t* ccount, const uint64_t* gmin, const uint64_t* gmax,
+                           ChildRec* out, hipStream_t st)
+{
+    if (ngroups == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_children, dim3(ngroups / nside), dim3(NB), 0, st, groups, nside, ccount, gmin,
+                       gmax, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_scan(const CBlockDesc* cblocks, uint32_t ncblocks, const GroupDesc* groups,
                        uint32_t ngroups, uint32_t* hist, uint32_t* cbsum, uint32_t* ccount,
                        uint64_t* cstart, hipStream_t st)
@@ -441,28 +532,31 @@ hipError_t launch_scan(const CBlockDesc* cblocks, uint32_t ncblocks, const Group
 
 // ---------------------------------------------------------------------------
 // stable LDS-staged scatter. Each block walks its chunk in tiles of
-// PART_TILE rows. Per tile: rows are loaded coalesced, ranked within their
-// wave by ballot match, offset across waves and digits (tile_scan), staged in
-// LDS grouped by digit, and then written out as per-digit runs.
-// Wave w of the tile owns rows [w*ITEMS*64, (w+1)*ITEMS*64); round r of a wave
-// covers 64 consecutive rows, so (wave, round, lane) is input order and the
-// partition is stable.
+// SC_TILE rows. Per tile: rows are ranked within their wave by ballot match,
+// offset across waves and digits by one block scan, staged in LDS grouped by
+// digit, and written out as per-digit runs while the next tile's loads are in
+// flight. Wave w of the tile owns rows [w*SC_KI*64, (w+1)*SC_KI*64); round r
+// of a wave covers 64 consecutive rows, so (wave, round, lane) is input order
+// and the partition is stable.
 // ---------------------------------------------------------------------------
+constexpr int SC_NT = 512, SC_KI = 8, SC_NW = SC_NT / 64, SC_TILE = SC_NT * SC_KI;
+constexpr int SC_STRIDE = NB + 1;
+static_assert(SC_TILE == PART_TILE, "chunk sizes are planned in scatter tiles");
+
 template <typename K, bool RIDS, bool WKEYS>
-__global__ __launch_bounds__(PART_THREADS) void k_scatter(const ChunkDesc* __restrict__ chunks,
-                                                          const GroupDesc* __restrict__ groups,
-                                                          const uint32_t* __restrict__ hist,
-                                                          const uint32_t* __restrict__ cbsum,
-                                                          const uint64_t* __restrict__ cstart,
-                                                          BufSet bufs)
+__global__ __launch_bounds__(SC_NT) void k_scatter(const ChunkDesc* __restrict__ chunks,
+                                                   const GroupDesc* __restrict__ groups,
+                                                   const uint32_t* __restrict__ hist,
+                                                   const uint32_t* __restrict__ cbsum,
+                                                   const uint64_t* __restrict__ cstart,
+                                                   BufSet bufs)
 {
-    constexpr int NT = PART_THREADS, KI = PART_ITEMS, NW = NT / 64, TILE = PART_TILE;
-    __shared__ uint32_t whist[NW * NB];
-    __shared__ uint32_t tcount[NB], texcl[NB], run[NB];
+    constexpr int NT = SC_NT, KI = SC_KI, NW = SC_NW, TILE = SC_TILE;
+    __shared__ uint32_t cnt[NW * SC_STRIDE];
+    __shared__ uint32_t run[NB], delta[NB];
     __shared__ uint32_t tmp[NW];
     __shared__ K skey[TILE];
     __shared__ int32_t srid[RIDS ? TILE : 1];
-    __shared__ uint16_t sdig[TILE];
 
     const ChunkDesc ch = chunks[blockIdx.x];
     const GroupDesc g = groups[ch.group];
@@ -470,55 +564,68 @@ __global__ __launch_bounds__(PART_THREADS) void k_scatter(const ChunkDesc* __res
     const int32_t* __restrict__ src_r = bufs.rid[g.src][g.side] + ch.start;
     K* __restrict__ dst_k = (K*)bufs.key[g.dst][g.side];
     int32_t* __restrict__ dst_r = (int32_t*)bufs.rid[g.dst][g.side];
-    const uint32_t nbins = 1u << g.bits;
+    const uint32_t nbins = 1u << g.bits, mask = nbins - 1u;
     const uint32_t w = threadIdx.x / 64, l = threadIdx.x & 63;
 
     for (uint32_t d = threadIdx.x; d < NB; d += NT)
         run[d] = d < nbins ? (uint32_t)(cstart[g.child0 + d] + cbsum[(uint64_t)ch.cblock * NB + d] +
                                         hist[(uint64_t)blockIdx.x * NB + d])
                            : 0u;
+    K key[KI];
+    int32_t rid[KI];
+#pragma unroll
+    for (int r = 0; r < KI; r++) {
+        const uint32_t q = (w * KI + r) * 64 + l;
+        key[r] = q < ch.len ? src_k[q] : K(0);
+        if (RIDS) rid[r] = q < ch.len ? src_r[q] : 0;
+    }
     for (uint32_t t0 = 0; t0 < ch.len; t0 += TILE) {
-        K key[KI];
-        int32_t rid[KI];
         uint32_t dig[KI], rk[KI];
         bool val[KI];
 #pragma unroll
         for (int r = 0; r < KI; r++) {
             const uint32_t q = t0 + (w * KI + r) * 64 + l;
-            val[r] = q < ch.len;
-            key[r] = val[r] ? src_k[q] : K(0);
-            if (RIDS) rid[r] = val[r] ? src_r[q] : 0;
-        }
-#pragma unroll
-        for (int r = 0; r < KI; r++) {
             const uint64_t o = ord_of(key[r]);
-            val[r] = val[r] && o >= g.flo && o <= g.fhi;
-            dig[r] = val[r] ? (uint32_t)((o - g.base) >> g.shift) & (nbins - 1u) : 0u;
+            val[r] = q < ch.len && o >= g.flo && o <= g.fhi;
+            dig[r] = val[r] ? (uint32_t)((o - g.base) >> g.shift) & mask : 0u;
         }
-        for (uint32_t i = l; i < NB; i += 64) whist[w * NB + i] = 0;
+        for (uint32_t i = l; i < NB; i += 64) cnt[w * SC_STRIDE + i] = 0;
 #pragma unroll
-        for (int r = 0; r < KI; r++) rk[r] = wave_rank(dig[r], val[r], (int)g.bits, &whist[w * NB]);
+        for (int r = 0; r < KI; r++) rk[r] = wave_rank(dig[r], val[r], (int)g.bits, &cnt[w * SC_STRIDE]);
         __syncthreads();
-        const uint32_t nvalid = tile_scan<NT, NB>(whist, tcount, texcl, tmp);
+        const uint32_t total = scan_counts<NT, NW, NB>(cnt, tmp);
+        for (uint32_t d = threadIdx.x; d < NB; d += NT) {
+            const uint32_t tex = cnt[d];
+            const uint32_t nxt = d + 1 < NB ? cnt[d + 1] : total;
+            delta[d] = run[d] - tex;
+            run[d] += nxt - tex;
+        }
 #pragma unroll
         for (int r = 0; r < KI; r++) {
             if (val[r]) {
-                const uint32_t d = dig[r];
-                const uint32_t p = texcl[d] + whist[w * NB + d] + rk[r];
+                const uint32_t p = cnt[w * SC_STRIDE + dig[r]] + rk[r];
                 skey[p] = key[r];
                 if (RIDS) srid[p] = rid[r];
-                sdig[p] = (uint16_t)d;
             }
         }
         __syncthreads();
-        for (uint32_t p = threadIdx.x; p < nvalid; p += NT) {
-            const uint32_t d = sdig[p];
-            const uint32_t dst = run[d] + (p - texcl[d]);
-            if (WKEYS) dst_k[dst] = skey[p];
+        // next tile's loads overlap the write-out of this one
+        const uint32_t n0 = t0 + TILE;
+        if (n0 < ch.len) {
+#pragma unroll
+            for (int r = 0; r < KI; r++) {
+                const uint32_t q = n0 + (w * KI + r) * 64 + l;
+                key[r] = q < ch.len ? src_k[q] : K(0);
+                if (RIDS) rid[r] = q < ch.len ? src_r[q] : 0;
+            }
+        }
+        for (uint32_t p = threadIdx.x; p < total; p += NT) {
+            const K k = skey[p];
+            const uint32_t d = (uint32_t)((ord_of(k) - g.base) >> g.shift) & mask;
+            const uint32_t dst = delta[d] + p;
+            if (WKEYS) dst_k[dst] = k;
             if (RIDS) dst_r[dst] = srid[p];
         }
-        __syncthreads();
-        for (uint32_t d = threadIdx.x; d < NB; d += NT) run[d] += tcount[d];
         __syncthreads();
     }
 }
@@ -528,7 +635,7 @@ hipError_t launch_scatter(int key_bytes, bool rids, bool keys, const ChunkDesc* 
                           const uint64_t* cstart, BufSet bufs, hipStream_t st)
 {
     if (nchunks == 0) return hipSuccess;
-    const dim3 grid(nchunks), block(PART_THREADS);
+    const dim3 grid(nchunks), block(SC_NT);
 #define TJ_SC(K, R, W)                                                                               \
     hipLaunchKernelGGL((k_scatter<K, R, W>), grid, block, 0, st, chunks, groups, hist, cbsum, cstart, bufs)
     if (key_bytes == 4) {
@@ -574,12 +681,22 @@ hipError_t launch_expand(int32_t* dst, const int32_t* src, uint64_t n, uint64_t 
 // On return the sorted items are in lds_key / lds_idx. Padding items carry
 // the all-ones key and the largest positions, so they sort last.
 // ---------------------------------------------------------------------------
+constexpr int LBINS = 256, LSTRIDE = LBINS + 1;
+// Leaf block shape per key word: 32-bit keys use 512 threads x 16 rows (57 KB
+// of LDS, two blocks per CU); 64-bit keys 1024 threads x 8 rows (97 KB, one
+// block of 16 waves per CU).
+template <typename KW> struct LeafShape {
+    static constexpr int NT = sizeof(KW) == 4 ? 512 : 1024;
+    static constexpr int KI = LEAF_CAP / NT;
+    static constexpr int NW = NT / 64;
+};
+
 template <typename KW, int NT, int KI>
 __device__ __forceinline__ void block_lsd_sort(KW (&key)[KI], uint16_t (&idx)[KI], int bits,
-                                               KW* lds_key, uint16_t* lds_idx, uint32_t* whist,
-                                               uint32_t* tcount, uint32_t* texcl, uint32_t* tmp)
+                                               KW* lds_key, uint16_t* lds_idx, uint32_t* cnt,
+                                               uint32_t* tmp)
 {
-    constexpr int NBL = 256;
+    constexpr int NW = NT / 64;
     const uint32_t w = threadIdx.x / 64, l = threadIdx.x & 63;
     const int passes = (bits + 7) / 8;
     if (passes == 0) {
@@ -599,15 +716,14 @@ __device__ __forceinline__ void block_lsd_sort(KW (&key)[KI], uint16_t (&idx)[KI
         uint32_t dig[KI], rk[KI];
 #pragma unroll
         for (int r = 0; r < KI; r++) dig[r] = (uint32_t)(key[r] >> sh) & mask;
-        for (uint32_t i = l; i < NBL; i += 64) whist[w * NBL + i] = 0;
+        for (uint32_t i = l; i < LBINS; i += 64) cnt[w * LSTRIDE + i] = 0;
 #pragma unroll
-        for (int r = 0; r < KI; r++) rk[r] = wave_rank(dig[r], true, nb, &whist[w * NBL]);
+        for (int r = 0; r < KI; r++) rk[r] = wave_rank(dig[r], true, nb, &cnt[w * LSTRIDE]);
         __syncthreads();
-        tile_scan<NT, NBL>(whist, tcount, texcl, tmp);
+        scan_counts<NT, NW, LBINS>(cnt, tmp);
 #pragma unroll
         for (int r = 0; r < KI; r++) {
-            const uint32_t d = dig[r];
-            const uint32_t pos = texcl[d] + whist[w * NBL + d] + rk[r];
+            const uint32_t pos = cnt[w * LSTRIDE + dig[r]] + rk[r];
             lds_key[pos] = key[r];
             lds_idx[pos] = idx[r];
         }
@@ -623,20 +739,17 @@ __device__ __forceinline__ void block_lsd_sort(KW (&key)[KI], uint16_t (&idx)[KI
     }
 }
 
-constexpr int LEAF_NW = LEAF_THREADS / 64;
-constexpr size_t LEAF_SCRATCH = (size_t)LEAF_NW * 256 * 4 + 2 * 256 * 4 + 64 * 8;
-
 template <typename K, typename KW>
-__global__ __launch_bounds__(LEAF_THREADS) void k_leaf_sort(const LeafDesc* __restrict__ leaves,
+__global__ __launch_bounds__(LeafShape<KW>::NT)
+__attribute__((amdgpu_waves_per_eu(4))) void k_leaf_sort(const LeafDesc* __restrict__ leaves,
                                                             BufSet bufs, K* __restrict__ out_k,
                                                             int32_t* __restrict__ out_r)
 {
-    constexpr int NT = LEAF_THREADS, KI = LEAF_ITEMS, C = LEAF_CAP;
+    constexpr int NT = LeafShape<KW>::NT, KI = LeafShape<KW>::KI, NW = LeafShape<KW>::NW, C = LEAF_CAP;
     __shared__ KW lds_key[C];
     __shared__ uint16_t lds_idx[C];
-    __shared__ int32_t lds_rid[C];
-    __shared__ uint32_t whist[LEAF_NW * 256];
-    __shared__ uint32_t tcount[256], texcl[256], tmp[LEAF_NW];
+    __shared__ uint32_t cnt[NW * LSTRIDE];
+    __shared__ uint32_t tmp[NW];
 
     const LeafDesc L = leaves[blockIdx.x];
     const K* __restrict__ src_k = (const K*)bufs.key[L.buf][0] + L.r0;
@@ -647,22 +760,26 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_leaf_sort(const LeafDesc* __re
 #pragma unroll
     for (int r = 0; r < KI; r++) {
         const uint32_t q = (w * KI + r) * 64 + l;
-        if (q < L.rn) {
-            key[r] = (KW)(ord_of(src_k[q]) - L.base);
-            lds_rid[q] = src_r[q];
-        } else {
-            key[r] = (KW)~(KW)0;
-        }
+        key[r] = q < L.rn ? (KW)(ord_of(src_k[q]) - L.base) : (KW)~(KW)0;
         idx[r] = (uint16_t)q;
     }
-    block_lsd_sort<KW, NT, KI>(key, idx, (int)L.bits, lds_key, lds_idx, whist, tcount, texcl, tmp);
+    block_lsd_sort<KW, NT, KI>(key, idx, (int)L.bits, lds_key, lds_idx, cnt, tmp);
+    // Keys go out first. The bucket may be sorted in place (its rows already
+    // sit in the output columns), so its row ids are all read (coalesced, into
+    // the now free key array) before any of them is overwritten.
 #pragma unroll
     for (int r = 0; r < KI; r++) {
         const uint32_t q = (w * KI + r) * 64 + l;
-        if (q < L.rn) {
-            out_k[L.out + q] = key_of<K>(L.base + (uint64_t)lds_key[q]);
-            out_r[L.out + q] = lds_rid[lds_idx[q]];
-        }
+        if (q < L.rn) out_k[L.out + q] = key_of<K>(L.base + (uint64_t)lds_key[q]);
+    }
+    __syncthreads();
+    int32_t* lds_rid = (int32_t*)lds_key;
+    for (uint32_t q = threadIdx.x; q < L.rn; q += NT) lds_rid[q] = src_r[q];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < KI; r++) {
+        const uint32_t q = (w * KI + r) * 64 + l;
+        if (q < L.rn) out_r[L.out + q] = lds_rid[lds_idx[q]];
     }
 }
 
@@ -670,7 +787,7 @@ hipError_t launch_leaf_sort(int key_bytes, bool wide, const LeafDesc* leaves, ui
                             BufSet bufs, void* out_k, int32_t* out_r, hipStream_t st)
 {
     if (n == 0) return hipSuccess;
-    const dim3 grid(n), block(LEAF_THREADS);
+    const dim3 grid(n), block(wide ? LeafShape<uint64_t>::NT : LeafShape<uint32_t>::NT);
     if (key_bytes == 4) {
         if (wide)
             hipLaunchKernelGGL((k_leaf_sort<int32_t, uint64_t>), grid, block, 0, st, leaves, bufs, (int32_t*)out_k, out_r);
@@ -692,16 +809,16 @@ hipError_t launch_leaf_sort(int key_bytes, bool wide, const LeafDesc* leaves, ui
 // order]. A run with a R rows and b S rows contributes a*b pairs; R row i of
 // the run owns the b consecutive output slots of its pairs, so the output is
 // key-ascending, R-major, S in input order.
+//
+// Count mode adds the block's pair count to *total. Materialise mode takes a
+// ticket (so blocks handle buckets in key order), publishes its pair count,
+// and finds its output offset by decoupled look-back over the published
+// counts of the buckets before it; status[0] holds the offset carried in.
+// Pairs at or beyond `capacity` are not written.
 // ---------------------------------------------------------------------------
-template <typename KW>
-__device__ __forceinline__ uint32_t lds_lower_bound(const KW* a, uint32_t lo, uint32_t hi, KW k)
-{
-    while (lo < hi) {
-        const uint32_t m = (lo + hi) >> 1;
-        if (a[m] < k) lo = m + 1; else hi = m;
-    }
-    return lo;
-}
+constexpr uint64_t ST_AGG = 1ull << 62, ST_INC = 2ull << 62, ST_VAL = (1ull << 62) - 1;
+constexpr uint64_t LOOKBACK_SPIN_LIMIT = 1ull << 22;
+constexpr uint32_t COOP_PAIRS = 16;  // R rows with more pairs are written by their whole wave
 
 template <typename KW>
 __device__ __forceinline__ uint32_t lds_upper_bound(const KW* a, uint32_t lo, uint32_t hi, KW k)
@@ -713,29 +830,81 @@ __device__ __forceinline__ uint32_t lds_upper_bound(const KW* a, uint32_t lo, ui
     return lo;
 }
 
-template <typename K, typename KW, bool MAT>
-__global__ __launch_bounds__(LEAF_THREADS) void k_leaf_join(const LeafDesc* __restrict__ leaves,
-                                                            BufSet bufs, uint64_t* __restrict__ counts,
-                                                            int32_t* __restrict__ out_r,
-                                                            int32_t* __restrict__ out_s)
+__device__ __forceinline__ void status_store(uint64_t* p, uint64_t v)
 {
-    constexpr int NT = LEAF_THREADS, KI = LEAF_ITEMS, C = LEAF_CAP;
-    // key array; after the run analysis its storage holds s0 (and, when KW is
-    // 64-bit, the pair offsets E as well)
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t status_load(const uint64_t* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Exclusive prefix of bucket `slot - 1` (slot >= 1), computed by one whole
+// wave: lane i reads status[hi - i] for a window of 64 predecessors. The window
+// is summed from its newest entry down to the nearest inclusive prefix; if the
+// window holds only aggregates it is summed whole and the walk moves 64 slots
+// back. A window is re-read while any entry it needs is unpublished. Every
+// predecessor already holds its ticket, so it is running or done and will
+// publish; the spin is bounded all the same, and on expiry *err is set and 0
+// returned. status[0] is always an inclusive prefix, so the walk ends.
+__device__ uint64_t look_back(uint64_t* status, uint32_t slot, uint32_t* err)
+{
+    const uint32_t l = lane_id();
+    uint64_t sum = 0, spins = 0;
+    int64_t hi = (int64_t)slot - 1;
+    while (true) {
+        const int64_t j = hi - (int64_t)l;
+        const uint64_t s = j >= 0 ? status_load(&status[j]) : 0;
+        const uint64_t f = s & ~ST_VAL;
+        const uint64_t inc = ballot(j >= 0 && f == ST_INC);
+        const uint64_t pending = ballot(j >= 0 && f == 0);
+        const int first = inc ? __ffsll((unsigned long long)inc) - 1 : 64;
+        const uint64_t need = first >= 63 ? ~0ull : ((2ull << first) - 1);
+        if (pending & need) {
+            if (++spins > LOOKBACK_SPIN_LIMIT) {
+                if (l == 0) atomicOr(err, 1u);
+                return 0;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        sum += wave_sum64(((need >> l) & 1ull) && j >= 0 ? (s & ST_VAL) : 0ull);
+        if (first < 64) return sum;
+        hi -= 64;
+    }
+}
+
+template <typename K, typename KW, bool MAT>
+__global__ __launch_bounds__(LeafShape<KW>::NT)
+__attribute__((amdgpu_waves_per_eu(4))) void k_leaf_join(const LeafDesc* __restrict__ leaves,
+                                                            BufSet bufs, uint64_t* __restrict__ status,
+                                                            uint32_t* __restrict__ ticket,
+                                                            uint64_t* __restrict__ total,
+                                                            uint32_t* __restrict__ err,
+                                                            int32_t* __restrict__ out_r,
+                                                            int32_t* __restrict__ out_s,
+                                                            uint64_t capacity)
+{
+    constexpr int NT = LeafShape<KW>::NT, KI = LeafShape<KW>::KI, NW = LeafShape<KW>::NW, C = LEAF_CAP;
     __shared__ KW lds_key[C];
     __shared__ uint16_t lds_idx[C];
-    __shared__ int32_t lds_rid[MAT ? C : 1];
-    __shared__ uint32_t lds_e_own[(MAT && sizeof(KW) == 4) ? C : 1];
-    __shared__ uint32_t whist[LEAF_NW * 256];
-    __shared__ uint32_t tcount[256], texcl[256], tmp[LEAF_NW];
-    __shared__ uint64_t tmp64[LEAF_NW];
+    __shared__ uint32_t cnt[NW * LSTRIDE];
+    __shared__ uint32_t tmp[NW];
+    __shared__ uint64_t tmp64[NW];
+    __shared__ uint32_t s_leaf;
+    __shared__ uint64_t s_base;
 
-    const LeafDesc L = leaves[blockIdx.x];
-    const uint32_t n = L.rn + L.sn;
+    uint32_t li = blockIdx.x;
+    if (MAT) {
+        if (threadIdx.x == 0) s_leaf = atomicAdd(ticket, 1u);
+        __syncthreads();
+        li = s_leaf;
+    }
+    const LeafDesc L = leaves[li];
+    const uint32_t rn = L.rn, n = L.rn + L.sn;
     const K* __restrict__ rk = (const K*)bufs.key[L.buf][0] + L.r0;
     const K* __restrict__ sk = (const K*)bufs.key[L.buf][1] + L.s0;
-    const int32_t* __restrict__ rr = bufs.rid[L.buf][0] + L.r0;
-    const int32_t* __restrict__ sr = bufs.rid[L.buf][1] + L.s0;
     const uint32_t w = threadIdx.x / 64, l = threadIdx.x & 63;
 
     KW key[KI];
@@ -743,90 +912,196 @@ __global__ __launch_bounds__(LEAF_THREADS) void k_leaf_join(const LeafDesc* __re
 #pragma unroll
     for (int r = 0; r < KI; r++) {
         const uint32_t q = (w * KI + r) * 64 + l;
-        if (q < L.rn) {
-            key[r] = (KW)(ord_of(rk[q]) - L.base);
-            if (MAT) lds_rid[q] = rr[q];
-        } else if (q < n) {
-            key[r] = (KW)(ord_of(sk[q - L.rn]) - L.base);
-            if (MAT) lds_rid[q] = sr[q - L.rn];
-        } else {
-            key[r] = (KW)~(KW)0;
-        }
+        if (q < rn) key[r] = (KW)(ord_of(rk[q]) - L.base);
+        else if (q < n) key[r] = (KW)(ord_of(sk[q - rn]) - L.base);
+        else key[r] = (KW)~(KW)0;
         idx[r] = (uint16_t)q;
     }
-    block_lsd_sort<KW, NT, KI>(key, idx, (int)L.bits, lds_key, lds_idx, whist, tcount, texcl, tmp);
+    block_lsd_sort<KW, NT, KI>(key, idx, (int)L.bits, lds_key, lds_idx, cnt, tmp);
 
-    if (!MAT) {
-        uint64_t c = 0;
-        for (uint32_t p = threadIdx.x; p < n; p += NT) {
-            if (lds_idx[p] >= L.rn) continue;
-            const KW k = lds_key[p];
-            const bool last_r = p + 1 == n || lds_idx[p + 1] >= L.rn || lds_key[p + 1] != k;
-            if (!last_r) continue;
-            const uint32_t lo = lds_lower_bound<KW>(lds_key, 0, p, k);
-            const uint32_t e = lds_upper_bound<KW>(lds_key, p + 1, n, k);
-            c += (uint64_t)(p + 1 - lo) * (uint64_t)(e - (p + 1));
-        }
-        c = block_sum64<NT>(c, tmp64);
-        if (threadIdx.x == 0) counts[blockIdx.x] = c;
-        return;
+    // Run analysis on blocked positions p = tid*KI + i. A run is a maximal
+    // stretch of equal keys: [rs, s0) holds its a R items, [s0, re) its b S
+    // items. rs comes from a block-wide max-scan of run starts; s0 and re are
+    // written, indexed by rs, by the run's last R item (or its first item when
+    // the run has no R item) and by its last item.
+    const uint32_t p0 = threadIdx.x * KI;
+    KW kk[KI];
+    uint32_t id[KI];
+#pragma unroll
+    for (int i = 0; i < KI; i++) {
+        kk[i] = lds_key[p0 + i];
+        id[i] = lds_idx[p0 + i];
     }
-
-    // Materialise. Phase A: for each R item, the S part of its run [s0, e).
-    uint32_t bcnt[KI], s0v[KI];
+    const KW kprev = p0 ? lds_key[p0 - 1] : (KW)0;
+    const KW knext = p0 + KI < C ? lds_key[p0 + KI] : (KW)0;
+    const uint32_t inext = p0 + KI < C ? lds_idx[p0 + KI] : 0xffffu;
+    uint32_t rs[KI];
+    uint32_t run_start = 0;
+#pragma unroll
+    for (int i = 0; i < KI; i++) {
+        const uint32_t p = p0 + i;
+        const bool start = p == 0 || p >= n || kk[i] != (i ? kk[i - 1] : kprev);
+        run_start = start ? p : run_start;
+        rs[i] = run_start;
+    }
+    {
+        const uint32_t carry = block_excl_max<NT>(run_start, tmp);  // barriers: keys all read
+#pragma unroll
+        for (int i = 0; i < KI; i++) rs[i] = max(rs[i], carry);
+    }
+    uint16_t* run_s0 = (uint16_t*)lds_key;   // the key array is free from here on
+    uint16_t* run_end = run_s0 + C;
+#pragma unroll
+    for (int i = 0; i < KI; i++) {
+        const uint32_t p = p0 + i;
+        if (p >= n) continue;
+        const bool last = p == n - 1 || (i + 1 < KI ? kk[i + 1] : knext) != kk[i];
+        const uint32_t idn = i + 1 < KI ? id[i + 1] : inext;
+        const bool isr = id[i] < rn;
+        if (last) run_end[rs[i]] = (uint16_t)(p + 1);
+        if (isr && (last || idn >= rn)) run_s0[rs[i]] = (uint16_t)(p + 1);   // last R item
+        if (!isr && p == rs[i]) run_s0[rs[i]] = (uint16_t)p;                  // run without R items
+    }
+    __syncthreads();
+    // per item, packed: [is R:1][a:14][b:14], a = R items and b = S items of its
+    // run (0 for padding); kv = position of the item inside the run's S part
+    uint32_t abv[KI], kv[KI];
     uint32_t local = 0;
 #pragma unroll
     for (int i = 0; i < KI; i++) {
-        const uint32_t p = threadIdx.x * KI + i;
-        bcnt[i] = 0;
-        s0v[i] = 0;
-        if (p < n && lds_idx[p] < L.rn) {
-            const KW k = lds_key[p];
-            const uint32_t e = lds_upper_bound<KW>(lds_key, p + 1, n, k);
-            // first S item of the run: S items follow the run's R items
-            uint32_t lo = p + 1, hi = e;
-            while (lo < hi) {
-                const uint32_t m = (lo + hi) >> 1;
-                if (lds_idx[m] < L.rn) lo = m + 1; else hi = m;
-            }
-            s0v[i] = lo;
-            bcnt[i] = e - lo;
+        abv[i] = 0;
+        kv[i] = 0;
+        if (p0 + i < n) {
+            const uint32_t s0 = run_s0[rs[i]], re = run_end[rs[i]];
+            const uint32_t a = s0 - rs[i], b = re - s0;
+            const bool isr = id[i] < rn;
+            abv[i] = (isr ? 0x80000000u : 0u) | (a << 14) | b;
+            kv[i] = p0 + i - s0;
+            if (isr) local += b;  // an R item owns b pairs
         }
-        local += bcnt[i];
     }
-    uint32_t total;
-    uint32_t ex = block_excl_scan<NT>(local, tmp, &total);  // contains barriers: keys no longer read
-    uint32_t* lds_s0 = (uint32_t*)lds_key;
-    uint32_t* lds_e = sizeof(KW) == 4 ? lds_e_own : (uint32_t*)lds_key + C;
-#pragma unroll
-    for (int i = 0; i < KI; i++) {
-        const uint32_t p = threadIdx.x * KI + i;
-        lds_s0[p] = s0v[i];
-        lds_e[p] = ex;
-        ex += bcnt[i];
+    if (!MAT) {
+        const uint64_t c = block_sum64<NT>((uint64_t)local, tmp64);
+        if (threadIdx.x == 0 && c) atomicAdd((unsigned long long*)total, (unsigned long long)c);
+        return;
+    }
+    uint32_t ltot;
+    uint32_t ex = block_excl_scan<NT>(local, tmp, &ltot);  // barriers: run tables all read
+    if (threadIdx.x == 0) status_store(&status[li + 1], ST_AGG | (uint64_t)ltot);
+    // Row ids: one coalesced load of the block's rows (R then S) into the free
+    // key array, then every item picks its own from LDS.
+    int32_t* lds_w = (int32_t*)lds_key;
+    {
+        const int32_t* __restrict__ rr = bufs.rid[L.buf][0] + L.r0;
+        const int32_t* __restrict__ sr = bufs.rid[L.buf][1] + L.s0;
+        for (uint32_t q = threadIdx.x; q < n; q += NT) lds_w[q] = q < rn ? rr[q] : sr[q - rn];
+    }
+    if (threadIdx.x < 64) {
+        const uint64_t excl = look_back(status, li + 1, err);
+        if (threadIdx.x == 0) {
+            status_store(&status[li + 1], ST_INC | (excl + ltot));
+            s_base = excl + L.out;
+        }
     }
     __syncthreads();
-    for (uint32_t t = threadIdx.x; t < total; t += NT) {
-        // the R item owning pair t: the last position p < n with E[p] <= t
-        uint32_t lo = 0, hi = n;
-        while (hi - lo > 1) {
-            const uint32_t m = (lo + hi) >> 1;
-            if (lds_e[m] <= t) lo = m; else hi = m;
+    const uint64_t base = s_base;
+    // Pair slots: R item j of a run owns E_rs + j*b .. + b (it writes out_r),
+    // S item k of a run appears at E_rs + i*b + k for its run's a R items (it
+    // writes out_s). Per item: first slot, and packed [side:1][slots:14][stride:14].
+    uint32_t firstv[KI], packv[KI];
+    uint32_t maxslots = 0;
+    {
+        uint32_t e = ex;
+#pragma unroll
+        for (int i = 0; i < KI; i++) {
+            const uint32_t ab = abv[i];
+            const bool isr = (ab >> 31) != 0;
+            const uint32_t a = (ab >> 14) & 0x3fffu, b = ab & 0x3fffu;
+            const uint32_t slots = isr ? b : (b ? a : 0u);
+            const uint32_t stride = isr ? 1u : b;
+            packv[i] = (isr ? 0x80000000u : 0u) | (slots << 14) | stride;
+            firstv[i] = isr ? e : e - a * b + kv[i];
+            maxslots = slots > maxslots ? slots : maxslots;
+            if (isr) e += b;
         }
-        const uint32_t j = t - lds_e[lo];
-        out_r[L.out + t] = lds_rid[lds_idx[lo]];
-        out_s[L.out + t] = lds_rid[lds_idx[lds_s0[lo] + j]];
+    }
+    maxslots = block_max<NT>(maxslots, tmp);
+    int32_t rid[KI];
+#pragma unroll
+    for (int i = 0; i < KI; i++) rid[i] = p0 + i < n ? lds_w[lds_idx[p0 + i]] : 0;
+    __syncthreads();  // the key array becomes the pair staging buffer
+    constexpr uint32_t OC = C / 2;  // pairs per staged chunk: two int32 columns in the key array
+    if (ltot <= 8 * OC && maxslots <= 64) {
+        // Staged: items scatter their slots of the chunk into LDS, then the chunk
+        // leaves as two coalesced runs.
+        int32_t* st_r = lds_w;
+        int32_t* st_s = lds_w + OC;
+        for (uint32_t c0 = 0; c0 < ltot; c0 += OC) {
+            const uint32_t c1 = c0 + OC;
+#pragma unroll
+            for (int i = 0; i < KI; i++) {
+                const uint32_t pk = packv[i];
+                const uint32_t sl = (pk >> 14) & 0x3fffu, stride = pk & 0x3fffu;
+                const uint32_t f = firstv[i];
+                int32_t* st = (pk >> 31) ? st_r : st_s;
+                for (uint32_t j = 0; j < sl; j++) {
+                    const uint32_t t = f + j * stride;
+                    if (t >= c0 && t < c1) st[t - c0] = rid[i];
+                }
+            }
+            __syncthreads();
+            const uint32_t cn = ltot - c0 < OC ? ltot - c0 : OC;
+            for (uint32_t t = threadIdx.x; t < cn; t += NT) {
+                const uint64_t o = base + c0 + t;
+                if (o < capacity) {
+                    out_r[o] = st_r[t];
+                    out_s[o] = st_s[t];
+                }
+            }
+            __syncthreads();
+        }
+        return;
+    }
+    // Very large outputs (hot keys inside the block): items write their own
+    // slots; items with many slots are written by their wave.
+#pragma unroll
+    for (int i = 0; i < KI; i++) {
+        const uint32_t pk = packv[i];
+        const uint32_t slots = (pk >> 14) & 0x3fffu, stride = pk & 0x3fffu, first = firstv[i];
+        int32_t* __restrict__ dst = (pk >> 31) ? out_r : out_s;
+        if (slots && slots <= COOP_PAIRS) {
+            for (uint32_t j = 0; j < slots; j++) {
+                const uint64_t t = base + first + (uint64_t)j * stride;
+                if (t < capacity) dst[t] = rid[i];
+            }
+        }
+        uint64_t m = ballot(slots > COOP_PAIRS);
+        while (m) {
+            const int src = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1;
+            const uint32_t cpk = __shfl(pk, src, 64);
+            const uint32_t cs = (cpk >> 14) & 0x3fffu, cst = cpk & 0x3fffu;
+            const uint32_t cf = __shfl(first, src, 64);
+            const int32_t cr = __shfl(rid[i], src, 64);
+            int32_t* __restrict__ cdst = (cpk >> 31) ? out_r : out_s;
+            for (uint32_t j = l; j < cs; j += 64) {
+                const uint64_t t = base + cf + (uint64_t)j * cst;
+                if (t < capacity) cdst[t] = cr;
+            }
+        }
     }
 }
 
 hipError_t launch_leaf_join(int key_bytes, bool wide, bool materialize, const LeafDesc* leaves,
-                            uint32_t n, BufSet bufs, uint64_t* counts, int32_t* out_r,
-                            int32_t* out_s, hipStream_t st)
+                            uint32_t n, BufSet bufs, uint64_t* status, uint32_t* ticket,
+                            uint64_t* total, uint32_t* err, int32_t* out_r, int32_t* out_s,
+                            uint64_t capacity, hipStream_t st)
 {
     if (n == 0) return hipSuccess;
-    const dim3 grid(n), block(LEAF_THREADS);
+    const dim3 grid(n), block(wide ? LeafShape<uint64_t>::NT : LeafShape<uint32_t>::NT);
 #define TJ_LJ(K, KW, M)                                                                              \
-    hipLaunchKernelGGL((k_leaf_join<K, KW, M>), grid, block, 0, st, leaves, bufs, counts, out_r, out_s)
+    hipLaunchKernelGGL((k_leaf_join<K, KW, M>), grid, block, 0, st, leaves, bufs, status, ticket,    \
+                       total, err, out_r, out_s, capacity)
     if (key_bytes == 4) {
         if (wide) { if (materialize) TJ_LJ(int32_t, uint64_t, true); else TJ_LJ(int32_t, uint64_t, false); }
         else      { if (materialize) TJ_LJ(int32_t, uint32_t, true); else TJ_LJ(int32_t, uint32_t, false); }
@@ -842,7 +1117,9 @@ hipError_t launch_leaf_join(int key_bytes, bool wide, bool materialize, const Le
 // single-key buckets of the join: pair t of a unit with a R rows and b S rows
 // is (R row t / b, S row t mod b); consecutive t are written by consecutive
 // threads (coalesced). Units are flattened into one sequence of pairs and
-// each block takes a fixed stretch of it.
+// each block takes a fixed stretch of it. A unit's output offset is the
+// inclusive pair prefix of the per-bucket joins before it (status, after the
+// materialising leaf launch) plus the pairs of earlier single-key units.
 // ---------------------------------------------------------------------------
 constexpr int CROSS_THREADS = 256;
 constexpr uint64_t CROSS_PER_BLOCK = 256 * 64;
@@ -861,8 +1138,10 @@ __device__ __forceinline__ uint32_t find_unit(const uint64_t* pfx_base, size_t s
 
 __global__ __launch_bounds__(CROSS_THREADS) void k_cross(const CrossDesc* __restrict__ units,
                                                          uint32_t n, uint64_t total, BufSet bufs,
+                                                         const uint64_t* __restrict__ status,
                                                          int32_t* __restrict__ out_r,
-                                                         int32_t* __restrict__ out_s)
+                                                         int32_t* __restrict__ out_s,
+                                                         uint64_t capacity)
 {
     const uint64_t t0 = blockIdx.x * CROSS_PER_BLOCK;
     uint64_t t1 = t0 + CROSS_PER_BLOCK;
@@ -873,25 +1152,32 @@ __global__ __launch_bounds__(CROSS_THREADS) void k_cross(const CrossDesc* __rest
     if (t >= t1) return;
     uint32_t u = find_unit(pfx, stride, n, t);
     CrossDesc U = units[u];
+    uint64_t base = U.out + (status[U.leaf_before] & ST_VAL);
     for (; t < t1; t += CROSS_THREADS) {
-        while (t >= U.pfx + U.a * U.b) U = units[++u];
+        while (t >= U.pfx + U.a * U.b) {
+            U = units[++u];
+            base = U.out + (status[U.leaf_before] & ST_VAL);
+        }
         const uint64_t loc = t - U.pfx;
         uint64_t i = (uint64_t)((double)loc / (double)U.b);
         while (i * U.b > loc) i--;
         while ((i + 1) * U.b <= loc) i++;
         const uint64_t j = loc - i * U.b;
-        out_r[U.out + loc] = bufs.rid[U.buf][0][U.r0 + i];
-        out_s[U.out + loc] = bufs.rid[U.buf][1][U.s0 + j];
+        if (base + loc < capacity) {
+            out_r[base + loc] = bufs.rid[U.buf][0][U.r0 + i];
+            out_s[base + loc] = bufs.rid[U.buf][1][U.s0 + j];
+        }
     }
 }
 
 hipError_t launch_cross(const CrossDesc* units, uint32_t n, uint64_t total, BufSet bufs,
-                        int32_t* out_r, int32_t* out_s, hipStream_t st)
+                        const uint64_t* status, int32_t* out_r, int32_t* out_s, uint64_t capacity,
+                        hipStream_t st)
 {
     if (n == 0 || total == 0) return hipSuccess;
     const uint64_t blocks = (total + CROSS_PER_BLOCK - 1) / CROSS_PER_BLOCK;
     hipLaunchKernelGGL(k_cross, dim3((uint32_t)blocks), dim3(CROSS_THREADS), 0, st, units, n, total,
-                       bufs, out_r, out_s);
+                       bufs, status, out_r, out_s, capacity);
     return hipGetLastError();
 }
 

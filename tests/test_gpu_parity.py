@@ -234,3 +234,33 @@ def test_budget_single_key_ranges(tj):
     exp_r, exp_s, cnt = oracle.join_pairs(rk2, rr, sk, sr)
     pr, ps = tj.join(dev(rk2), dev(rr), dev(sk), dev(sr), capacity=cnt, workspace_bytes=1 << 20)
     assert np.array_equal(host(pr), exp_r) and np.array_equal(host(ps), exp_s)
+
+
+# --------------------------------------------------------------------------- profiling hook
+
+def test_timing_hook_counts_launches(tj):
+    w = tjgen.paper_shaped(0.0, n=100_000)
+    rk, sk = dev(w["r_keys"]), dev(w["s_keys"])
+    tj.timing(True)
+    assert tj.join_count(rk, sk) == 80_000
+    tj.timing(False)
+    fams = tj.timing_read()
+    assert fams["probe"]["launches"] == 1
+    assert fams["leaf_join_count"]["launches"] >= 1 and fams["leaf_join_count"]["ms"] > 0
+    assert fams["leaf_join_count"]["bytes"] >= 8 * 200_000
+    tj.timing(True)  # re-enabling clears the counters
+    assert all(v["launches"] == 0 for v in tj.timing_read().values())
+    tj.timing(False)
+
+
+def test_skewed_buckets_dominated_by_one_key(tj):
+    # buckets where almost every row holds one key exercise the histogram's
+    # wave-uniform path and the single-key detection at every depth
+    rng = np.random.default_rng(17)
+    n = 300_000
+    k = np.where(rng.random(n) < 0.97, 1 << 35, rng.integers(0, 1 << 40, n)).astype(np.int64)
+    r = rng.permutation(n).astype(np.int32)
+    check_sort(tj, k, r)
+    sk = np.where(rng.random(n) < 0.9, 1 << 35, rng.integers(0, 1 << 40, n)).astype(np.int64)
+    rk = np.concatenate([np.full(3, 1 << 35), rng.integers(0, 1 << 40, 5000)]).astype(np.int64)
+    check_join(tj, rk, np.arange(rk.size, dtype=np.int32), sk, r)

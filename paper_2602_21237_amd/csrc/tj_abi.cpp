@@ -34,6 +34,11 @@ namespace {
 constexpr uint64_t ALIGN = 256;
 constexpr int TABLE_TIERS = 8;
 constexpr uint64_t TARGET_CHUNKS = 2048;  // blocks per partition pass
+#ifndef TJ_PASS_DIGIT_BITS
+#define TJ_PASS_DIGIT_BITS MAX_DIGIT_BITS
+#endif
+// widest digit a partition pass uses (at most MAX_DIGIT_BITS)
+constexpr int PASS_DIGIT_BITS = TJ_PASS_DIGIT_BITS;
 
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
@@ -320,7 +325,7 @@ struct Exec {
             const uint64_t rows = s.rn + s.sn;
             const uint32_t kbits = nbits64(s.hi - s.lo);
             uint32_t want = 1;
-            while (want < (uint32_t)MAX_DIGIT_BITS && (rows >> want) > (uint64_t)LEAF_CAP / 2) want++;
+            while (want < (uint32_t)PASS_DIGIT_BITS && (rows >> want) > (uint64_t)LEAF_CAP / 2) want++;
             uint32_t b = std::min<uint32_t>(want, kbits);
             if (b == 0) b = 1;  // filtered roots of a single-key range still need a compaction pass
             plan[i].bits = b;

@@ -694,7 +694,7 @@ template <typename KW> struct LeafShape {
 template <typename KW, int NT, int KI>
 __device__ __forceinline__ void block_lsd_sort(KW (&key)[KI], uint16_t (&idx)[KI], int bits,
                                                KW* lds_key, uint16_t* lds_idx, uint32_t* cnt,
-                                               uint32_t* tmp)
+                                               uint32_t* tmp, int lo_bit = 0)
 {
     constexpr int NW = NT / 64;
     const uint32_t w = threadIdx.x / 64, l = threadIdx.x & 63;
@@ -710,8 +710,8 @@ __device__ __forceinline__ void block_lsd_sort(KW (&key)[KI], uint16_t (&idx)[KI
         return;
     }
     for (int p = 0; p < passes; p++) {
-        const int sh = 8 * p;
-        const int nb = bits - sh < 8 ? bits - sh : 8;
+        const int sh = lo_bit + 8 * p;
+        const int nb = bits - 8 * p < 8 ? bits - 8 * p : 8;
         const uint32_t mask = (1u << nb) - 1u;
         uint32_t dig[KI], rk[KI];
 #pragma unroll
@@ -750,6 +750,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_leaf_sort(const LeafDesc* __restr
     __shared__ uint16_t lds_idx[C];
     __shared__ uint32_t cnt[NW * LSTRIDE];
     __shared__ uint32_t tmp[NW];
+    __shared__ uint64_t tmp64[NW];
 
     const LeafDesc L = leaves[blockIdx.x];
     const K* __restrict__ src_k = (const K*)bufs.key[L.buf][0] + L.r0;
@@ -763,7 +764,56 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_leaf_sort(const LeafDesc* __restr
         key[r] = q < L.rn ? (KW)(ord_of(src_k[q]) - L.base) : (KW)~(KW)0;
         idx[r] = (uint16_t)q;
     }
-    block_lsd_sort<KW, NT, KI>(key, idx, (int)L.bits, lds_key, lds_idx, cnt, tmp);
+    if (sizeof(KW) == 8 && L.bits > 32) {
+        // Wide keys: sort by the top 32 bits of the relative key only (4 digit
+        // passes instead of up to 8). The order is final unless two rows share
+        // those 32 bits; short runs of such ties are then put in order by one
+        // thread each (insertion sort on the full key, which keeps equal keys in
+        // input order); many ties fall back to the full sort.
+        const int H = (int)L.bits - 32;
+        block_lsd_sort<KW, NT, KI>(key, idx, 32, lds_key, lds_idx, cnt, tmp, H);
+        uint32_t ties = 0;
+#pragma unroll
+        for (int r = 0; r < KI; r++) {
+            const uint32_t q = threadIdx.x * KI + r;
+            if (q > 0 && q < L.rn && (lds_key[q] >> H) == (lds_key[q - 1] >> H)) ties++;
+        }
+        ties = (uint32_t)block_sum64<NT>((uint64_t)ties, tmp64);
+        if (ties > 0 && ties <= 256) {
+#pragma unroll
+            for (int r = 0; r < KI; r++) {
+                const uint32_t q = threadIdx.x * KI + r;
+                const bool head = q + 1 < L.rn && (lds_key[q] >> H) == (lds_key[q + 1] >> H) &&
+                                  (q == 0 || (lds_key[q] >> H) != (lds_key[q - 1] >> H));
+                if (!head) continue;
+                uint32_t e = q + 1;
+                while (e < L.rn && (lds_key[e] >> H) == (lds_key[q] >> H)) e++;
+                for (uint32_t i = q + 1; i < e; i++) {  // stable insertion sort of [q, e)
+                    const KW kv = lds_key[i];
+                    const uint16_t iv = lds_idx[i];
+                    uint32_t j = i;
+                    while (j > q && lds_key[j - 1] > kv) {
+                        lds_key[j] = lds_key[j - 1];
+                        lds_idx[j] = lds_idx[j - 1];
+                        j--;
+                    }
+                    lds_key[j] = kv;
+                    lds_idx[j] = iv;
+                }
+            }
+            __syncthreads();
+        } else if (ties > 256) {
+#pragma unroll
+            for (int r = 0; r < KI; r++) {
+                const uint32_t q = (w * KI + r) * 64 + l;
+                key[r] = q < L.rn ? (KW)(ord_of(src_k[q]) - L.base) : (KW)~(KW)0;
+                idx[r] = (uint16_t)q;
+            }
+            block_lsd_sort<KW, NT, KI>(key, idx, (int)L.bits, lds_key, lds_idx, cnt, tmp);
+        }
+    } else {
+        block_lsd_sort<KW, NT, KI>(key, idx, (int)L.bits, lds_key, lds_idx, cnt, tmp);
+    }
     // Keys go out first. The bucket may be sorted in place (its rows already
     // sit in the output columns), so its row ids are all read (coalesced, into
     // the now free key array) before any of them is overwritten.

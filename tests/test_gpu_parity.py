@@ -264,3 +264,17 @@ def test_skewed_buckets_dominated_by_one_key(tj):
     sk = np.where(rng.random(n) < 0.9, 1 << 35, rng.integers(0, 1 << 40, n)).astype(np.int64)
     rk = np.concatenate([np.full(3, 1 << 35), rng.integers(0, 1 << 40, 5000)]).astype(np.int64)
     check_join(tj, rk, np.arange(rk.size, dtype=np.int32), sk, r)
+
+
+def test_sort_wide_keys_with_ties(tj):
+    # 64-bit keys spread wide (wide leaves) with duplicated keys and keys that
+    # share their high bits: the top-32-bit sort plus tie fix-up, and the
+    # fall-back to the full sort when ties are many
+    rng = np.random.default_rng(23)
+    n = 400_000
+    base = rng.integers(I64.min // 2, I64.max // 2, n // 4, dtype=np.int64)
+    k = np.concatenate([base, base, base + rng.integers(0, 16, base.size), base ^ 1])
+    rng.shuffle(k)
+    check_sort(tj, k, rng.permutation(n).astype(np.int32))
+    few = rng.choice(rng.integers(I64.min, I64.max, 7, dtype=np.int64), n)  # long tie runs
+    check_sort(tj, few, np.arange(n, dtype=np.int32))

@@ -32,6 +32,18 @@ template <> __device__ __forceinline__ int64_t key_of<int64_t>(uint64_t o)
     return (int64_t)(o ^ 0x8000000000000000ull);
 }
 
+// Workgroup barrier that orders LDS traffic only. Blocks here never hand data
+// to each other through global memory inside a launch (global reads that feed
+// LDS complete before their LDS write, by data dependence), so outstanding
+// global stores need not drain at a barrier; a plain __syncthreads() would wait
+// for them (vmcnt(0)) and serialise store latency into every tile.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ---------------------------------------------------------------------------
 // wave64 primitives
 // ---------------------------------------------------------------------------
@@ -108,7 +120,7 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* tmp, u
     const uint32_t w = threadIdx.x / 64;
     uint32_t inc = wave_incl_scan(v);
     if ((threadIdx.x & 63) == 63) tmp[w] = inc;
-    __syncthreads();
+    lds_barrier();
     uint32_t off = 0, tot = 0;
 #pragma unroll
     for (int i = 0; i < NW; i++) {
@@ -116,7 +128,7 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* tmp, u
         off += ((uint32_t)i < w) ? t : 0u;
         tot += t;
     }
-    __syncthreads();
+    lds_barrier();
     *total = tot;
     return off + inc - v;
 }
@@ -127,11 +139,11 @@ __device__ __forceinline__ uint64_t block_sum64(uint64_t v, uint64_t* tmp)
     constexpr int NW = NT / 64;
     v = wave_sum64(v);
     if ((threadIdx.x & 63) == 0) tmp[threadIdx.x / 64] = v;
-    __syncthreads();
+    lds_barrier();
     uint64_t tot = 0;
 #pragma unroll
     for (int i = 0; i < NW; i++) tot += tmp[i];
-    __syncthreads();
+    lds_barrier();
     return tot;
 }
 
@@ -158,11 +170,11 @@ __device__ __forceinline__ uint32_t block_excl_max(uint32_t v, uint32_t* tmp)
     if (l == 63) tmp[w] = inc;
     uint32_t prev = (uint32_t)__shfl_up((int)inc, 1u, 64);
     if (l == 0) prev = 0;
-    __syncthreads();
+    lds_barrier();
     uint32_t off = 0;
 #pragma unroll
     for (int i = 0; i < NW; i++) off = ((uint32_t)i < w && tmp[i] > off) ? tmp[i] : off;
-    __syncthreads();
+    lds_barrier();
     return max(off, prev);
 }
 
@@ -173,11 +185,11 @@ __device__ __forceinline__ uint32_t block_max(uint32_t v, uint32_t* tmp)
     constexpr int NW = NT / 64;
     const uint32_t inc = wave_incl_max(v);
     if ((threadIdx.x & 63) == 63) tmp[threadIdx.x / 64] = inc;
-    __syncthreads();
+    lds_barrier();
     uint32_t m = 0;
 #pragma unroll
     for (int i = 0; i < NW; i++) m = tmp[i] > m ? tmp[i] : m;
-    __syncthreads();
+    lds_barrier();
     return m;
 }
 
@@ -229,7 +241,7 @@ __device__ __forceinline__ uint32_t scan_counts(uint32_t* cnt, uint32_t* tmp)
         cnt[(e % NW) * STRIDE + e / NW] = ex;
         ex += v[i];
     }
-    __syncthreads();
+    lds_barrier();
     return tot;
 }
 
@@ -295,7 +307,7 @@ __global__ __launch_bounds__(256) void k_probe(const K* __restrict__ a, uint64_t
         smin[threadIdx.x / 64] = mn;
         smax[threadIdx.x / 64] = mx;
     }
-    __syncthreads();
+    lds_barrier();
     if (threadIdx.x == 0) {
         for (int i = 0; i < 4; i++) {
             mn = smin[i] < mn ? smin[i] : mn;
@@ -349,7 +361,7 @@ __global__ __launch_bounds__(PART_THREADS) void k_hist(const ChunkDesc* __restri
         mn[d] = ~0ull;
         mx[d] = 0;
     }
-    __syncthreads();
+    lds_barrier();
     // Rows are counted with LDS atomics. When every valid row of a wave's round
     // falls in one bin (skewed inputs: buckets dominated by one key), the wave
     // reduces them first and one lane updates the bin.
@@ -388,7 +400,7 @@ __global__ __launch_bounds__(PART_THREADS) void k_hist(const ChunkDesc* __restri
             }
         }
     }
-    __syncthreads();
+    lds_barrier();
     for (uint32_t d = threadIdx.x; d < nbins; d += PART_THREADS) {
         hist[(uint64_t)blockIdx.x * NB + d] = cnt[d];
         if (cnt[d]) {
@@ -592,7 +604,7 @@ __global__ __launch_bounds__(SC_NT) void k_scatter(const ChunkDesc* __restrict__
         for (uint32_t i = l; i < NB; i += 64) cnt[w * SC_STRIDE + i] = 0;
 #pragma unroll
         for (int r = 0; r < KI; r++) rk[r] = wave_rank(dig[r], val[r], (int)g.bits, &cnt[w * SC_STRIDE]);
-        __syncthreads();
+        lds_barrier();
         const uint32_t total = scan_counts<NT, NW, NB>(cnt, tmp);
         for (uint32_t d = threadIdx.x; d < NB; d += NT) {
             const uint32_t tex = cnt[d];
@@ -608,7 +620,7 @@ __global__ __launch_bounds__(SC_NT) void k_scatter(const ChunkDesc* __restrict__
                 if (RIDS) srid[p] = rid[r];
             }
         }
-        __syncthreads();
+        lds_barrier();
         // next tile's loads overlap the write-out of this one
         const uint32_t n0 = t0 + TILE;
         if (n0 < ch.len) {
@@ -626,7 +638,7 @@ __global__ __launch_bounds__(SC_NT) void k_scatter(const ChunkDesc* __restrict__
             if (WKEYS) dst_k[dst] = k;
             if (RIDS) dst_r[dst] = srid[p];
         }
-        __syncthreads();
+        lds_barrier();
     }
 }
 
@@ -706,7 +718,7 @@ __device__ __forceinline__ void block_lsd_sort(KW (&key)[KI], uint16_t (&idx)[KI
             lds_key[q] = key[r];
             lds_idx[q] = idx[r];
         }
-        __syncthreads();
+        lds_barrier();
         return;
     }
     for (int p = 0; p < passes; p++) {
@@ -719,7 +731,7 @@ __device__ __forceinline__ void block_lsd_sort(KW (&key)[KI], uint16_t (&idx)[KI
         for (uint32_t i = l; i < LBINS; i += 64) cnt[w * LSTRIDE + i] = 0;
 #pragma unroll
         for (int r = 0; r < KI; r++) rk[r] = wave_rank(dig[r], true, nb, &cnt[w * LSTRIDE]);
-        __syncthreads();
+        lds_barrier();
         scan_counts<NT, NW, LBINS>(cnt, tmp);
 #pragma unroll
         for (int r = 0; r < KI; r++) {
@@ -727,7 +739,7 @@ __device__ __forceinline__ void block_lsd_sort(KW (&key)[KI], uint16_t (&idx)[KI
             lds_key[pos] = key[r];
             lds_idx[pos] = idx[r];
         }
-        __syncthreads();
+        lds_barrier();
         if (p + 1 < passes) {
 #pragma unroll
             for (int r = 0; r < KI; r++) {
@@ -801,7 +813,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_leaf_sort(const LeafDesc* __restr
                     lds_idx[j] = iv;
                 }
             }
-            __syncthreads();
+            lds_barrier();
         } else if (ties > 256) {
 #pragma unroll
             for (int r = 0; r < KI; r++) {
@@ -822,10 +834,10 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_leaf_sort(const LeafDesc* __restr
         const uint32_t q = (w * KI + r) * 64 + l;
         if (q < L.rn) out_k[L.out + q] = key_of<K>(L.base + (uint64_t)lds_key[q]);
     }
-    __syncthreads();
+    lds_barrier();
     int32_t* lds_rid = (int32_t*)lds_key;
     for (uint32_t q = threadIdx.x; q < L.rn; q += NT) lds_rid[q] = src_r[q];
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int r = 0; r < KI; r++) {
         const uint32_t q = (w * KI + r) * 64 + l;
@@ -948,7 +960,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_leaf_join(const LeafDesc* __restr
     uint32_t li = blockIdx.x;
     if (MAT) {
         if (threadIdx.x == 0) s_leaf = atomicAdd(ticket, 1u);
-        __syncthreads();
+        lds_barrier();
         li = s_leaf;
     }
     const LeafDesc L = leaves[li];
@@ -1012,7 +1024,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_leaf_join(const LeafDesc* __restr
         if (isr && (last || idn >= rn)) run_s0[rs[i]] = (uint16_t)(p + 1);   // last R item
         if (!isr && p == rs[i]) run_s0[rs[i]] = (uint16_t)p;                  // run without R items
     }
-    __syncthreads();
+    lds_barrier();
     // per item, packed: [is R:1][a:14][b:14], a = R items and b = S items of its
     // run (0 for padding); kv = position of the item inside the run's S part
     uint32_t abv[KI], kv[KI];
@@ -1053,7 +1065,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_leaf_join(const LeafDesc* __restr
             s_base = excl + L.out;
         }
     }
-    __syncthreads();
+    lds_barrier();
     const uint64_t base = s_base;
     // Pair slots: R item j of a run owns E_rs + j*b .. + b (it writes out_r),
     // S item k of a run appears at E_rs + i*b + k for its run's a R items (it
@@ -1079,7 +1091,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_leaf_join(const LeafDesc* __restr
     int32_t rid[KI];
 #pragma unroll
     for (int i = 0; i < KI; i++) rid[i] = p0 + i < n ? lds_w[lds_idx[p0 + i]] : 0;
-    __syncthreads();  // the key array becomes the pair staging buffer
+    lds_barrier();  // the key array becomes the pair staging buffer
     constexpr uint32_t OC = C / 2;  // pairs per staged chunk: two int32 columns in the key array
     if (ltot <= 8 * OC && maxslots <= 64) {
         // Staged: items scatter their slots of the chunk into LDS, then the chunk
@@ -1099,7 +1111,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_leaf_join(const LeafDesc* __restr
                     if (t >= c0 && t < c1) st[t - c0] = rid[i];
                 }
             }
-            __syncthreads();
+            lds_barrier();
             const uint32_t cn = ltot - c0 < OC ? ltot - c0 : OC;
             for (uint32_t t = threadIdx.x; t < cn; t += NT) {
                 const uint64_t o = base + c0 + t;
@@ -1108,7 +1120,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_leaf_join(const LeafDesc* __restr
                     out_s[o] = st_s[t];
                 }
             }
-            __syncthreads();
+            lds_barrier();
         }
         return;
     }

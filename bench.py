@@ -38,6 +38,36 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+def kernel_source_digest() -> str:
+    """Short SHA-256 of the kernel sources; a traffic record taken on other
+    sources no longer describes the kernels that run."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("tj_kernels.hip", "tj_internal.h"):
+        with open(os.path.join(ROOT, "paper_2602_21237_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(family: str, workload: str):
+    """HBM bytes per launch of a kernel family, from the committed summary of
+    two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by a plain copy of
+    known size. Returns (bytes or None, reason)."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.md" % (family, workload))
+    if not os.path.exists(path):
+        return None, "no counter summary for this kernel"
+    rec = None
+    with open(path) as fh:
+        for ln in fh:
+            if ln.startswith("traffic-record: "):
+                rec = json.loads(ln[len("traffic-record: "):])
+    if rec is None:
+        return None, "summary has no traffic-record line"
+    if rec.get("kernel_source_sha256_16") != kernel_source_digest():
+        return None, "kernel sources changed since the counters were taken"
+    return int(rec["hbm_bytes_per_launch"]), os.path.relpath(path, ROOT)
+
+
 def pct(xs, q):
     """Nearest-rank percentile: sorted ascending, x[ceil(q*m) - 1]."""
     xs = sorted(xs)
@@ -148,6 +178,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-sweep", action="store_true", help="skip the paper-shaped budget sweep")
     ap.add_argument("--sweep-repeats", type=int, default=100)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="before timing, copy MIB MiB device-to-device three times (a plain copy "
+                         "of known size that scales the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -192,10 +225,16 @@ def main():
     for i in range(args.warmup):
         cnt, _, _ = step()
         log("warmup %d done, join count %d" % (i, cnt))
-    if expected is not None:
-        assert cnt == expected, "join count %d != closed form %d" % (cnt, expected)
-    # check the sort output is ordered (a property that holds at any size)
-    assert bool((ko[1:] >= ko[:-1]).all().item()), "sort output not ordered"
+
+    if args.copy_calibration > 0:
+        nb = args.copy_calibration << 20
+        c_src = torch.ones(nb, dtype=torch.uint8, device="cuda")
+        c_dst = torch.empty_like(c_src)
+        for _ in range(3):
+            c_dst.copy_(c_src)
+        torch.cuda.synchronize()
+        log("copy calibration: %d bytes copied 3 times" % nb)
+        del c_src, c_dst
 
     tj.timing(True)
     torch.cuda.synchronize()
@@ -216,6 +255,10 @@ def main():
         log("step %d: sort %.2f ms, join %.2f ms" % (i, (t1 - t0) * 1e3, (t2 - t1) * 1e3))
     tj.timing(False)
     fams = tj.timing_read()
+    # properties of the last step's results that hold at any size
+    if expected is not None:
+        assert pr.numel() == expected, "join count %d != closed form %d" % (pr.numel(), expected)
+    assert bool((ko[1:] >= ko[:-1]).all().item()), "sort output not ordered"
     total_s = sum(times)
     ms_per_step = total_s / args.steps * 1e3
     tuples = n_sort + n_r + n_s
@@ -226,8 +269,10 @@ def main():
     avg_ms = fd["ms"] / max(fd["launches"], 1)
     bytes_per_launch = fd["bytes"] / max(fd["launches"], 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    traffic, traffic_src = measured_traffic(dom, args.workload + ("_theta%g" % args.theta if args.theta else ""))
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "traffic_source": traffic_src, "kernel_source_sha256_16": kernel_source_digest(),
                 "bytes_per_launch": int(bytes_per_launch), "avg_launch_ms": round(avg_ms, 4),
                 "launches_per_step": fd["launches"] / args.steps}
     kernels = {f: {"launches_per_step": v["launches"] / args.steps,

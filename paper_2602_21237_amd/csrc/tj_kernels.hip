@@ -57,6 +57,15 @@ __device__ __forceinline__ uint32_t mbcnt(uint64_t m)
 
 __device__ __forceinline__ uint32_t lane_id() { return mbcnt(~0ull); }
 
+// p[min(q, n - 1)], n >= 1. The load is unconditional (the clamped index
+// always names a real element), so an unrolled batch of them is issued before
+// the first wait; a guarded load would wait on each one in turn.
+template <typename T>
+__device__ __forceinline__ T ld_clamp(const T* __restrict__ p, uint64_t q, uint64_t n)
+{
+    return p[q < n ? q : n - 1];
+}
+
 // Inclusive prefix sum across the 64 lanes with DPP: shifts of 1, 2, 4, 8
 // inside each row of 16 lanes, then row_bcast:15 carries row totals into rows
 // 1 and 3 and row_bcast:31 carries the first half's total into rows 2 and 3.
@@ -291,15 +300,30 @@ __global__ __launch_bounds__(256) void k_probe(const K* __restrict__ a, uint64_t
     uint64_t mn = ~0ull, mx = 0;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     const uint64_t t0 = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
-    for (uint64_t i = t0; i < na; i += stride) {
-        const uint64_t o = ord_of(a[i]);
-        mn = o < mn ? o : mn;
-        mx = o > mx ? o : mx;
+    // U loads in flight per thread; a clamped index re-reads a real element,
+    // which leaves the minimum and maximum unchanged.
+    constexpr int U = 8;
+    for (uint64_t i0 = t0; i0 < na; i0 += stride * U) {
+        K v[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) v[u] = ld_clamp(a, i0 + u * stride, na);
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const uint64_t o = ord_of(v[u]);
+            mn = o < mn ? o : mn;
+            mx = o > mx ? o : mx;
+        }
     }
-    for (uint64_t i = t0; i < nb; i += stride) {
-        const uint64_t o = ord_of(b[i]);
-        mn = o < mn ? o : mn;
-        mx = o > mx ? o : mx;
+    for (uint64_t i0 = t0; i0 < nb; i0 += stride * U) {
+        K v[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) v[u] = ld_clamp(b, i0 + u * stride, nb);
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const uint64_t o = ord_of(v[u]);
+            mn = o < mn ? o : mn;
+            mx = o > mx ? o : mx;
+        }
     }
     mn = wave_min64(mn);
     mx = wave_max64(mx);
@@ -373,7 +397,7 @@ __global__ __launch_bounds__(PART_THREADS) void k_hist(const ChunkDesc* __restri
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const uint32_t q = q0 + u * PART_THREADS;
-            k[u] = q < ch.len ? src[q] : K(0);
+            k[u] = ld_clamp(src, q, ch.len);  // rows past the chunk are masked below
         }
 #pragma unroll
         for (int u = 0; u < U; u++) {
@@ -551,7 +575,7 @@ hipError_t launch_scan(const CBlockDesc* cblocks, uint32_t ncblocks, const Group
 // of a wave covers 64 consecutive rows, so (wave, round, lane) is input order
 // and the partition is stable.
 // ---------------------------------------------------------------------------
-constexpr int SC_NT = 512, SC_KI = 8, SC_NW = SC_NT / 64, SC_TILE = SC_NT * SC_KI;
+constexpr int SC_NT = 1024, SC_KI = 8, SC_NW = SC_NT / 64, SC_TILE = SC_NT * SC_KI;
 constexpr int SC_STRIDE = NB + 1;
 static_assert(SC_TILE == PART_TILE, "chunk sizes are planned in scatter tiles");
 
@@ -701,7 +725,125 @@ template <typename KW> struct LeafShape {
     static constexpr int NT = sizeof(KW) == 4 ? 512 : 1024;
     static constexpr int KI = LEAF_CAP / NT;
     static constexpr int NW = NT / 64;
+    static constexpr int NBB = sizeof(KW) == 4 ? 12 : 13;  // bin bits of block_bin_sort
+    static constexpr int NBIN = 1 << NBB;
+    // LDS words shared by the bin counters and the LSD digit counters
+    static constexpr int CNT_WORDS = NBIN > NW * LSTRIDE ? NBIN : NW * LSTRIDE;
 };
+
+// Largest bin block_bin_sort accepts: the exact ranking inside a bin costs
+// every item of the bin one pass over it.
+constexpr uint32_t BIN_MAXC = 48;  // < 64: the bin size is packed in 6 bits
+
+// Stable sort of the block's items in one counting pass. Item key[r] sits at
+// position q = (w*KI + r)*64 + l; items with q < n are sorted, the rest are
+// padding and stay at q (their keys are all ones and their positions the
+// largest, so that is their sorted place too). An item's index is its
+// position q, so the stable order is the order of the pairs (key, q).
+//  1. Each item is counted into one of 2^NBB bins by the top bits of its key
+//     (LDS atomics; the slot an item gets inside its bin is arbitrary).
+//  2. An exclusive scan of the bin counts gives each bin's first position;
+//     the items are written there in slot order.
+//  3. Each item of a bin with two or more items counts the items of its bin
+//     that precede it in (key, q) order and moves to that rank.
+// The result, in lds_key / lds_idx, is exact whatever order the atomics take.
+// Returns false, having written nothing to lds_key / lds_idx, when some bin
+// holds more than BIN_MAXC items; the caller then sorts another way.
+template <typename KW, int NT, int KI, int NBB>
+__device__ __forceinline__ bool block_bin_sort(const KW (&key)[KI], int bits, uint32_t n, KW* lds_key,
+                                               uint16_t* lds_idx, uint32_t* hist, uint32_t* tmp)
+{
+    constexpr int NBIN = 1 << NBB, BPT = NBIN / NT;
+    static_assert(NBIN % NT == 0, "bins must split evenly over the block");
+    static_assert(NT * KI <= 8192, "positions are packed in 13 bits");
+    const uint32_t w = threadIdx.x / 64, l = threadIdx.x & 63;
+    const int hb = bits < NBB ? bits : NBB;
+    const int sh = bits - hb;
+    for (uint32_t i = threadIdx.x; i < (uint32_t)NBIN; i += NT) hist[i] = 0;
+    lds_barrier();
+    // per item: bin | slot << 16, then pos | first of bin << 13 | bin size << 26,
+    // then (1 << 31 | final position) for the items that move
+    // (array elements are only ever assigned unconditionally: a conditional
+    // assignment makes the compiler copy the whole array through every branch)
+    uint32_t info[KI];
+#pragma unroll
+    for (int r = 0; r < KI; r++) {
+        const uint32_t q = (w * KI + r) * 64 + l;
+        const KW kb = key[r] >> sh;  // < 2^NBB when the keys span `bits` bits
+        const uint32_t b = kb < (KW)NBIN ? (uint32_t)kb : (uint32_t)NBIN - 1u;
+        uint32_t slot = 0;
+        if (q < n) slot = atomicAdd(&hist[b], 1u);
+        info[r] = b | (slot << 16);
+    }
+    lds_barrier();
+    uint32_t c[BPT], sum = 0, mx = 0;
+#pragma unroll
+    for (int i = 0; i < BPT; i++) {
+        c[i] = hist[threadIdx.x * BPT + i];
+        sum += c[i];
+        mx = c[i] > mx ? c[i] : mx;
+    }
+    if (block_max<NT>(mx, tmp) > BIN_MAXC) return false;
+    uint32_t tot;
+    uint32_t ex = block_excl_scan<NT>(sum, tmp, &tot);
+#pragma unroll
+    for (int i = 0; i < BPT; i++) {
+        hist[threadIdx.x * BPT + i] = ex;
+        ex += c[i];
+    }
+    lds_barrier();
+#pragma unroll
+    for (int r = 0; r < KI; r++) {
+        const uint32_t q = (w * KI + r) * 64 + l;
+        const uint32_t b = info[r] & 0xffffu;
+        const uint32_t s0 = hist[b];
+        const uint32_t e0 = b + 1 < (uint32_t)NBIN ? hist[b + 1] : n;
+        const bool valid = q < n;
+        const uint32_t pos = valid ? s0 + (info[r] >> 16) : q;
+        info[r] = valid ? pos | (s0 << 13) | ((e0 - s0) << 26) : 0u;
+        lds_key[pos] = key[r];
+        lds_idx[pos] = (uint16_t)q;
+    }
+    lds_barrier();
+    // The thread's items walk their bins in step, so that the LDS reads of all
+    // of them are in flight together: step j reads element j of each bin (an
+    // item whose bin is shorter re-reads its bin's first element and ignores it).
+    uint32_t rank[KI], cbmax = 0;
+#pragma unroll
+    for (int r = 0; r < KI; r++) {
+        const uint32_t cb = info[r] >> 26;
+        rank[r] = 0;
+        cbmax = cb > 1 && cb > cbmax ? cb : cbmax;
+    }
+    for (uint32_t j = 0; j < cbmax; j++) {
+#pragma unroll
+        for (int r = 0; r < KI; r++) {
+            const uint32_t q = (w * KI + r) * 64 + l;
+            const uint32_t s0 = (info[r] >> 13) & 0x1fffu, cb = info[r] >> 26;
+            const bool act = j < cb;
+            const uint32_t e = act ? s0 + j : s0;
+            const KW kj = lds_key[e];
+            const uint32_t ij = lds_idx[e];
+            rank[r] += (act && (kj < key[r] || (kj == key[r] && ij < q))) ? 1u : 0u;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < KI; r++) {
+        const uint32_t pos = info[r] & 0x1fffu, s0 = (info[r] >> 13) & 0x1fffu, cb = info[r] >> 26;
+        info[r] = (cb > 1 && s0 + rank[r] != pos) ? 0x80000000u | (s0 + rank[r]) : 0u;
+    }
+    lds_barrier();
+#pragma unroll
+    for (int r = 0; r < KI; r++) {
+        if (info[r] >> 31) {
+            const uint32_t q = (w * KI + r) * 64 + l;
+            lds_key[info[r] & 0x1fffu] = key[r];
+            lds_idx[info[r] & 0x1fffu] = (uint16_t)q;
+        }
+    }
+    lds_barrier();
+    return true;
+}
 
 template <typename KW, int NT, int KI>
 __device__ __forceinline__ void block_lsd_sort(KW (&key)[KI], uint16_t (&idx)[KI], int bits,
@@ -740,13 +882,13 @@ __device__ __forceinline__ void block_lsd_sort(KW (&key)[KI], uint16_t (&idx)[KI
             lds_idx[pos] = idx[r];
         }
         lds_barrier();
-        if (p + 1 < passes) {
+        // (reloaded after the last pass too: a conditional reload would make
+        // the compiler copy both arrays through the branch)
 #pragma unroll
-            for (int r = 0; r < KI; r++) {
-                const uint32_t q = (w * KI + r) * 64 + l;
-                key[r] = lds_key[q];
-                idx[r] = lds_idx[q];
-            }
+        for (int r = 0; r < KI; r++) {
+            const uint32_t q = (w * KI + r) * 64 + l;
+            key[r] = lds_key[q];
+            idx[r] = lds_idx[q];
         }
     }
 }
@@ -760,23 +902,29 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_leaf_sort(const LeafDesc* __restr
     constexpr int NT = LeafShape<KW>::NT, KI = LeafShape<KW>::KI, NW = LeafShape<KW>::NW, C = LEAF_CAP;
     __shared__ KW lds_key[C];
     __shared__ uint16_t lds_idx[C];
-    __shared__ uint32_t cnt[NW * LSTRIDE];
+    __shared__ uint32_t cnt[LeafShape<KW>::CNT_WORDS];
     __shared__ uint32_t tmp[NW];
     __shared__ uint64_t tmp64[NW];
 
     const LeafDesc L = leaves[blockIdx.x];
+    if (L.rn == 0) return;
     const K* __restrict__ src_k = (const K*)bufs.key[L.buf][0] + L.r0;
     const int32_t* __restrict__ src_r = bufs.rid[L.buf][0] + L.r0;
     const uint32_t w = threadIdx.x / 64, l = threadIdx.x & 63;
     KW key[KI];
-    uint16_t idx[KI];
 #pragma unroll
     for (int r = 0; r < KI; r++) {
         const uint32_t q = (w * KI + r) * 64 + l;
-        key[r] = q < L.rn ? (KW)(ord_of(src_k[q]) - L.base) : (KW)~(KW)0;
-        idx[r] = (uint16_t)q;
+        const K v = ld_clamp(src_k, q, L.rn);
+        key[r] = q < L.rn ? (KW)(ord_of(v) - L.base) : (KW)~(KW)0;
     }
-    if (sizeof(KW) == 8 && L.bits > 32) {
+    uint16_t idx[KI];
+#pragma unroll
+    for (int r = 0; r < KI; r++) idx[r] = (uint16_t)((w * KI + r) * 64 + l);
+    if (L.bits > 0 &&
+        block_bin_sort<KW, NT, KI, LeafShape<KW>::NBB>(key, (int)L.bits, L.rn, lds_key, lds_idx, cnt, tmp)) {
+        // sorted in one counting pass
+    } else if (sizeof(KW) == 8 && L.bits > 32) {
         // Wide keys: sort by the top 32 bits of the relative key only (4 digit
         // passes instead of up to 8). The order is final unless two rows share
         // those 32 bits; short runs of such ties are then put in order by one
@@ -818,7 +966,8 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_leaf_sort(const LeafDesc* __restr
 #pragma unroll
             for (int r = 0; r < KI; r++) {
                 const uint32_t q = (w * KI + r) * 64 + l;
-                key[r] = q < L.rn ? (KW)(ord_of(src_k[q]) - L.base) : (KW)~(KW)0;
+                const K v = ld_clamp(src_k, q, L.rn);
+        key[r] = q < L.rn ? (KW)(ord_of(v) - L.base) : (KW)~(KW)0;
                 idx[r] = (uint16_t)q;
             }
             block_lsd_sort<KW, NT, KI>(key, idx, (int)L.bits, lds_key, lds_idx, cnt, tmp);
@@ -836,7 +985,12 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_leaf_sort(const LeafDesc* __restr
     }
     lds_barrier();
     int32_t* lds_rid = (int32_t*)lds_key;
-    for (uint32_t q = threadIdx.x; q < L.rn; q += NT) lds_rid[q] = src_r[q];
+#pragma unroll
+    for (int r = 0; r < KI; r++) {
+        const uint32_t q = threadIdx.x + r * NT;
+        const int32_t v = ld_clamp(src_r, q, L.rn);
+        if (q < L.rn) lds_rid[q] = v;
+    }
     lds_barrier();
 #pragma unroll
     for (int r = 0; r < KI; r++) {
@@ -974,11 +1128,21 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_leaf_join(const LeafDesc* __restr
 #pragma unroll
     for (int r = 0; r < KI; r++) {
         const uint32_t q = (w * KI + r) * 64 + l;
-        if (q < rn) key[r] = (KW)(ord_of(rk[q]) - L.base);
-        else if (q < n) key[r] = (KW)(ord_of(sk[q - rn]) - L.base);
-        else key[r] = (KW)~(KW)0;
+        key[r] = (KW)~(KW)0;
         idx[r] = (uint16_t)q;
     }
+    if (n > 0) {
+#pragma unroll
+        for (int r = 0; r < KI; r++) {
+            const uint32_t q = (w * KI + r) * 64 + l;
+            const uint32_t qc = q < n ? q : n - 1;  // every lane loads a real row
+            const K v = qc < rn ? rk[qc] : sk[qc - rn];
+            if (q < n) key[r] = (KW)(ord_of(v) - L.base);
+        }
+    }
+    // (LSD rather than block_bin_sort: a key here usually has several rows, one
+    // of R and its S matches, which makes the bins too full for the exact
+    // in-bin ranking to pay)
     block_lsd_sort<KW, NT, KI>(key, idx, (int)L.bits, lds_key, lds_idx, cnt, tmp);
 
     // Run analysis on blocked positions p = tid*KI + i. A run is a maximal
@@ -1056,7 +1220,13 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_leaf_join(const LeafDesc* __restr
     {
         const int32_t* __restrict__ rr = bufs.rid[L.buf][0] + L.r0;
         const int32_t* __restrict__ sr = bufs.rid[L.buf][1] + L.s0;
-        for (uint32_t q = threadIdx.x; q < n; q += NT) lds_w[q] = q < rn ? rr[q] : sr[q - rn];
+#pragma unroll
+        for (int r = 0; r < KI; r++) {
+            const uint32_t q = threadIdx.x + r * NT;
+            const uint32_t qc = q < n ? q : n - 1;
+            const int32_t v = qc < rn ? rr[qc] : sr[qc - rn];
+            if (q < n) lds_w[q] = v;
+        }
     }
     if (threadIdx.x < 64) {
         const uint64_t excl = look_back(status, li + 1, err);

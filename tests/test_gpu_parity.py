@@ -95,7 +95,7 @@ def test_sort_uniform_64bit_keys(tj):
     check_sort(tj, w["keys"], w["rids"])
 
 
-@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 4095, 4096, 4097, 8191, 8192, 8193, 20_000])
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 4095, 4096, 4097, 8191, 8192, 8193, 16383, 16385, 20_000])
 def test_sort_sizes(tj, n):
     rng = np.random.default_rng(n)
     k = rng.integers(-1000, 1000, n).astype(np.int64)
@@ -120,6 +120,20 @@ def test_sort_edge_distributions(tj):
         r = rng.permutation(n).astype(np.int32)
         check_sort(tj, k, r)
     check_sort(tj, np.array([I32.min, I32.max, -1, 0, I32.min], np.int32), np.arange(5, dtype=np.int32))
+
+
+@pytest.mark.parametrize("distinct", [3, 40, 150, 700, 5000])
+def test_sort_leaf_duplicates(tj, distinct):
+    """One leaf-sized bucket with few distinct keys: with 40 distinct keys and
+    fewer the one-pass bin sort sees bins above its limit and falls back to the
+    digit passes; with more it ranks many equal keys inside each bin."""
+    rng = np.random.default_rng(distinct)
+    for n in (6000, 8192):
+        vals = rng.integers(-(1 << 40), 1 << 40, distinct)
+        k = rng.choice(vals, n).astype(np.int64)
+        r = rng.permutation(n).astype(np.int32)
+        check_sort(tj, k, r)
+        check_sort(tj, (k >> 20).astype(np.int32), r)
 
 
 def test_sort_empty(tj):

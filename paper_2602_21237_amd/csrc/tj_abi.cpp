@@ -24,6 +24,7 @@
 #include "../../include/tj.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -183,9 +184,10 @@ struct Unit {                 // a final piece of join output, ordered by key
 // Kernel timing registry (tj_timing / tj_timing_read).
 // ---------------------------------------------------------------------------
 enum Fam { F_PROBE, F_HIST, F_SCAN, F_SCATTER, F_LEAF_SORT, F_LEAF_COUNT, F_LEAF_MAT, F_CROSS, F_COPY,
-           F_EXPAND, NFAM };
+           F_EXPAND, F_HOST_CLASSIFY, F_HOST_LEAVES, NFAM };
 const char* const kFamName[NFAM] = {"probe", "histogram", "scan", "scatter", "leaf_sort",
-                                    "leaf_join_count", "leaf_join_mat", "cross", "copy", "expand"};
+                                    "leaf_join_count", "leaf_join_mat", "cross", "copy", "expand",
+                                    "host_classify", "host_leaves"};
 
 struct Timing {
     std::mutex mu;
@@ -198,6 +200,44 @@ Timing& timing()
 {
     static Timing t;
     return t;
+}
+
+// Host-side lists of one call (see Exec::hv).
+struct HostVecs {
+    std::vector<LeafDesc> leaves, batch_leaves;
+    std::vector<CrossDesc> crosses, batch_crosses;
+    std::vector<CopyDesc> copies;
+    bool busy = false;
+    void clear()
+    {
+        leaves.clear();
+        batch_leaves.clear();
+        crosses.clear();
+        batch_crosses.clear();
+        copies.clear();
+    }
+};
+thread_local HostVecs* t_host_vecs = nullptr;  // never freed, like the pinned staging
+
+// The thread's lists, or (if a call on this thread already holds them) a
+// private set owned through `owned`.
+HostVecs& borrow_host_vecs(HostVecs*& owned)
+{
+    if (!t_host_vecs) t_host_vecs = new HostVecs();
+    if (!t_host_vecs->busy) {
+        t_host_vecs->busy = true;
+        t_host_vecs->clear();
+        return *t_host_vecs;
+    }
+    owned = new HostVecs();
+    return *owned;
+}
+
+void return_host_vecs(HostVecs& hv, HostVecs* owned)
+{
+    hv.clear();
+    if (owned) delete owned;
+    else hv.busy = false;
 }
 
 struct Pending {
@@ -271,14 +311,43 @@ struct Exec {
         pending.clear();
     }
 
-    ~Exec() { flush_timing(); }
+    ~Exec()
+    {
+        flush_timing();
+        return_host_vecs(hv, hv_owned);
+    }
+
+    // Host planning time between a read-back and the next launch (families
+    // host_*; launches counts timed sections, bytes stays 0).
+    struct HostTimer {
+        Exec* x;
+        int fam;
+        std::chrono::steady_clock::time_point t0;
+        bool done = false;
+        HostTimer(Exec* e, int f) : x(e), fam(f), t0(std::chrono::steady_clock::now()) {}
+        ~HostTimer() { stop(); }
+        void stop()
+        {
+            if (done || !x->timed_on) return;
+            done = true;
+            const double ms =
+                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            Timing& t = timing();
+            std::lock_guard<std::mutex> g(t.mu);
+            t.launches[fam]++;
+            t.ms[fam] += ms;
+        }
+    };
 
     // host-side results
-    std::vector<LeafDesc> leaves;
-    std::vector<uint64_t> leaf_lo;
-    std::vector<CrossDesc> crosses;
-    std::vector<uint64_t> cross_lo;
-    std::vector<CopyDesc> copies;
+    // Host-side lists live in per-thread storage that keeps its capacity from
+    // call to call: a fresh multi-megabyte vector costs a page fault per 4 KiB
+    // on every call, more than the planning itself.
+    HostVecs* hv_owned = nullptr;
+    HostVecs& hv = borrow_host_vecs(hv_owned);
+    std::vector<LeafDesc>& leaves = hv.leaves;
+    std::vector<CrossDesc>& crosses = hv.crosses;
+    std::vector<CopyDesc>& copies = hv.copies;
 
     // ---- workspace layout -------------------------------------------------
     int carve_tables(char*& p, char* end)
@@ -308,9 +377,11 @@ struct Exec {
     }
 
     // ---- one partition pass over a list of segments that live in `src` ----
-    // Appends the children (in key order) to `out`.
+    // Hands every child, in key order, to `sink` (called with a const Seg&)
+    // as soon as its launch batch has been read back.
+    template <class Sink>
     int run_pass(const std::vector<Seg>& segs, uint32_t src, uint32_t dst,
-                 const uint64_t* filter, std::vector<Seg>& out)
+                 const uint64_t* filter, Sink&& sink)
     {
         stats.passes++;
         const int nside = sh.join ? 2 : 1;
@@ -445,6 +516,7 @@ struct Exec {
             TJ_CK(hipStreamSynchronize(st));
             // children in key order: segment order, then digit order; a child's
             // rows start where its smaller-digit siblings end
+            HostTimer ht(this, F_HOST_CLASSIFY);
             uint64_t moved_rows = 0;
             for (uint32_t gi = 0; gi < ng; gi += (uint32_t)nside) {
                 const GroupDesc& g0 = groups[gi];
@@ -463,7 +535,7 @@ struct Exec {
                     r0 += c.rn;
                     s0 += c.sn;
                     moved_rows += c.rn + c.sn;
-                    out.push_back(c);
+                    sink(c);
                 }
             }
             stats.bytes_written += moved_rows * row_bytes(sh.kb, sh.rids);
@@ -472,80 +544,79 @@ struct Exec {
         return TJ_OK;
     }
 
-    // ---- classification and leaf batching of one level's buckets ---------
-    // Buckets that need another pass go to `next`; the rest become leaves,
-    // crosses (join) or copies (sort). `out_delta` maps buffer rows to output
-    // rows of the sort.
-    void classify(const std::vector<Seg>& level, std::vector<Seg>& next, uint64_t out_delta)
+    // ---- classification and leaf batching of buckets ----------------------
+    // Buckets arrive in key order, one level at a time. Those that need another
+    // pass go to `next`; the rest become leaves (adjacent small buckets batched
+    // up to LEAF_CAP rows), crosses (join) or copies (sort). `out_delta` maps
+    // buffer rows to output rows of the sort. classify_flush closes the open
+    // leaf at the end of a level.
+    bool cl_open = false, cl_useful = false;
+    LeafDesc cl_cur{};
+    uint64_t cl_lo = 0, cl_hi = 0;
+
+    void classify_flush(uint64_t out_delta)
     {
-        bool open = false;
-        LeafDesc cur{};
-        uint64_t cur_lo = 0, cur_hi = 0;
-        bool cur_useful = false;
-        auto flush = [&]() {
-            if (open && cur_useful) {
-                cur.base = cur_lo;
-                cur.bits = nbits64(cur_hi - cur_lo);
-                cur.out = sh.join ? 0 : cur.r0 + out_delta;
-                leaves.push_back(cur);
-                leaf_lo.push_back(cur_lo);
-            }
-            open = false;
-            cur_useful = false;
-        };
-        for (const Seg& s : level) {
-            const uint64_t rows = s.rn + s.sn;
-            if (rows == 0) continue;  // occupies no rows: does not break adjacency
-            const bool single = s.lo == s.hi;
-            const bool both = s.rn > 0 && s.sn > 0;
-            const bool useful = sh.join ? both : true;
-            if (rows <= (uint64_t)LEAF_CAP) {
-                const bool adjacent = open && cur.buf == s.buf && cur.r0 + cur.rn == s.r0 &&
-                                      (!sh.join || cur.s0 + cur.sn == s.s0) &&
-                                      cur.rn + cur.sn + rows <= (uint64_t)LEAF_CAP;
-                if (!adjacent) {
-                    flush();
-                    open = true;
-                    cur = LeafDesc{};
-                    cur.r0 = s.r0;
-                    cur.s0 = s.s0;
-                    cur.buf = s.buf;
-                    cur_lo = s.lo;
-                    cur_hi = s.hi;
-                }
-                cur.rn += (uint32_t)s.rn;
-                cur.sn += (uint32_t)s.sn;
-                cur_lo = std::min(cur_lo, s.lo);
-                cur_hi = std::max(cur_hi, s.hi);
-                cur_useful = cur_useful || useful;
-                continue;
-            }
-            flush();
-            if (sh.join && !both) continue;  // no partner rows: no output
-            if (single) {
-                stats.single_key++;
-                if (sh.join) {
-                    CrossDesc c{};
-                    c.r0 = s.r0;
-                    c.s0 = s.s0;
-                    c.a = s.rn;
-                    c.b = s.sn;
-                    c.buf = s.buf;
-                    crosses.push_back(c);
-                    cross_lo.push_back(s.lo);
-                } else if (!(out_is_a && s.buf == BUF_A && out_delta == 0)) {
-                    CopyDesc c{};
-                    c.start = s.r0;
-                    c.len = s.rn;
-                    c.out = s.r0 + out_delta;
-                    c.buf = s.buf;
-                    copies.push_back(c);
-                }
-                continue;
-            }
-            next.push_back(s);
+        if (cl_open && cl_useful) {
+            cl_cur.base = cl_lo;
+            cl_cur.bits = nbits64(cl_hi - cl_lo);
+            cl_cur.out = sh.join ? 0 : cl_cur.r0 + out_delta;
+            leaves.push_back(cl_cur);
         }
-        flush();
+        cl_open = false;
+        cl_useful = false;
+    }
+
+    void classify_one(const Seg& s, std::vector<Seg>& next, uint64_t out_delta)
+    {
+        const uint64_t rows = s.rn + s.sn;
+        if (rows == 0) return;  // occupies no rows: does not break adjacency
+        const bool single = s.lo == s.hi;
+        const bool both = s.rn > 0 && s.sn > 0;
+        const bool useful = sh.join ? both : true;
+        if (rows <= (uint64_t)LEAF_CAP) {
+            const bool adjacent = cl_open && cl_cur.buf == s.buf && cl_cur.r0 + cl_cur.rn == s.r0 &&
+                                  (!sh.join || cl_cur.s0 + cl_cur.sn == s.s0) &&
+                                  cl_cur.rn + cl_cur.sn + rows <= (uint64_t)LEAF_CAP;
+            if (!adjacent) {
+                classify_flush(out_delta);
+                cl_open = true;
+                cl_cur = LeafDesc{};
+                cl_cur.r0 = s.r0;
+                cl_cur.s0 = s.s0;
+                cl_cur.buf = s.buf;
+                cl_lo = s.lo;
+                cl_hi = s.hi;
+            }
+            cl_cur.rn += (uint32_t)s.rn;
+            cl_cur.sn += (uint32_t)s.sn;
+            cl_lo = std::min(cl_lo, s.lo);
+            cl_hi = std::max(cl_hi, s.hi);
+            cl_useful = cl_useful || useful;
+            return;
+        }
+        classify_flush(out_delta);
+        if (sh.join && !both) return;  // no partner rows: no output
+        if (single) {
+            stats.single_key++;
+            if (sh.join) {
+                CrossDesc c{};
+                c.r0 = s.r0;
+                c.s0 = s.s0;
+                c.a = s.rn;
+                c.b = s.sn;
+                c.buf = s.buf;
+                crosses.push_back(c);
+            } else if (!(out_is_a && s.buf == BUF_A && out_delta == 0)) {
+                CopyDesc c{};
+                c.start = s.r0;
+                c.len = s.rn;
+                c.out = s.r0 + out_delta;
+                c.buf = s.buf;
+                copies.push_back(c);
+            }
+            return;
+        }
+        next.push_back(s);
     }
 
     // ---- process one key range (the whole domain when the budget does not bind)
@@ -560,23 +631,25 @@ struct Exec {
         root.lo = lo;
         root.hi = hi;
         root.buf = BUF_IN;
-        std::vector<Seg> level, next;
+        std::vector<Seg> next, next2;
+        auto to_next = [&](const Seg& c) { classify_one(c, next, out_delta); };
         if (filtered) {
             // first pass: compaction + split of the range's rows out of the input
             const uint64_t f[2] = {lo, hi};
             std::vector<Seg> roots{root};
-            TJ_RET(run_pass(roots, BUF_IN, BUF_A, f, level));
+            TJ_RET(run_pass(roots, BUF_IN, BUF_A, f, to_next));
         } else {
-            level.push_back(root);
+            classify_one(root, next, out_delta);
         }
+        classify_flush(out_delta);
         uint32_t cur = filtered ? (uint32_t)BUF_A : (uint32_t)BUF_IN;
         for (int depth = 0; depth < 80; depth++) {
-            next.clear();
-            classify(level, next, out_delta);
             if (next.empty()) return TJ_OK;
             const uint32_t dst = cur == BUF_A ? (uint32_t)BUF_B : (uint32_t)BUF_A;
-            level.clear();
-            TJ_RET(run_pass(next, cur, dst, nullptr, level));
+            next2.clear();
+            TJ_RET(run_pass(next, cur, dst, nullptr, [&](const Seg& c) { classify_one(c, next2, out_delta); }));
+            classify_flush(out_delta);
+            next.swap(next2);
             cur = dst;
         }
         return TJ_E_INTERNAL;
@@ -585,10 +658,13 @@ struct Exec {
     // ---- leaves and singles ---------------------------------------------
     int run_sort_leaves(void* out_k, int32_t* out_r)
     {
+        HostTimer ht(this, F_HOST_LEAVES);
         for (int wide = 0; wide < 2; wide++) {
-            std::vector<LeafDesc> sel;
+            std::vector<LeafDesc>& sel = hv.batch_leaves;
+            sel.clear();
             for (const LeafDesc& L : leaves)
                 if ((L.bits > 32) == (wide == 1)) sel.push_back(L);
+            ht.stop();
             for (size_t i = 0; i < sel.size(); i += caps.leaves) {
                 const uint32_t n = (uint32_t)std::min<size_t>(caps.leaves, sel.size() - i);
                 TJ_CK(hipMemcpyAsync(d_leaves, sel.data() + i, n * sizeof(LeafDesc), hipMemcpyHostToDevice, st));
@@ -622,7 +698,6 @@ struct Exec {
             TJ_CK(hipStreamSynchronize(st));
         }
         leaves.clear();
-        leaf_lo.clear();
         copies.clear();
         return TJ_OK;
     }
@@ -635,6 +710,7 @@ struct Exec {
     int finish_join(uint64_t* total_out, uint64_t base, int32_t* out_r, int32_t* out_s,
                     uint64_t capacity, bool mat)
     {
+        HostTimer ht(this, F_HOST_LEAVES);
         auto lr0 = [](const LeafDesc& a, const LeafDesc& b) { return a.r0 < b.r0; };
         auto cr0 = [](const CrossDesc& a, const CrossDesc& b) { return a.r0 < b.r0; };
         if (!std::is_sorted(leaves.begin(), leaves.end(), lr0)) std::sort(leaves.begin(), leaves.end(), lr0);
@@ -652,6 +728,7 @@ struct Exec {
         if (!mat) {
             uint64_t cross_pairs = 0;
             for (const CrossDesc& c : crosses) cross_pairs += c.a * c.b;
+            ht.stop();
             TJ_CK(launch_fill_u64(d_total, 1, 0, st));
             for (size_t i = 0; i < leaves.size(); i += caps.leaves) {
                 const uint32_t n = (uint32_t)std::min<size_t>(caps.leaves, leaves.size() - i);
@@ -671,8 +748,8 @@ struct Exec {
         } else {
             uint64_t carry = base;
             size_t li = 0, ci = 0;
-            std::vector<LeafDesc> bl;
-            std::vector<CrossDesc> bc;
+            std::vector<LeafDesc>& bl = hv.batch_leaves;
+            std::vector<CrossDesc>& bc = hv.batch_crosses;
             while (li < leaves.size() || ci < crosses.size()) {
                 bl.clear();
                 bc.clear();
@@ -696,6 +773,7 @@ struct Exec {
                     }
                 }
                 const uint32_t nl = (uint32_t)bl.size(), nc = (uint32_t)bc.size();
+                ht.stop();
                 TJ_CK(launch_fill_u64(d_status, 1, STATUS_INCLUSIVE | carry, st));
                 TJ_CK(launch_fill_u64(d_status + 1, nl, 0, st));
                 TJ_CK(launch_fill_u64(d_probe + 3, 1, 0, st));  // ticket and error flag
@@ -739,9 +817,7 @@ struct Exec {
             stats.bytes_written += written * 8;
         }
         leaves.clear();
-        leaf_lo.clear();
         crosses.clear();
-        cross_lo.clear();
         return TJ_OK;
     }
 
@@ -761,7 +837,7 @@ struct Exec {
             root.lo = root.hi = k;
             root.buf = BUF_IN;
             if (side == 0) root.rn = a; else root.sn = b;
-            std::vector<Seg> roots{root}, kids;
+            std::vector<Seg> roots{root};
             const uint64_t f[2] = {k, k};
             // only the requested side is scanned: zero the other's input length
             const uint64_t keep_r = sh.n_r, keep_s = sh.n_s;
@@ -775,7 +851,7 @@ struct Exec {
                 bufs.rid[BUF_A][0] = dst;
                 sh.n_r = keep_s;
             }
-            int rc = run_pass(roots, BUF_IN, BUF_A, f, kids);
+            int rc = run_pass(roots, BUF_IN, BUF_A, f, [](const Seg&) {});  // children unused
             sh.n_r = keep_r;
             sh.n_s = keep_s;
             sh.join = keep_join;
@@ -1157,9 +1233,8 @@ int tj_sort(int key_type, const void* keys_in, const int32_t* rids_in, uint64_t 
                 x.bufs.rid[BUF_A][0] = rids_out + out_row;
                 const Exec::Range rr = r;
                 std::vector<Seg> roots{Seg{0, rr.rn, 0, 0, rr.lo, rr.hi, BUF_IN}};
-                std::vector<Seg> kids;
                 const uint64_t f[2] = {rr.lo, rr.hi};
-                TJ_RET(x.run_pass(roots, BUF_IN, BUF_A, f, kids));
+                TJ_RET(x.run_pass(roots, BUF_IN, BUF_A, f, [](const Seg&) {}));  // children unused
                 x.bufs = saved;
                 x.stats.single_key++;
             } else {

@@ -159,6 +159,15 @@ struct Seg {
     uint64_t r0, rn, s0, sn;  // row ranges (side 0, side 1)
     uint64_t lo, hi;          // ordinal range present (lo > hi: no rows)
     uint32_t buf;
+    uint32_t kb = 0;          // key bytes of the rows in `buf`
+    // Narrowed keys (kb 4 of an int64 input) hold ord - win; win is the
+    // original ordinal of their 2^32-aligned window. ~0: keys are not narrowed.
+    uint64_t win = ~0ull;
+    // Row i's key sits at index i + koff of its side's key array. Narrowed
+    // keys use koff = first row of the bucket that narrowed them, which keeps
+    // them (4 bytes at index i + koff) inside that bucket's 8-byte footprint,
+    // away from the 8-byte keys of other buckets in the same buffer.
+    uint64_t koff_r = 0, koff_s = 0;
 };
 
 struct Unit {                 // a final piece of join output, ordered by key
@@ -387,7 +396,7 @@ struct Exec {
         const int nside = sh.join ? 2 : 1;
         // per segment digit choice
         struct Plan {
-            uint32_t shift, bits;
+            uint32_t shift, bits, kb_out;
         };
         std::vector<Plan> plan(segs.size());
         uint64_t total_rows = 0;
@@ -401,6 +410,9 @@ struct Exec {
             if (b == 0) b = 1;  // filtered roots of a single-key range still need a compaction pass
             plan[i].bits = b;
             plan[i].shift = kbits > b ? kbits - b : 0;
+            // join keys are narrowed to 4 bytes once every child spans at most
+            // 2^32 ordinals; the sort writes its keys out and never narrows
+            plan[i].kb_out = sh.join && write_keys && s.kb == 8 && plan[i].shift <= 32 ? 4u : s.kb;
             total_rows += filter ? (uint64_t)(i == 0 ? sh.n_r + sh.n_s : 0) : rows;
         }
         uint64_t ch_rows = align_up((total_rows + TARGET_CHUNKS - 1) / TARGET_CHUNKS, PART_TILE);
@@ -424,9 +436,11 @@ struct Exec {
             gseg.clear();
             uint32_t child = 0;
             const size_t first = si;
-            // fill one launch batch
+            // fill one launch batch (all of its segments share both key widths)
+            const uint32_t kb_in = segs[si].kb, kb_out = plan[si].kb_out;
             while (si < segs.size()) {
                 const Seg& s = segs[si];
+                if (s.kb != kb_in || plan[si].kb_out != kb_out) break;
                 uint64_t need_chunks = 0, need_cb = 0;
                 for (int side = 0; side < nside; side++) {
                     const uint64_t len = filter ? (side ? sh.n_s : sh.n_r) : (side ? s.sn : s.rn);
@@ -458,6 +472,8 @@ struct Exec {
                     g.cblock0 = (uint32_t)cblocks.size();
                     g.child0 = child;
                     child += 1u << g.bits;
+                    g.src_koff = filter ? 0 : (side ? s.koff_s : s.koff_r);
+                    g.dst_koff = kb_out < kb_in ? g.dst_start : g.src_koff;
                     const uint32_t gi = (uint32_t)groups.size();
                     for (uint64_t c0 = 0; c0 < len; c0 += ch_rows) {
                         ChunkDesc c{};
@@ -478,8 +494,8 @@ struct Exec {
                     g.ncblocks = (uint32_t)cblocks.size() - g.cblock0;
                     groups.push_back(g);
                     gseg.push_back(si);
-                    stats.bytes_read += len * (uint64_t)sh.kb;                                   // histogram
-                    stats.bytes_read += len * (uint64_t)sh.kb + (sh.rids ? len * 4 : 0);         // scatter
+                    stats.bytes_read += len * (uint64_t)kb_in;                                   // histogram
+                    stats.bytes_read += len * (uint64_t)kb_in + (sh.rids ? len * 4 : 0);         // scatter
                 }
                 si++;
             }
@@ -496,15 +512,15 @@ struct Exec {
                 const Seg& s = segs[gseg[&g - groups.data()]];
                 moved += g.side ? s.sn : s.rn;
             }
-            const uint64_t rb = row_bytes(sh.kb, sh.rids), wb = (write_keys ? sh.kb : 0) + (sh.rids ? 4 : 0);
-            TJ_CK(timed(F_HIST, scanned * sh.kb, [&] {
-                return launch_hist(sh.kb, d_chunks, nc, d_groups, bufs, d_hist, d_gmin, d_gmax, st);
+            const uint64_t rb = row_bytes((int)kb_in, sh.rids), wb = (write_keys ? kb_out : 0) + (sh.rids ? 4 : 0);
+            TJ_CK(timed(F_HIST, scanned * kb_in, [&] {
+                return launch_hist((int)kb_in, d_chunks, nc, d_groups, bufs, d_hist, d_gmin, d_gmax, st);
             }));
             TJ_CK(timed(F_SCAN, 0, [&] {
                 return launch_scan(d_cblocks, ncb, d_groups, ng, d_hist, d_cbsum, d_ccount, d_cstart, st);
             }));
             TJ_CK(timed(F_SCATTER, scanned * rb + moved * wb, [&] {
-                return launch_scatter(sh.kb, sh.rids, write_keys, d_chunks, nc, d_groups, d_hist, d_cbsum,
+                return launch_scatter((int)kb_in, (int)kb_out, sh.rids, write_keys, d_chunks, nc, d_groups, d_hist, d_cbsum,
                                       d_cstart, bufs, st);
             }));
             // one compact record per child (both sides folded), read back pinned
@@ -522,23 +538,37 @@ struct Exec {
                 const GroupDesc& g0 = groups[gi];
                 const uint32_t nbins = 1u << g0.bits;
                 const ChildRec* cr = rec + g0.child0 / (uint32_t)nside;
+                const uint64_t parent_win = segs[gseg[gi]].win;
+                const bool narrowing = kb_out < kb_in;
+                const uint64_t koff_r = g0.dst_koff, koff_s = nside == 2 ? groups[gi + 1].dst_koff : 0;
                 uint64_t r0 = g0.dst_start, s0 = nside == 2 ? groups[gi + 1].dst_start : 0;
                 for (uint32_t d = 0; d < nbins; d++) {
                     Seg c;
                     c.buf = dst;
+                    c.kb = kb_out;
                     c.r0 = r0;
                     c.rn = cr[d].rn;
                     c.s0 = s0;
                     c.sn = cr[d].sn;
                     c.lo = cr[d].lo;
                     c.hi = cr[d].hi;
+                    c.win = parent_win;
+                    c.koff_r = koff_r;
+                    c.koff_s = koff_s;
+                    if (narrowing && c.lo <= c.hi) {
+                        // keys now hold (ord - g.base) mod 2^32 (see k_scatter)
+                        const uint64_t off = c.lo - g0.base;
+                        c.win = g0.base + (off & ~0xffffffffull);
+                        c.lo = off & 0xffffffffull;
+                        c.hi = (c.hi - g0.base) & 0xffffffffull;
+                    }
                     r0 += c.rn;
                     s0 += c.sn;
                     moved_rows += c.rn + c.sn;
                     sink(c);
                 }
             }
-            stats.bytes_written += moved_rows * row_bytes(sh.kb, sh.rids);
+            stats.bytes_written += moved_rows * row_bytes((int)kb_out, sh.rids);
             (void)first;
         }
         return TJ_OK;
@@ -552,13 +582,15 @@ struct Exec {
     // leaf at the end of a level.
     bool cl_open = false, cl_useful = false;
     LeafDesc cl_cur{};
-    uint64_t cl_lo = 0, cl_hi = 0;
+    uint64_t cl_lo = 0, cl_hi = 0, cl_win = 0;
+    uint32_t cl_kb = 0;
 
     void classify_flush(uint64_t out_delta)
     {
         if (cl_open && cl_useful) {
             cl_cur.base = cl_lo;
-            cl_cur.bits = nbits64(cl_hi - cl_lo);
+            cl_cur.bits = (uint16_t)nbits64(cl_hi - cl_lo);
+            cl_cur.kb = (uint16_t)cl_kb;
             cl_cur.out = sh.join ? 0 : cl_cur.r0 + out_delta;
             leaves.push_back(cl_cur);
         }
@@ -574,7 +606,9 @@ struct Exec {
         const bool both = s.rn > 0 && s.sn > 0;
         const bool useful = sh.join ? both : true;
         if (rows <= (uint64_t)LEAF_CAP) {
-            const bool adjacent = cl_open && cl_cur.buf == s.buf && cl_cur.r0 + cl_cur.rn == s.r0 &&
+            const bool adjacent = cl_open && cl_cur.buf == s.buf && cl_kb == s.kb && cl_win == s.win &&
+                                  cl_cur.kr0 - cl_cur.r0 == s.koff_r && cl_cur.ks0 - cl_cur.s0 == s.koff_s &&
+                                  cl_cur.r0 + cl_cur.rn == s.r0 &&
                                   (!sh.join || cl_cur.s0 + cl_cur.sn == s.s0) &&
                                   cl_cur.rn + cl_cur.sn + rows <= (uint64_t)LEAF_CAP;
             if (!adjacent) {
@@ -583,9 +617,13 @@ struct Exec {
                 cl_cur = LeafDesc{};
                 cl_cur.r0 = s.r0;
                 cl_cur.s0 = s.s0;
+                cl_cur.kr0 = s.r0 + s.koff_r;
+                cl_cur.ks0 = s.s0 + s.koff_s;
                 cl_cur.buf = s.buf;
                 cl_lo = s.lo;
                 cl_hi = s.hi;
+                cl_kb = s.kb;
+                cl_win = s.win;
             }
             cl_cur.rn += (uint32_t)s.rn;
             cl_cur.sn += (uint32_t)s.sn;
@@ -624,6 +662,7 @@ struct Exec {
                       uint64_t out_delta)
     {
         Seg root{};
+        root.kb = (uint32_t)sh.kb;
         root.r0 = 0;
         root.rn = rn;
         root.s0 = 0;
@@ -715,12 +754,6 @@ struct Exec {
         auto cr0 = [](const CrossDesc& a, const CrossDesc& b) { return a.r0 < b.r0; };
         if (!std::is_sorted(leaves.begin(), leaves.end(), lr0)) std::sort(leaves.begin(), leaves.end(), lr0);
         if (!std::is_sorted(crosses.begin(), crosses.end(), cr0)) std::sort(crosses.begin(), crosses.end(), cr0);
-        bool wide = false;
-        uint64_t leaf_rows = 0;
-        for (const LeafDesc& L : leaves) {
-            wide = wide || L.bits > 32;
-            leaf_rows += L.rn + L.sn;
-        }
         stats.leaves += (uint32_t)leaves.size();
         uint64_t* d_total = d_probe + 2;
         uint32_t* d_ticket = (uint32_t*)(d_probe + 3);
@@ -730,20 +763,33 @@ struct Exec {
             for (const CrossDesc& c : crosses) cross_pairs += c.a * c.b;
             ht.stop();
             TJ_CK(launch_fill_u64(d_total, 1, 0, st));
-            for (size_t i = 0; i < leaves.size(); i += caps.leaves) {
-                const uint32_t n = (uint32_t)std::min<size_t>(caps.leaves, leaves.size() - i);
-                uint64_t rows = 0;
-                for (uint32_t k = 0; k < n; k++) rows += leaves[i + k].rn + leaves[i + k].sn;
-                TJ_CK(hipMemcpyAsync(d_leaves, leaves.data() + i, n * sizeof(LeafDesc), hipMemcpyHostToDevice, st));
-                TJ_CK(timed(F_LEAF_COUNT, rows * sh.kb, [&] {
-                    return launch_leaf_join(sh.kb, wide, false, d_leaves, n, bufs, d_status, d_ticket, d_total,
-                                            d_err, nullptr, nullptr, 0, st);
-                }));
+            // leaves grouped by key width (order does not matter for a count)
+            for (int kb : {8, 4}) {
+                std::vector<LeafDesc>& sel = hv.batch_leaves;
+                sel.clear();
+                for (size_t i = 0; i < leaves.size(); i++)
+                    if (leaves[i].kb == kb) sel.push_back(leaves[i]);
+                for (size_t i = 0; i < sel.size(); i += caps.leaves) {
+                    const uint32_t n = (uint32_t)std::min<size_t>(caps.leaves, sel.size() - i);
+                    uint64_t rows = 0;
+                    bool wide = false;
+                    for (uint32_t k = 0; k < n; k++) {
+                        rows += sel[i + k].rn + sel[i + k].sn;
+                        wide = wide || sel[i + k].bits > 32;
+                    }
+                    TJ_CK(hipMemcpyAsync(d_leaves, sel.data() + i, n * sizeof(LeafDesc), hipMemcpyHostToDevice, st));
+                    TJ_CK(timed(F_LEAF_COUNT, rows * kb, [&] {
+                        return launch_leaf_join(kb, wide, false, d_leaves, n, bufs, d_status, d_ticket, d_total,
+                                                d_err, nullptr, nullptr, 0, st);
+                    }));
+                    stats.bytes_read += rows * kb;
+                    // the selection buffer is refilled for the next width: wait for the upload
+                    TJ_CK(hipStreamSynchronize(st));
+                }
             }
             uint64_t t = 0;
             TJ_CK(hipMemcpyAsync(&t, d_total, 8, hipMemcpyDeviceToHost, st));
             TJ_CK(hipStreamSynchronize(st));
-            stats.bytes_read += leaf_rows * sh.kb;
             *total_out = t + cross_pairs;
         } else {
             uint64_t carry = base;
@@ -754,6 +800,7 @@ struct Exec {
                 bl.clear();
                 bc.clear();
                 uint64_t pre = 0;  // single-key pairs of this batch so far
+                int bkb = 0;       // key width of the batch's leaves
                 while (li < leaves.size() || ci < crosses.size()) {
                     const bool take_cross =
                         ci < crosses.size() && (li == leaves.size() || crosses[ci].r0 < leaves[li].r0);
@@ -767,6 +814,8 @@ struct Exec {
                         bc.push_back(c);
                     } else {
                         if (bl.size() == caps.leaves) break;
+                        if (bkb != 0 && leaves[li].kb != bkb) break;  // one launch, one key width
+                        bkb = leaves[li].kb;
                         LeafDesc L = leaves[li++];
                         L.out = pre;
                         bl.push_back(L);
@@ -780,14 +829,18 @@ struct Exec {
                 size_t leaf_timer = (size_t)-1;
                 if (nl) {
                     uint64_t rows = 0;
-                    for (const LeafDesc& L : bl) rows += L.rn + L.sn;
+                    bool wide = false;
+                    for (const LeafDesc& L : bl) {
+                        rows += L.rn + L.sn;
+                        wide = wide || L.bits > 32;
+                    }
                     leaf_timer = pending.size();
                     TJ_CK(hipMemcpyAsync(d_leaves, bl.data(), nl * sizeof(LeafDesc), hipMemcpyHostToDevice, st));
-                    TJ_CK(timed(F_LEAF_MAT, rows * row_bytes(sh.kb, true), [&] {
-                        return launch_leaf_join(sh.kb, wide, true, d_leaves, nl, bufs, d_status, d_ticket,
+                    TJ_CK(timed(F_LEAF_MAT, rows * row_bytes(bkb, true), [&] {
+                        return launch_leaf_join(bkb, wide, true, d_leaves, nl, bufs, d_status, d_ticket,
                                                 d_total, d_err, out_r, out_s, capacity, st);
                     }));
-                    stats.bytes_read += rows * row_bytes(sh.kb, true);
+                    stats.bytes_read += rows * row_bytes(bkb, true);
                 }
                 if (nc) {
                     uint64_t t = 0, in_rows = 0;
@@ -834,6 +887,7 @@ struct Exec {
         auto compact = [&](int side, int32_t* dst) -> int {
             bufs.rid[BUF_A][side] = dst;
             Seg root{};
+            root.kb = (uint32_t)sh.kb;
             root.lo = root.hi = k;
             root.buf = BUF_IN;
             if (side == 0) root.rn = a; else root.sn = b;
@@ -958,8 +1012,10 @@ struct Exec {
         const uint32_t nbins = 1u << bits;
         auto bin_lo = [&](uint32_t d) { return lo + ((uint64_t)d << shift); };
         auto bin_hi = [&](uint32_t d) {
-            const uint64_t e = lo + (((uint64_t)d + 1) << shift) - 1;
-            return std::min(e, hi);
+            // last offset of bin d, formed without passing 2^64 (the top bin of
+            // a full-width key range ends exactly there)
+            const uint64_t off = ((uint64_t)d << shift) + ((1ull << shift) - 1);
+            return off >= hi - lo ? hi : lo + off;
         };
         bool open = false;
         Range cur{};
@@ -1232,7 +1288,7 @@ int tj_sort(int key_type, const void* keys_in, const int32_t* rids_in, uint64_t 
                 x.bufs.key[BUF_A][0] = (char*)keys_out + out_row * (uint64_t)key_type;
                 x.bufs.rid[BUF_A][0] = rids_out + out_row;
                 const Exec::Range rr = r;
-                std::vector<Seg> roots{Seg{0, rr.rn, 0, 0, rr.lo, rr.hi, BUF_IN}};
+                std::vector<Seg> roots{Seg{0, rr.rn, 0, 0, rr.lo, rr.hi, BUF_IN, (uint32_t)key_type}};
                 const uint64_t f[2] = {rr.lo, rr.hi};
                 TJ_RET(x.run_pass(roots, BUF_IN, BUF_A, f, [](const Seg&) {}));  // children unused
                 x.bufs = saved;
@@ -1398,7 +1454,7 @@ int tj_debug_partition_pass(const int64_t* keys, const int32_t* rids, uint64_t n
     TJ_CK(launch_fill_u64(x.d_gmax, 1u << bits, 0ull, st));
     TJ_CK(launch_hist(8, x.d_chunks, g.nchunks, x.d_groups, x.bufs, x.d_hist, x.d_gmin, x.d_gmax, st));
     TJ_CK(launch_scan(x.d_cblocks, g.ncblocks, x.d_groups, 1, x.d_hist, x.d_cbsum, x.d_ccount, x.d_cstart, st));
-    TJ_CK(launch_scatter(8, true, true, x.d_chunks, g.nchunks, x.d_groups, x.d_hist, x.d_cbsum, x.d_cstart, x.bufs, st));
+    TJ_CK(launch_scatter(8, 8, true, true, x.d_chunks, g.nchunks, x.d_groups, x.d_hist, x.d_cbsum, x.d_cstart, x.bufs, st));
     TJ_CK(hipMemcpyAsync(counts_out, x.d_ccount, (1u << bits) * 4ull, hipMemcpyDeviceToDevice, st));
     TJ_CK(hipStreamSynchronize(st));
     return TJ_OK;

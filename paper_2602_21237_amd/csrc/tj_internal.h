@@ -53,16 +53,22 @@ struct GroupDesc {
     uint32_t cblock0, ncblocks;
     uint32_t child0;     // first entry of this group's children in the packed child tables
     uint32_t pad[2];
+    // Key arrays are addressed at (row + koff). Keys narrowed to 4 bytes are
+    // kept inside the byte footprint of the 8-byte keys of the bucket that
+    // narrowed them: koff = that bucket's first row (see the planner).
+    uint64_t src_koff, dst_koff;
 };
 
 // One per-bucket LDS block: a run of adjacent final buckets of one level.
 struct LeafDesc {
     uint64_t r0, s0;     // first row of each side in the buffer
+    uint64_t kr0, ks0;   // index of the first row's key in each side's key array
     uint64_t base;       // ordinal subtracted before sorting inside the block
     uint64_t out;        // sort: output index of the first row; join: range base + pairs of
                          // the single-key units before this block in key order
     uint32_t rn, sn;     // rows per side (sn = 0 for the sort)
-    uint32_t bits;       // significant bits of (ord - base) over the block's rows
+    uint16_t bits;       // significant bits of (ord - base) over the block's rows
+    uint16_t kb;         // key bytes of the rows in the buffer (host bookkeeping)
     uint32_t buf;        // buffer holding the rows
 };
 
@@ -114,9 +120,10 @@ hipError_t launch_hist(int key_bytes, const ChunkDesc* chunks, uint32_t nchunks,
 hipError_t launch_scan(const CBlockDesc* cblocks, uint32_t ncblocks, const GroupDesc* groups,
                        uint32_t ngroups, uint32_t* hist, uint32_t* cbsum, uint32_t* ccount,
                        uint64_t* cstart, hipStream_t st);
-hipError_t launch_scatter(int key_bytes, bool rids, bool keys, const ChunkDesc* chunks, uint32_t nchunks,
-                          const GroupDesc* groups, const uint32_t* hist, const uint32_t* cbsum,
-                          const uint64_t* cstart, BufSet bufs, hipStream_t st);
+// out_key_bytes < key_bytes (8 -> 4) writes narrowed keys (see k_scatter).
+hipError_t launch_scatter(int key_bytes, int out_key_bytes, bool rids, bool keys, const ChunkDesc* chunks,
+                          uint32_t nchunks, const GroupDesc* groups, const uint32_t* hist,
+                          const uint32_t* cbsum, const uint64_t* cstart, BufSet bufs, hipStream_t st);
 // Folds each segment's per-side child tables into ChildRec records, written at
 // group.child0 / nside (groups come in side order per segment).
 hipError_t launch_children(const GroupDesc* groups, uint32_t ngroups, int nside,

@@ -378,7 +378,7 @@ __global__ __launch_bounds__(PART_THREADS) void k_hist(const ChunkDesc* __restri
     __shared__ uint64_t mn[NB], mx[NB];
     const ChunkDesc ch = chunks[blockIdx.x];
     const GroupDesc g = groups[ch.group];
-    const K* __restrict__ src = (const K*)bufs.key[g.src][g.side] + ch.start;
+    const K* __restrict__ src = (const K*)bufs.key[g.src][g.side] + g.src_koff + ch.start;
     const uint32_t nbins = 1u << g.bits;
     for (uint32_t d = threadIdx.x; d < nbins; d += PART_THREADS) {
         cnt[d] = 0;
@@ -574,12 +574,18 @@ hipError_t launch_scan(const CBlockDesc* cblocks, uint32_t ncblocks, const Group
 // flight. Wave w of the tile owns rows [w*SC_KI*64, (w+1)*SC_KI*64); round r
 // of a wave covers 64 consecutive rows, so (wave, round, lane) is input order
 // and the partition is stable.
+// KO is the written key type. KO = int32 with K = int64 narrows the keys: a
+// row is written as the low 32 bits of (ord - g.base), stored so that ord_of
+// of the stored int32 gives them back. Every child of such a pass spans at
+// most 2^32 ordinals and lies inside one window g.base + [j*2^32, (j+1)*2^32),
+// so inside a child (and among children of one window) the narrowed keys
+// order as the originals.
 // ---------------------------------------------------------------------------
 constexpr int SC_NT = 1024, SC_KI = 8, SC_NW = SC_NT / 64, SC_TILE = SC_NT * SC_KI;
 constexpr int SC_STRIDE = NB + 1;
 static_assert(SC_TILE == PART_TILE, "chunk sizes are planned in scatter tiles");
 
-template <typename K, bool RIDS, bool WKEYS>
+template <typename K, typename KO, bool RIDS, bool WKEYS>
 __global__ __launch_bounds__(SC_NT) void k_scatter(const ChunkDesc* __restrict__ chunks,
                                                    const GroupDesc* __restrict__ groups,
                                                    const uint32_t* __restrict__ hist,
@@ -596,9 +602,9 @@ __global__ __launch_bounds__(SC_NT) void k_scatter(const ChunkDesc* __restrict__
 
     const ChunkDesc ch = chunks[blockIdx.x];
     const GroupDesc g = groups[ch.group];
-    const K* __restrict__ src_k = (const K*)bufs.key[g.src][g.side] + ch.start;
+    const K* __restrict__ src_k = (const K*)bufs.key[g.src][g.side] + g.src_koff + ch.start;
     const int32_t* __restrict__ src_r = bufs.rid[g.src][g.side] + ch.start;
-    K* __restrict__ dst_k = (K*)bufs.key[g.dst][g.side];
+    KO* __restrict__ dst_k = (KO*)bufs.key[g.dst][g.side] + g.dst_koff;
     int32_t* __restrict__ dst_r = (int32_t*)bufs.rid[g.dst][g.side];
     const uint32_t nbins = 1u << g.bits, mask = nbins - 1u;
     const uint32_t w = threadIdx.x / 64, l = threadIdx.x & 63;
@@ -659,29 +665,36 @@ __global__ __launch_bounds__(SC_NT) void k_scatter(const ChunkDesc* __restrict__
             const K k = skey[p];
             const uint32_t d = (uint32_t)((ord_of(k) - g.base) >> g.shift) & mask;
             const uint32_t dst = delta[d] + p;
-            if (WKEYS) dst_k[dst] = k;
+            if (WKEYS) {
+                if (sizeof(KO) == sizeof(K)) dst_k[dst] = (KO)k;
+                else dst_k[dst] = (KO)((uint32_t)(ord_of(k) - g.base) ^ 0x80000000u);
+            }
             if (RIDS) dst_r[dst] = srid[p];
         }
         lds_barrier();
     }
 }
 
-hipError_t launch_scatter(int key_bytes, bool rids, bool keys, const ChunkDesc* chunks, uint32_t nchunks,
-                          const GroupDesc* groups, const uint32_t* hist, const uint32_t* cbsum,
-                          const uint64_t* cstart, BufSet bufs, hipStream_t st)
+hipError_t launch_scatter(int key_bytes, int out_key_bytes, bool rids, bool keys, const ChunkDesc* chunks,
+                          uint32_t nchunks, const GroupDesc* groups, const uint32_t* hist,
+                          const uint32_t* cbsum, const uint64_t* cstart, BufSet bufs, hipStream_t st)
 {
     if (nchunks == 0) return hipSuccess;
+    if (out_key_bytes > key_bytes) return hipErrorInvalidValue;
     const dim3 grid(nchunks), block(SC_NT);
-#define TJ_SC(K, R, W)                                                                               \
-    hipLaunchKernelGGL((k_scatter<K, R, W>), grid, block, 0, st, chunks, groups, hist, cbsum, cstart, bufs)
+#define TJ_SC(K, KO, R, W)                                                                           \
+    hipLaunchKernelGGL((k_scatter<K, KO, R, W>), grid, block, 0, st, chunks, groups, hist, cbsum, cstart, bufs)
     if (key_bytes == 4) {
-        if (!keys) TJ_SC(int32_t, true, false);
-        else if (rids) TJ_SC(int32_t, true, true);
-        else TJ_SC(int32_t, false, true);
+        if (!keys) TJ_SC(int32_t, int32_t, true, false);
+        else if (rids) TJ_SC(int32_t, int32_t, true, true);
+        else TJ_SC(int32_t, int32_t, false, true);
+    } else if (out_key_bytes == 8 || !keys) {
+        if (!keys) TJ_SC(int64_t, int64_t, true, false);
+        else if (rids) TJ_SC(int64_t, int64_t, true, true);
+        else TJ_SC(int64_t, int64_t, false, true);
     } else {
-        if (!keys) TJ_SC(int64_t, true, false);
-        else if (rids) TJ_SC(int64_t, true, true);
-        else TJ_SC(int64_t, false, true);
+        if (rids) TJ_SC(int64_t, int32_t, true, true);
+        else TJ_SC(int64_t, int32_t, false, true);
     }
 #undef TJ_SC
     return hipGetLastError();
@@ -908,7 +921,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_leaf_sort(const LeafDesc* __restr
 
     const LeafDesc L = leaves[blockIdx.x];
     if (L.rn == 0) return;
-    const K* __restrict__ src_k = (const K*)bufs.key[L.buf][0] + L.r0;
+    const K* __restrict__ src_k = (const K*)bufs.key[L.buf][0] + L.kr0;
     const int32_t* __restrict__ src_r = bufs.rid[L.buf][0] + L.r0;
     const uint32_t w = threadIdx.x / 64, l = threadIdx.x & 63;
     KW key[KI];
@@ -1119,8 +1132,8 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_leaf_join(const LeafDesc* __restr
     }
     const LeafDesc L = leaves[li];
     const uint32_t rn = L.rn, n = L.rn + L.sn;
-    const K* __restrict__ rk = (const K*)bufs.key[L.buf][0] + L.r0;
-    const K* __restrict__ sk = (const K*)bufs.key[L.buf][1] + L.s0;
+    const K* __restrict__ rk = (const K*)bufs.key[L.buf][0] + L.kr0;
+    const K* __restrict__ sk = (const K*)bufs.key[L.buf][1] + L.ks0;
     const uint32_t w = threadIdx.x / 64, l = threadIdx.x & 63;
 
     KW key[KI];

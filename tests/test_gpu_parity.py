@@ -210,6 +210,28 @@ def test_join_capacity_contract(tj):
     assert np.array_equal(host(pr), er) and np.array_equal(host(ps), es)
 
 
+@pytest.mark.parametrize("budget", [None, 4 << 20])
+def test_join_mixed_key_widths(tj, budget):
+    """Half the keys spread over the whole int64 range (their first-level
+    buckets are leaves with 8-byte keys), half packed into a 2^36-wide range
+    (one first-level bucket that is split again with keys narrowed to 4 bytes):
+    one call runs leaves of both key widths, in key order."""
+    rng = np.random.default_rng(36)
+    n = 150_000
+    sparse = rng.integers(I64.min, I64.max, n, dtype=np.int64)
+    dense = (rng.integers(0, 1 << 36, n) + (5 << 50)).astype(np.int64)
+    rk = np.concatenate([sparse, dense])
+    rng.shuffle(rk)
+    # S: 70% of its rows match R (some several times), the rest are fresh keys
+    sk = np.concatenate([rng.choice(rk, 2 * n * 7 // 10),
+                         rng.integers(I64.min, I64.max, 2 * n * 3 // 10, dtype=np.int64)])
+    rng.shuffle(sk)
+    rr = rng.permutation(rk.size).astype(np.int32)
+    sr = rng.permutation(sk.size).astype(np.int32)
+    kw = {} if budget is None else {"workspace_bytes": budget}
+    check_join(tj, rk, rr, sk, sr, **kw)
+
+
 def test_join_empty_sides(tj):
     k = dev(np.arange(10, dtype=np.int64))
     z = dev(np.zeros(0, np.int64))

@@ -160,11 +160,15 @@ int tj_version(void);
  *   with ord the order-preserving map of signed keys to unsigned, rows written
  *   to keys_out/rids_out grouped by digit ascending, input order kept within a
  *   digit; counts_out[2^bits] (device, uint32) receives the digit histogram.
- *   bits in [1, 8]; base must be <= every ord(k); shift + bits <= 64.
+ *   bits in [1, 9]; base must be <= every ord(k); shift + bits <= 64.
+ *   flags: 0, or TJ_DEBUG_FORCE_REORDER to make every scatter tile take the
+ *   path that re-ranks it when its first ranking is not in input order (the
+ *   result must not change). Other bits give TJ_E_ARG.
  */
+#define TJ_DEBUG_FORCE_REORDER 1u
 int tj_debug_wave_scan(const uint32_t *in, uint32_t *out, uint64_t n, void *stream);
 int tj_debug_partition_pass(const int64_t *keys, const int32_t *rids, uint64_t n,
-                            uint64_t base, uint32_t shift, uint32_t bits,
+                            uint64_t base, uint32_t shift, uint32_t bits, uint32_t flags,
                             int64_t *keys_out, int32_t *rids_out, uint32_t *counts_out,
                             void *workspace, uint64_t workspace_bytes, void *stream);
 

@@ -1406,12 +1406,13 @@ int tj_join_materialize(int key_type, const void* r_keys, const int32_t* r_rids,
 }
 
 int tj_debug_partition_pass(const int64_t* keys, const int32_t* rids, uint64_t n, uint64_t base,
-                            uint32_t shift, uint32_t bits, int64_t* keys_out, int32_t* rids_out,
-                            uint32_t* counts_out, void* workspace, uint64_t workspace_bytes,
-                            void* stream)
+                            uint32_t shift, uint32_t bits, uint32_t flags, int64_t* keys_out,
+                            int32_t* rids_out, uint32_t* counts_out, void* workspace,
+                            uint64_t workspace_bytes, void* stream)
 {
     if (!keys || !rids || !keys_out || !rids_out || !counts_out || !workspace) return TJ_E_ARG;
-    if (bits < 1 || bits > 8 || shift > 63 || shift + bits > 64) return TJ_E_ARG;
+    if (bits < 1 || bits > (uint32_t)MAX_DIGIT_BITS || shift > 63 || shift + bits > 64) return TJ_E_ARG;
+    if (flags & ~(uint32_t)TJ_DEBUG_FORCE_REORDER) return TJ_E_ARG;
     if (n == 0 || n > kMaxRows) return n ? TJ_E_TOO_LARGE : TJ_E_ARG;
     if ((uintptr_t)workspace % ALIGN) return TJ_E_WORKSPACE;
     Exec x;
@@ -1435,6 +1436,7 @@ int tj_debug_partition_pass(const int64_t* keys, const int32_t* rids, uint64_t n
     g.bits = bits;
     g.src = BUF_IN;
     g.dst = BUF_A;
+    g.flags = (flags & TJ_DEBUG_FORCE_REORDER) ? GROUP_FORCE_REORDER : 0u;
     std::vector<ChunkDesc> chunks;
     uint64_t ch = std::max<uint64_t>(PART_TILE, align_up((n + TARGET_CHUNKS - 1) / TARGET_CHUNKS, PART_TILE));
     while ((n + ch - 1) / ch > x.caps.chunks) ch *= 2;

@@ -39,6 +39,11 @@ struct CBlockDesc {
 };
 
 // One side of one segment being partitioned in a pass.
+// GroupDesc::flags: the scatter writes every tile twice, the second time
+// ranked by ballot match (exercises the path taken when the ranks of a tile
+// come out of input order; used by the self-test hook only).
+constexpr uint32_t GROUP_FORCE_REORDER = 1u;
+
 struct GroupDesc {
     uint64_t start;      // first row scanned in the source array
     uint64_t len;        // rows scanned
@@ -52,7 +57,8 @@ struct GroupDesc {
     uint32_t chunk0, nchunks;
     uint32_t cblock0, ncblocks;
     uint32_t child0;     // first entry of this group's children in the packed child tables
-    uint32_t pad[2];
+    uint32_t flags;      // GROUP_* bits
+    uint32_t pad;
     // Key arrays are addressed at (row + koff). Keys narrowed to 4 bytes are
     // kept inside the byte footprint of the 8-byte keys of the bucket that
     // narrowed them: koff = that bucket's first row (see the planner).

@@ -595,10 +595,13 @@ __global__ __launch_bounds__(SC_NT) void k_scatter(const ChunkDesc* __restrict__
 {
     constexpr int NT = SC_NT, KI = SC_KI, NW = SC_NW, TILE = SC_TILE;
     __shared__ uint32_t cnt[NW * SC_STRIDE];
+    __shared__ uint32_t spare[NT];  // one private counter per thread for rows that take no part
     __shared__ uint32_t run[NB], delta[NB];
     __shared__ uint32_t tmp[NW];
+    __shared__ uint32_t s_unordered;
     __shared__ K skey[TILE];
     __shared__ int32_t srid[RIDS ? TILE : 1];
+    __shared__ uint16_t sidx[TILE];  // the staged row's index inside the tile
 
     const ChunkDesc ch = chunks[blockIdx.x];
     const GroupDesc g = groups[ch.group];
@@ -608,6 +611,16 @@ __global__ __launch_bounds__(SC_NT) void k_scatter(const ChunkDesc* __restrict__
     int32_t* __restrict__ dst_r = (int32_t*)bufs.rid[g.dst][g.side];
     const uint32_t nbins = 1u << g.bits, mask = nbins - 1u;
     const uint32_t w = threadIdx.x / 64, l = threadIdx.x & 63;
+    const bool force_reorder = (g.flags & GROUP_FORCE_REORDER) != 0;
+
+    auto digit_of = [&](K k) { return (uint32_t)((ord_of(k) - g.base) >> g.shift) & mask; };
+    auto write_row = [&](uint32_t dst, K k, int32_t rid) {
+        if (WKEYS) {
+            if (sizeof(KO) == sizeof(K)) dst_k[dst] = (KO)k;
+            else dst_k[dst] = (KO)((uint32_t)(ord_of(k) - g.base) ^ 0x80000000u);
+        }
+        if (RIDS) dst_r[dst] = rid;
+    };
 
     for (uint32_t d = threadIdx.x; d < NB; d += NT)
         run[d] = d < nbins ? (uint32_t)(cstart[g.child0 + d] + cbsum[(uint64_t)ch.cblock * NB + d] +
@@ -632,8 +645,16 @@ __global__ __launch_bounds__(SC_NT) void k_scatter(const ChunkDesc* __restrict__
             dig[r] = val[r] ? (uint32_t)((o - g.base) >> g.shift) & mask : 0u;
         }
         for (uint32_t i = l; i < NB; i += 64) cnt[w * SC_STRIDE + i] = 0;
+        // Rank inside the wave: one LDS atomic per row on the wave's own
+        // counters. The wave issues its rounds in row order; within a round the
+        // hardware applies the lanes that hit one counter in lane order, which
+        // makes the ranks stable. Nothing relies on that order: the write-out
+        // checks it and the tile is written again, ranked by ballots, if a
+        // digit's rows ever come out of input order.
 #pragma unroll
-        for (int r = 0; r < KI; r++) rk[r] = wave_rank(dig[r], val[r], (int)g.bits, &cnt[w * SC_STRIDE]);
+        for (int r = 0; r < KI; r++)
+            rk[r] = atomicAdd(val[r] ? &cnt[w * SC_STRIDE + dig[r]] : &spare[threadIdx.x], 1u);
+        if (threadIdx.x == 0) s_unordered = 0;
         lds_barrier();
         const uint32_t total = scan_counts<NT, NW, NB>(cnt, tmp);
         for (uint32_t d = threadIdx.x; d < NB; d += NT) {
@@ -648,6 +669,7 @@ __global__ __launch_bounds__(SC_NT) void k_scatter(const ChunkDesc* __restrict__
                 const uint32_t p = cnt[w * SC_STRIDE + dig[r]] + rk[r];
                 skey[p] = key[r];
                 if (RIDS) srid[p] = rid[r];
+                sidx[p] = (uint16_t)((w * KI + r) * 64 + l);
             }
         }
         lds_barrier();
@@ -661,17 +683,50 @@ __global__ __launch_bounds__(SC_NT) void k_scatter(const ChunkDesc* __restrict__
                 if (RIDS) rid[r] = q < ch.len ? src_r[q] : 0;
             }
         }
+        bool unordered = false;
         for (uint32_t p = threadIdx.x; p < total; p += NT) {
             const K k = skey[p];
-            const uint32_t d = (uint32_t)((ord_of(k) - g.base) >> g.shift) & mask;
-            const uint32_t dst = delta[d] + p;
-            if (WKEYS) {
-                if (sizeof(KO) == sizeof(K)) dst_k[dst] = (KO)k;
-                else dst_k[dst] = (KO)((uint32_t)(ord_of(k) - g.base) ^ 0x80000000u);
-            }
-            if (RIDS) dst_r[dst] = srid[p];
+            const uint32_t d = digit_of(k);
+            write_row(delta[d] + p, k, RIDS ? srid[p] : 0);
+            // cnt[d] (wave 0's entry) is where digit d starts inside the tile
+            unordered = unordered || (p > cnt[d] && sidx[p - 1] > sidx[p]);
         }
+        if (unordered) s_unordered = 1;
         lds_barrier();
+        if (s_unordered || force_reorder) {
+            // Rare path: rank the tile again by ballot match (from its rows in
+            // the source) and write it over the same destination rows.
+            K k2[KI];
+            int32_t r2[KI];
+#pragma unroll
+            for (int r = 0; r < KI; r++) {
+                const uint32_t q = t0 + (w * KI + r) * 64 + l;
+                k2[r] = q < ch.len ? src_k[q] : K(0);
+                r2[r] = RIDS && q < ch.len ? src_r[q] : 0;
+                const uint64_t o = ord_of(k2[r]);
+                val[r] = q < ch.len && o >= g.flo && o <= g.fhi;
+                dig[r] = val[r] ? (uint32_t)((o - g.base) >> g.shift) & mask : 0u;
+            }
+            for (uint32_t i = l; i < NB; i += 64) cnt[w * SC_STRIDE + i] = 0;
+#pragma unroll
+            for (int r = 0; r < KI; r++) rk[r] = wave_rank(dig[r], val[r], (int)g.bits, &cnt[w * SC_STRIDE]);
+            lds_barrier();
+            scan_counts<NT, NW, NB>(cnt, tmp);  // same counts, so delta[] still holds
+#pragma unroll
+            for (int r = 0; r < KI; r++) {
+                if (val[r]) {
+                    const uint32_t p = cnt[w * SC_STRIDE + dig[r]] + rk[r];
+                    skey[p] = k2[r];
+                    if (RIDS) srid[p] = r2[r];
+                }
+            }
+            lds_barrier();
+            for (uint32_t p = threadIdx.x; p < total; p += NT) {
+                const K k = skey[p];
+                write_row(delta[digit_of(k)] + p, k, RIDS ? srid[p] : 0);
+            }
+            lds_barrier();
+        }
     }
 }
 

@@ -53,7 +53,7 @@ EXPORTS = {
     "tj_timing_read": (ctypes.c_int, [_P, ctypes.c_int]),
     "tj_debug_wave_scan": (ctypes.c_int, [_P, _P, _u64, _P]),
     "tj_debug_partition_pass": (ctypes.c_int, [_P, _P, _u64, _u64, ctypes.c_uint32, ctypes.c_uint32,
-                                               _P, _P, _P, _P, _u64, _P]),
+                                               ctypes.c_uint32, _P, _P, _P, _P, _u64, _P]),
 }
 
 
@@ -238,14 +238,20 @@ def debug_wave_scan(x):
     return out
 
 
-def debug_partition_pass(keys, rids, base: int, shift: int, bits: int, workspace_bytes: int = 64 << 20):
-    """One stable radix partition pass (int64 keys); returns (keys_out, rids_out, counts)."""
+TJ_DEBUG_FORCE_REORDER = 1
+
+
+def debug_partition_pass(keys, rids, base: int, shift: int, bits: int, workspace_bytes: int = 64 << 20,
+                         force_reorder: bool = False):
+    """One stable radix partition pass (int64 keys); returns (keys_out, rids_out, counts).
+    force_reorder sends every tile through the scatter's re-ranking path."""
     torch = _torch()
     ko, ro = torch.empty_like(keys), torch.empty_like(rids)
     counts = torch.empty(1 << bits, dtype=torch.int32, device=keys.device)
     ws = torch.empty(workspace_bytes, dtype=torch.uint8, device=keys.device)
     _check(load().tj_debug_partition_pass(keys.data_ptr(), rids.data_ptr(), keys.numel(), base, shift,
-                                          bits, ko.data_ptr(), ro.data_ptr(), counts.data_ptr(),
+                                          bits, TJ_DEBUG_FORCE_REORDER if force_reorder else 0,
+                                          ko.data_ptr(), ro.data_ptr(), counts.data_ptr(),
                                           ws.data_ptr(), workspace_bytes, _stream(None)),
            "tj_debug_partition_pass")
     return ko, ro, counts

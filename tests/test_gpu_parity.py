@@ -61,13 +61,20 @@ def test_wave_scan_dpp(tj):
     assert np.array_equal(got, exp)
 
 
-@pytest.mark.parametrize("bits,shift", [(8, 0), (8, 12), (3, 40), (1, 5)])
-def test_partition_pass(tj, bits, shift):
+@pytest.mark.parametrize("force_reorder", [False, True])
+@pytest.mark.parametrize("bits,shift,skew", [(8, 0, False), (8, 12, False), (9, 55, False), (3, 40, False),
+                                             (1, 5, False), (9, 55, True), (4, 60, True)])
+def test_partition_pass(tj, bits, shift, skew, force_reorder):
+    """One pass against a stable counting sort. force_reorder makes every tile
+    take the scatter's re-ranking path as well; skew makes most rows share a
+    few digits (long runs inside a tile)."""
     rng = np.random.default_rng(bits * 100 + shift)
     n = 100_003
     k = rng.integers(I64.min, I64.max, n, dtype=np.int64)
+    if skew:
+        k = rng.choice(k[:5], n)
     r = rng.integers(I32.min, I32.max, n, dtype=np.int32)
-    ko, ro, counts = tj.tj.debug_partition_pass(dev(k), dev(r), 0, shift, bits)
+    ko, ro, counts = tj.tj.debug_partition_pass(dev(k), dev(r), 0, shift, bits, force_reorder=force_reorder)
     ordv = k.view(np.uint64) ^ np.uint64(1 << 63)
     digit = ((ordv >> np.uint64(shift)) & np.uint64((1 << bits) - 1)).astype(np.int64)
     order = np.argsort(digit, kind="stable")   # stable counting-sort partition

@@ -166,6 +166,14 @@ int tj_version(void);
  *   result must not change). Other bits give TJ_E_ARG.
  */
 #define TJ_DEBUG_FORCE_REORDER 1u
+/*
+ * tj_debug_set_flags: process-wide self-test switch for every later call.
+ *   TJ_DEBUG_FORCE_REORDER: each partition tile and each join block also runs
+ *   the ballot-ranked path that replaces an atomic-ranked order found out of
+ *   input order; results must not change, only time. 0 turns it off.
+ *   Returns TJ_OK, or TJ_E_ARG for unknown bits.
+ */
+int tj_debug_set_flags(uint32_t flags);
 int tj_debug_wave_scan(const uint32_t *in, uint32_t *out, uint64_t n, void *stream);
 int tj_debug_partition_pass(const int64_t *keys, const int32_t *rids, uint64_t n,
                             uint64_t base, uint32_t shift, uint32_t bits, uint32_t flags,

@@ -24,6 +24,7 @@
 #include "../../include/tj.h"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstring>
 #include <mutex>
@@ -210,6 +211,9 @@ Timing& timing()
     static Timing t;
     return t;
 }
+
+// Process-wide self-test flags (tj_debug_set_flags).
+std::atomic<uint32_t> g_debug_flags{0};
 
 // Host-side lists of one call (see Exec::hv).
 struct HostVecs {
@@ -472,6 +476,7 @@ struct Exec {
                     g.cblock0 = (uint32_t)cblocks.size();
                     g.child0 = child;
                     child += 1u << g.bits;
+                    g.flags = (g_debug_flags.load() & TJ_DEBUG_FORCE_REORDER) ? GROUP_FORCE_REORDER : 0u;
                     g.src_koff = filter ? 0 : (side ? s.koff_s : s.koff_r);
                     g.dst_koff = kb_out < kb_in ? g.dst_start : g.src_koff;
                     const uint32_t gi = (uint32_t)groups.size();
@@ -591,6 +596,7 @@ struct Exec {
             cl_cur.base = cl_lo;
             cl_cur.bits = (uint16_t)nbits64(cl_hi - cl_lo);
             cl_cur.kb = (uint16_t)cl_kb;
+            cl_cur.flags = (g_debug_flags.load() & TJ_DEBUG_FORCE_REORDER) ? LEAF_FORCE_REORDER : 0;
             cl_cur.out = sh.join ? 0 : cl_cur.r0 + out_delta;
             leaves.push_back(cl_cur);
         }
@@ -619,7 +625,7 @@ struct Exec {
                 cl_cur.s0 = s.s0;
                 cl_cur.kr0 = s.r0 + s.koff_r;
                 cl_cur.ks0 = s.s0 + s.koff_s;
-                cl_cur.buf = s.buf;
+                cl_cur.buf = (uint16_t)s.buf;
                 cl_lo = s.lo;
                 cl_hi = s.hi;
                 cl_kb = s.kb;
@@ -1459,6 +1465,13 @@ int tj_debug_partition_pass(const int64_t* keys, const int32_t* rids, uint64_t n
     TJ_CK(launch_scatter(8, 8, true, true, x.d_chunks, g.nchunks, x.d_groups, x.d_hist, x.d_cbsum, x.d_cstart, x.bufs, st));
     TJ_CK(hipMemcpyAsync(counts_out, x.d_ccount, (1u << bits) * 4ull, hipMemcpyDeviceToDevice, st));
     TJ_CK(hipStreamSynchronize(st));
+    return TJ_OK;
+}
+
+int tj_debug_set_flags(uint32_t flags)
+{
+    if (flags & ~(uint32_t)TJ_DEBUG_FORCE_REORDER) return TJ_E_ARG;
+    g_debug_flags.store(flags);
     return TJ_OK;
 }
 

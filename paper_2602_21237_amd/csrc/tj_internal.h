@@ -75,8 +75,14 @@ struct LeafDesc {
     uint32_t rn, sn;     // rows per side (sn = 0 for the sort)
     uint16_t bits;       // significant bits of (ord - base) over the block's rows
     uint16_t kb;         // key bytes of the rows in the buffer (host bookkeeping)
-    uint32_t buf;        // buffer holding the rows
+    uint16_t buf;        // buffer holding the rows
+    uint16_t flags;      // LEAF_* bits
 };
+
+// LeafDesc::flags: the join block sorts its rows a second time with ballot
+// ranking (exercises the path taken when the atomic-ranked order fails its
+// check; set by the self-test hook only).
+constexpr uint16_t LEAF_FORCE_REORDER = 1u;
 
 // A bucket whose rows all hold one key: join output is the full cross product.
 // Its first pair goes to out + (pair prefix of the per-bucket joins before it).

@@ -913,7 +913,10 @@ __device__ __forceinline__ bool block_bin_sort(const KW (&key)[KI], int bits, ui
     return true;
 }
 
-template <typename KW, int NT, int KI>
+// ATOMIC ranks with one LDS atomic per item (in lane order on this hardware,
+// which makes every pass stable); the caller must then check that the result
+// is ordered by (key, idx) and sort again with ATOMIC = false if it is not.
+template <typename KW, int NT, int KI, bool ATOMIC = false>
 __device__ __forceinline__ void block_lsd_sort(KW (&key)[KI], uint16_t (&idx)[KI], int bits,
                                                KW* lds_key, uint16_t* lds_idx, uint32_t* cnt,
                                                uint32_t* tmp, int lo_bit = 0)
@@ -939,8 +942,13 @@ __device__ __forceinline__ void block_lsd_sort(KW (&key)[KI], uint16_t (&idx)[KI
 #pragma unroll
         for (int r = 0; r < KI; r++) dig[r] = (uint32_t)(key[r] >> sh) & mask;
         for (uint32_t i = l; i < LBINS; i += 64) cnt[w * LSTRIDE + i] = 0;
+        if (ATOMIC) {
 #pragma unroll
-        for (int r = 0; r < KI; r++) rk[r] = wave_rank(dig[r], true, nb, &cnt[w * LSTRIDE]);
+            for (int r = 0; r < KI; r++) rk[r] = atomicAdd(&cnt[w * LSTRIDE + dig[r]], 1u);
+        } else {
+#pragma unroll
+            for (int r = 0; r < KI; r++) rk[r] = wave_rank(dig[r], true, nb, &cnt[w * LSTRIDE]);
+        }
         lds_barrier();
         scan_counts<NT, NW, LBINS>(cnt, tmp);
 #pragma unroll
@@ -959,6 +967,34 @@ __device__ __forceinline__ void block_lsd_sort(KW (&key)[KI], uint16_t (&idx)[KI
             idx[r] = lds_idx[q];
         }
     }
+}
+
+// True (the same on every thread) when the first n items of lds_key/lds_idx
+// are in strictly increasing (key, idx) order. *flag must be 0 on entry and
+// is 0 again on return; ends with a barrier.
+template <typename KW, int NT, int KI>
+__device__ __forceinline__ bool block_check_order(const KW* lds_key, const uint16_t* lds_idx, uint32_t n,
+                                                  uint32_t* flag)
+{
+    const uint32_t p0 = threadIdx.x * KI;
+    KW kp = p0 ? lds_key[p0 - 1] : (KW)0;
+    uint32_t ip = p0 ? lds_idx[p0 - 1] : 0u;
+    bool bad = false;
+#pragma unroll
+    for (int i = 0; i < KI; i++) {
+        const uint32_t p = p0 + i;
+        const KW k = lds_key[p];
+        const uint32_t x = lds_idx[p];
+        bad = bad || (p > 0 && p < n && !(kp < k || (kp == k && ip < x)));
+        kp = k;
+        ip = x;
+    }
+    if (bad) *flag = 1;
+    lds_barrier();
+    const bool ok = *flag == 0;
+    lds_barrier();
+    if (threadIdx.x == 0) *flag = 0;
+    return ok;
 }
 
 template <typename K, typename KW>
@@ -1178,7 +1214,9 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_leaf_join(const LeafDesc* __restr
     __shared__ uint64_t tmp64[NW];
     __shared__ uint32_t s_leaf;
     __shared__ uint64_t s_base;
+    __shared__ uint32_t s_unordered;
 
+    if (threadIdx.x == 0) s_unordered = 0;
     uint32_t li = blockIdx.x;
     if (MAT) {
         if (threadIdx.x == 0) s_leaf = atomicAdd(ticket, 1u);
@@ -1193,25 +1231,33 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_leaf_join(const LeafDesc* __restr
 
     KW key[KI];
     uint16_t idx[KI];
-#pragma unroll
-    for (int r = 0; r < KI; r++) {
-        const uint32_t q = (w * KI + r) * 64 + l;
-        key[r] = (KW)~(KW)0;
-        idx[r] = (uint16_t)q;
-    }
-    if (n > 0) {
+    auto load_items = [&]() {
 #pragma unroll
         for (int r = 0; r < KI; r++) {
             const uint32_t q = (w * KI + r) * 64 + l;
-            const uint32_t qc = q < n ? q : n - 1;  // every lane loads a real row
-            const K v = qc < rn ? rk[qc] : sk[qc - rn];
-            if (q < n) key[r] = (KW)(ord_of(v) - L.base);
+            key[r] = (KW)~(KW)0;
+            idx[r] = (uint16_t)q;
         }
-    }
+        if (n > 0) {
+#pragma unroll
+            for (int r = 0; r < KI; r++) {
+                const uint32_t q = (w * KI + r) * 64 + l;
+                const uint32_t qc = q < n ? q : n - 1;  // every lane loads a real row
+                const K v = qc < rn ? rk[qc] : sk[qc - rn];
+                if (q < n) key[r] = (KW)(ord_of(v) - L.base);
+            }
+        }
+    };
     // (LSD rather than block_bin_sort: a key here usually has several rows, one
     // of R and its S matches, which makes the bins too full for the exact
-    // in-bin ranking to pay)
-    block_lsd_sort<KW, NT, KI>(key, idx, (int)L.bits, lds_key, lds_idx, cnt, tmp);
+    // in-bin ranking to pay.) Ranked by atomics, then checked; sorted again
+    // with ballot ranking if the order is not exact.
+    load_items();
+    block_lsd_sort<KW, NT, KI, true>(key, idx, (int)L.bits, lds_key, lds_idx, cnt, tmp);
+    if (!block_check_order<KW, NT, KI>(lds_key, lds_idx, n, &s_unordered) || (L.flags & LEAF_FORCE_REORDER)) {
+        load_items();
+        block_lsd_sort<KW, NT, KI, false>(key, idx, (int)L.bits, lds_key, lds_idx, cnt, tmp);
+    }
 
     // Run analysis on blocked positions p = tid*KI + i. A run is a maximal
     // stretch of equal keys: [rs, s0) holds its a R items, [s0, re) its b S

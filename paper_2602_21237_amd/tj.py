@@ -52,6 +52,7 @@ EXPORTS = {
     "tj_timing": (ctypes.c_int, [ctypes.c_int]),
     "tj_timing_read": (ctypes.c_int, [_P, ctypes.c_int]),
     "tj_debug_wave_scan": (ctypes.c_int, [_P, _P, _u64, _P]),
+    "tj_debug_set_flags": (ctypes.c_int, [ctypes.c_uint32]),
     "tj_debug_partition_pass": (ctypes.c_int, [_P, _P, _u64, _u64, ctypes.c_uint32, ctypes.c_uint32,
                                                ctypes.c_uint32, _P, _P, _P, _P, _u64, _P]),
 }
@@ -239,6 +240,11 @@ def debug_wave_scan(x):
 
 
 TJ_DEBUG_FORCE_REORDER = 1
+
+
+def debug_set_flags(flags: int) -> None:
+    """Process-wide self-test flags for later calls (TJ_DEBUG_FORCE_REORDER or 0)."""
+    _check(load().tj_debug_set_flags(flags), "tj_debug_set_flags")
 
 
 def debug_partition_pass(keys, rids, base: int, shift: int, bits: int, workspace_bytes: int = 64 << 20,

@@ -321,3 +321,23 @@ def test_sort_wide_keys_with_ties(tj):
     check_sort(tj, k, rng.permutation(n).astype(np.int32))
     few = rng.choice(rng.integers(I64.min, I64.max, 7, dtype=np.int64), n)  # long tie runs
     check_sort(tj, few, np.arange(n, dtype=np.int32))
+
+
+# --------------------------------------------------------------------------- fallback paths
+
+def test_forced_reranking_paths(tj):
+    """With TJ_DEBUG_FORCE_REORDER every partition tile and every join block
+    also runs the ballot-ranked path that replaces an atomic-ranked order found
+    out of input order: the results must be the same."""
+    tj.tj.debug_set_flags(tj.tj.TJ_DEBUG_FORCE_REORDER)
+    try:
+        w = tjgen.paper_shaped(0.99, n=200_000, rid_perm=True)
+        check_join(tj, w["r_keys"], w["r_rids"], w["s_keys"], w["s_rids"])
+        check_sort(tj, w["s_keys"], w["s_rids"])
+        rng = np.random.default_rng(11)
+        k = rng.integers(-50, 50, 30_000).astype(np.int64)
+        check_join(tj, k[:12_000], np.arange(12_000, dtype=np.int32), k[12_000:],
+                   np.arange(18_000, dtype=np.int32))
+        check_sort(tj, k, rng.permutation(k.size).astype(np.int32))
+    finally:
+        tj.tj.debug_set_flags(0)

@@ -79,6 +79,7 @@ uint64_t table_bytes(const Caps& c)
     b += align_up((uint64_t)c.leaves * sizeof(LeafDesc), ALIGN);
     b += align_up(((uint64_t)c.leaves + 1) * 8, ALIGN);              // look-back status
     b += align_up(children * sizeof(ChildRec), ALIGN);                // folded child records
+    b += align_up((uint64_t)c.groups * 4, ALIGN);                     // leaves per segment
     const uint64_t ub = sizeof(CrossDesc) > sizeof(CopyDesc) ? sizeof(CrossDesc) : sizeof(CopyDesc);
     b += align_up((uint64_t)c.units * ub, ALIGN);
     return b;
@@ -280,13 +281,16 @@ struct Exec {
     LeafDesc* d_leaves = nullptr;
     uint64_t* d_status = nullptr;  // caps.leaves + 1 look-back words
     ChildRec* d_crec = nullptr;     // caps.children folded child records
-    // scalars in the probe block: [0..1] min/max, [2] pair total, [3] ticket (low) + error (high)
+    uint32_t* d_segcount = nullptr; // caps.groups leaf counts (device batching)
+    // scalars in the probe block: [0..1] min/max, [2] pair total, [3] ticket (low) + error (high),
+    // [4..6] device batching summary (leaves, rows, flags)
     void* d_units = nullptr;
 
     // data buffer capacities (rows per side) when the buffers live in the workspace
     uint64_t cap_r = 0, cap_s = 0;
     bool out_is_a = false;  // sort: buffer A is the caller's output
     bool write_keys = true; // partition passes write key columns (off: rid-only compaction)
+    bool device_batching = true;  // the last level's leaves may be batched on the device
 
     // timing of this call's launches (when enabled)
     bool timed_on = false;
@@ -384,6 +388,7 @@ struct Exec {
         d_leaves = (LeafDesc*)take((uint64_t)caps.leaves * sizeof(LeafDesc));
         d_status = (uint64_t*)take(((uint64_t)caps.leaves + 1) * 8);
         d_crec = (ChildRec*)take(children * sizeof(ChildRec));
+        d_segcount = (uint32_t*)take((uint64_t)caps.groups * 4);
         const uint64_t ub = sizeof(CrossDesc) > sizeof(CopyDesc) ? sizeof(CrossDesc) : sizeof(CopyDesc);
         d_units = take((uint64_t)caps.units * ub);
         return p <= end ? TJ_OK : TJ_E_WORKSPACE;
@@ -419,6 +424,10 @@ struct Exec {
             plan[i].kb_out = sh.join && write_keys && s.kb == 8 && plan[i].shift <= 32 ? 4u : s.kb;
             total_rows += filter ? (uint64_t)(i == 0 ? sh.n_r + sh.n_s : 0) : rows;
         }
+        // device batching only pays where the children are expected to be leaves
+        if (dev_ok)
+            for (size_t i = 0; i < segs.size(); i++)
+                if (((segs[i].rn + segs[i].sn) >> plan[i].bits) > (uint64_t)LEAF_CAP / 2) dev_ok = false;
         uint64_t ch_rows = align_up((total_rows + TARGET_CHUNKS - 1) / TARGET_CHUNKS, PART_TILE);
         if (ch_rows < PART_TILE) ch_rows = PART_TILE;
         // make sure the largest group fits the chunk table
@@ -528,10 +537,44 @@ struct Exec {
                 return launch_scatter((int)kb_in, (int)kb_out, sh.rids, write_keys, d_chunks, nc, d_groups, d_hist, d_cbsum,
                                       d_cstart, bufs, st);
             }));
-            // one compact record per child (both sides folded), read back pinned
+            // one compact record per child (both sides folded)
             const uint32_t nrec = child / (uint32_t)nside;
             TJ_CK(launch_children(d_groups, ng, nside, d_ccount, d_gmin, d_gmax, d_crec, st));
-            ChildRec* rec = (ChildRec*)pinned_down(nrec * sizeof(ChildRec));
+            if (dev_ok) {
+                // batch the children into leaves on the device; the host reads three words
+                BatchArgs ba{};
+                ba.nseg = ng / (uint32_t)nside;
+                ba.nside = (uint32_t)nside;
+                ba.narrowing = kb_out < kb_in ? 1u : 0u;
+                ba.join = sh.join ? 1u : 0u;
+                ba.buf = dst;
+                ba.kb = kb_out;
+                ba.flags = (g_debug_flags.load() & TJ_DEBUG_FORCE_REORDER) ? LEAF_FORCE_REORDER : 0u;
+                ba.leaf_base = dev_leaves;
+                ba.leaf_cap = caps.leaves;
+                ba.out_delta = cur_out_delta;
+                uint64_t* d_sum = d_probe + 4;
+                TJ_CK(launch_fill_u64(d_sum, 3, 0, st));
+                TJ_CK(launch_batch_leaves(d_groups, d_crec, ba, d_segcount, d_leaves, d_sum, 0, st));
+                TJ_CK(launch_batch_leaves(d_groups, d_crec, ba, d_segcount, d_leaves, d_sum, 1, st));
+                uint64_t* sum = (uint64_t*)pinned_down(3 * sizeof(uint64_t));
+                if (!sum) return TJ_E_HIP;
+                TJ_CK(hipMemcpyAsync(sum, d_sum, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+                TJ_CK(hipStreamSynchronize(st));
+                if (!(sum[2] & (BATCH_NEEDS_HOST | BATCH_OVERFLOW))) {
+                    uint64_t moved = 0;
+                    for (uint32_t gi = 0; gi < ng; gi++) moved += segs[gseg[gi]].rn * (groups[gi].side == 0) +
+                                                              segs[gseg[gi]].sn * (groups[gi].side == 1);
+                    stats.bytes_written += moved * row_bytes((int)kb_out, sh.rids);
+                    dev_leaves += (uint32_t)sum[0];
+                    dev_rows += sum[1];
+                    dev_wide = dev_wide || (sum[2] & BATCH_WIDE);
+                    dev_kb = kb_out;
+                    continue;
+                }
+                TJ_RET(demote_device_leaves());  // this level needs the host planner
+            }
+            ChildRec* rec = (ChildRec*)pinned_down((size_t)nrec * sizeof(ChildRec));
             if (!rec) return TJ_E_HIP;
             TJ_CK(hipMemcpyAsync(rec, d_crec, nrec * sizeof(ChildRec), hipMemcpyDeviceToHost, st));
             TJ_CK(hipStreamSynchronize(st));
@@ -585,6 +628,32 @@ struct Exec {
     // up to LEAF_CAP rows), crosses (join) or copies (sort). `out_delta` maps
     // buffer rows to output rows of the sort. classify_flush closes the open
     // leaf at the end of a level.
+    // Leaves batched on the device for the current key range: d_leaves[0, dev_leaves).
+    // Used for a level only when no host-side leaf, cross or copy exists yet
+    // (so that the device leaves are the range's leaves in key order).
+    bool dev_ok = false;
+    uint32_t dev_leaves = 0, dev_kb = 0;
+    uint64_t dev_rows = 0;
+    bool dev_wide = false;
+    uint64_t cur_out_delta = 0;
+
+    // Moves the device leaves to the host list (they precede every later leaf).
+    int demote_device_leaves()
+    {
+        if (dev_leaves) {
+            const size_t n0 = leaves.size();
+            leaves.resize(n0 + dev_leaves);
+            TJ_CK(hipMemcpyAsync(leaves.data() + n0, d_leaves, (size_t)dev_leaves * sizeof(LeafDesc),
+                                 hipMemcpyDeviceToHost, st));
+            TJ_CK(hipStreamSynchronize(st));
+        }
+        dev_leaves = 0;
+        dev_rows = 0;
+        dev_wide = false;
+        dev_ok = false;
+        return TJ_OK;
+    }
+
     bool cl_open = false, cl_useful = false;
     LeafDesc cl_cur{};
     uint64_t cl_lo = 0, cl_hi = 0, cl_win = 0;
@@ -678,11 +747,17 @@ struct Exec {
         root.buf = BUF_IN;
         std::vector<Seg> next, next2;
         auto to_next = [&](const Seg& c) { classify_one(c, next, out_delta); };
+        cur_out_delta = out_delta;
+        auto allow_device = [&]() {
+            dev_ok = device_batching && leaves.empty() && crosses.empty() && copies.empty() && dev_leaves == 0;
+        };
         if (filtered) {
             // first pass: compaction + split of the range's rows out of the input
             const uint64_t f[2] = {lo, hi};
             std::vector<Seg> roots{root};
+            allow_device();
             TJ_RET(run_pass(roots, BUF_IN, BUF_A, f, to_next));
+            dev_ok = false;
         } else {
             classify_one(root, next, out_delta);
         }
@@ -692,7 +767,9 @@ struct Exec {
             if (next.empty()) return TJ_OK;
             const uint32_t dst = cur == BUF_A ? (uint32_t)BUF_B : (uint32_t)BUF_A;
             next2.clear();
+            allow_device();
             TJ_RET(run_pass(next, cur, dst, nullptr, [&](const Seg& c) { classify_one(c, next2, out_delta); }));
+            dev_ok = false;
             classify_flush(out_delta);
             next.swap(next2);
             cur = dst;
@@ -703,6 +780,22 @@ struct Exec {
     // ---- leaves and singles ---------------------------------------------
     int run_sort_leaves(void* out_k, int32_t* out_r)
     {
+        if (dev_leaves) {
+            // batched on the device: no other leaf or copy exists in this range
+            if (!leaves.empty() || !copies.empty()) return TJ_E_INTERNAL;
+            const uint32_t n = dev_leaves;
+            TJ_CK(timed(F_LEAF_SORT, dev_rows * row_bytes(sh.kb, true) * 2, [&] {
+                return launch_leaf_sort(sh.kb, dev_wide, d_leaves, n, bufs, out_k, out_r, st);
+            }));
+            TJ_CK(hipStreamSynchronize(st));
+            stats.leaves += n;
+            stats.bytes_read += dev_rows * row_bytes(sh.kb, true);
+            stats.bytes_written += dev_rows * row_bytes(sh.kb, true);
+            dev_leaves = 0;
+            dev_rows = 0;
+            dev_wide = false;
+            return TJ_OK;
+        }
         HostTimer ht(this, F_HOST_LEAVES);
         for (int wide = 0; wide < 2; wide++) {
             std::vector<LeafDesc>& sel = hv.batch_leaves;
@@ -755,6 +848,54 @@ struct Exec {
     int finish_join(uint64_t* total_out, uint64_t base, int32_t* out_r, int32_t* out_s,
                     uint64_t capacity, bool mat)
     {
+        if (dev_leaves) {
+            // batched on the device: no other leaf or cross exists in this range
+            if (!leaves.empty() || !crosses.empty()) return TJ_E_INTERNAL;
+            const uint32_t nl = dev_leaves;
+            const int kb = (int)dev_kb;
+            const bool wide = dev_wide;
+            const uint64_t rows = dev_rows;
+            dev_leaves = 0;
+            dev_rows = 0;
+            dev_wide = false;
+            stats.leaves += nl;
+            uint64_t* d_total = d_probe + 2;
+            uint32_t* d_ticket = (uint32_t*)(d_probe + 3);
+            uint32_t* d_err = d_ticket + 1;
+            if (!mat) {
+                TJ_CK(launch_fill_u64(d_total, 1, 0, st));
+                TJ_CK(timed(F_LEAF_COUNT, rows * kb, [&] {
+                    return launch_leaf_join(kb, wide, false, d_leaves, nl, bufs, d_status, d_ticket, d_total,
+                                            d_err, nullptr, nullptr, 0, st);
+                }));
+                uint64_t t = 0;
+                TJ_CK(hipMemcpyAsync(&t, d_total, 8, hipMemcpyDeviceToHost, st));
+                TJ_CK(hipStreamSynchronize(st));
+                stats.bytes_read += rows * kb;
+                *total_out = t;
+                return TJ_OK;
+            }
+            TJ_CK(launch_fill_u64(d_status, 1, STATUS_INCLUSIVE | base, st));
+            TJ_CK(launch_fill_u64(d_status + 1, nl, 0, st));
+            TJ_CK(launch_fill_u64(d_probe + 3, 1, 0, st));  // ticket and error flag
+            const size_t leaf_timer = pending.size();
+            TJ_CK(timed(F_LEAF_MAT, rows * row_bytes(kb, true), [&] {
+                return launch_leaf_join(kb, wide, true, d_leaves, nl, bufs, d_status, d_ticket, d_total, d_err,
+                                        out_r, out_s, capacity, st);
+            }));
+            stats.bytes_read += rows * row_bytes(kb, true);
+            uint64_t fin[2] = {0, 0};
+            TJ_CK(hipMemcpyAsync(&fin[0], d_status + nl, 8, hipMemcpyDeviceToHost, st));
+            TJ_CK(hipMemcpyAsync(&fin[1], d_probe + 3, 8, hipMemcpyDeviceToHost, st));
+            TJ_CK(hipStreamSynchronize(st));
+            if (fin[1] >> 32) return TJ_E_INTERNAL;  // a look-back expired
+            const uint64_t end = fin[0] & STATUS_VALUE;
+            if (leaf_timer < pending.size()) pending[leaf_timer].bytes += (end - base) * 8;
+            *total_out = end - base;
+            const uint64_t written = std::min(end, capacity) > base ? std::min(end, capacity) - base : 0;
+            stats.bytes_written += written * 8;
+            return TJ_OK;
+        }
         HostTimer ht(this, F_HOST_LEAVES);
         auto lr0 = [](const LeafDesc& a, const LeafDesc& b) { return a.r0 < b.r0; };
         auto cr0 = [](const CrossDesc& a, const CrossDesc& b) { return a.r0 < b.r0; };

@@ -111,6 +111,25 @@ struct ChildRec {
     uint64_t lo, hi;
 };
 
+// Device-side leaf batching of one launch batch (k_batch_leaves).
+struct BatchArgs {
+    uint32_t nseg;        // segments of the launch (groups / nside)
+    uint32_t nside;       // 2 for a join, 1 for a sort
+    uint32_t narrowing;   // this pass narrowed the keys (children get relative ranges)
+    uint32_t join;        // leaves need rows on both sides to be kept
+    uint32_t buf;         // buffer holding the children
+    uint32_t kb;          // key bytes of the children
+    uint32_t flags;       // LeafDesc flags to set
+    uint32_t leaf_base;   // first leaf slot of this batch
+    uint32_t leaf_cap;    // leaf slots available in total
+    uint32_t pad;
+    uint64_t out_delta;   // sort: output row of buffer row 0
+};
+// Summary words written by k_batch_leaves (pass 1): leaves, rows, flags.
+constexpr uint64_t BATCH_NEEDS_HOST = 1;  // a child needs another pass or is a large single key
+constexpr uint64_t BATCH_WIDE = 2;        // a leaf spans more than 32 key bits
+constexpr uint64_t BATCH_OVERFLOW = 4;    // the leaf slots ran out
+
 struct BufSet {
     const void* key[3][2];
     const int32_t* rid[3][2];
@@ -141,6 +160,11 @@ hipError_t launch_scatter(int key_bytes, int out_key_bytes, bool rids, bool keys
 hipError_t launch_children(const GroupDesc* groups, uint32_t ngroups, int nside,
                            const uint32_t* ccount, const uint64_t* gmin, const uint64_t* gmax,
                            ChildRec* out, hipStream_t st);
+// pass 0 counts each segment's leaves into seg_count; pass 1 writes them and
+// adds to summary[0..2] (which the caller clears first).
+hipError_t launch_batch_leaves(const GroupDesc* groups, const ChildRec* crec, const BatchArgs& a,
+                               uint32_t* seg_count, LeafDesc* leaves, uint64_t* summary, int pass,
+                               hipStream_t st);
 hipError_t launch_leaf_sort(int key_bytes, bool wide, const LeafDesc* leaves, uint32_t n,
                             BufSet bufs, void* out_k, int32_t* out_r, hipStream_t st);
 // Count mode adds the leaves' pair counts to *total. Materialise mode needs

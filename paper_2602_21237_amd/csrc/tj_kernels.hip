@@ -554,6 +554,130 @@ hipError_t launch_children(const GroupDesc* groups, uint32_t ngroups, int nside,
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Leaf batching of a level on the device, for the common last level where
+// every child fits one LDS block: the host then reads back three words instead
+// of one record per child. One wave per segment stages the segment's child
+// records in LDS and its first lane batches adjacent children greedily into
+// leaves of at most LEAF_CAP rows (a child whose keys were narrowed into
+// another 2^32 window starts a new leaf), as the host planner does. A child
+// over LEAF_CAP sets BATCH_NEEDS_HOST and the host redoes the level. Pass 0
+// counts the leaves of each segment; pass 1 writes them after the leaves of
+// the earlier segments of the batch.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_batch_leaves(const GroupDesc* __restrict__ groups,
+                                                     const ChildRec* __restrict__ crec, BatchArgs a,
+                                                     uint32_t* __restrict__ seg_count,
+                                                     LeafDesc* __restrict__ leaves,
+                                                     unsigned long long* __restrict__ summary, int pass)
+{
+    __shared__ ChildRec rec[NB];
+    const uint32_t sgi = blockIdx.x, l = threadIdx.x;
+    const GroupDesc g0 = groups[sgi * a.nside];
+    const uint64_t s_start = a.nside == 2 ? groups[sgi * 2 + 1].dst_start : 0;
+    const uint64_t koff_s = a.nside == 2 ? groups[sgi * 2 + 1].dst_koff : 0;
+    const uint32_t nb = 1u << g0.bits;
+    const ChildRec* cr = crec + g0.child0 / a.nside;
+    for (uint32_t d = l; d < nb; d += 64) rec[d] = cr[d];
+    uint64_t before = 0;
+    if (pass == 1) {
+        for (uint32_t i = l; i < sgi; i += 64) before += seg_count[i];
+        before = wave_sum64(before);
+    }
+    __syncthreads();
+    if (l != 0) return;
+    uint32_t nleaf = 0;
+    uint64_t rows_all = 0, fl = 0;
+    bool open = false, useful = false;
+    uint64_t r0 = g0.dst_start, s0 = s_start, lr0 = 0, ls0 = 0, lrn = 0, lsn = 0, llo = 0, lhi = 0, lwin = 0;
+    auto flush = [&]() {
+        if (open && useful) {
+            if (pass == 1) {
+                const uint64_t slot = a.leaf_base + before + nleaf;
+                if (slot < a.leaf_cap) {
+                    LeafDesc L;
+                    L.r0 = lr0;
+                    L.s0 = ls0;
+                    L.kr0 = lr0 + g0.dst_koff;
+                    L.ks0 = ls0 + koff_s;
+                    L.base = llo;
+                    L.out = a.join ? 0 : lr0 + a.out_delta;
+                    L.rn = (uint32_t)lrn;
+                    L.sn = (uint32_t)lsn;
+                    const uint64_t span = lhi - llo;
+                    L.bits = (uint16_t)(span ? 64 - __clzll((long long)span) : 0);
+                    L.kb = (uint16_t)a.kb;
+                    L.buf = (uint16_t)a.buf;
+                    L.flags = (uint16_t)a.flags;
+                    leaves[slot] = L;
+                    if (L.bits > 32) fl |= BATCH_WIDE;
+                } else {
+                    fl |= BATCH_OVERFLOW;
+                }
+                rows_all += lrn + lsn;
+            }
+            nleaf++;
+        }
+        open = false;
+        useful = false;
+    };
+    for (uint32_t d = 0; d < nb; d++) {
+        const ChildRec c = rec[d];
+        const uint64_t rows = (uint64_t)c.rn + c.sn;
+        if (rows == 0) continue;  // occupies no rows: does not break adjacency
+        if (rows > (uint64_t)LEAF_CAP) {
+            fl |= BATCH_NEEDS_HOST;
+            flush();
+            r0 += c.rn;
+            s0 += c.sn;
+            continue;
+        }
+        uint64_t lo = c.lo, hi = c.hi, win = 0;
+        if (a.narrowing) {
+            const uint64_t off = lo - g0.base;
+            win = off >> 32;
+            lo = off & 0xffffffffull;
+            hi = (hi - g0.base) & 0xffffffffull;
+        }
+        if (!(open && win == lwin && lrn + lsn + rows <= (uint64_t)LEAF_CAP)) {
+            flush();
+            open = true;
+            lr0 = r0;
+            ls0 = s0;
+            lrn = lsn = 0;
+            llo = lo;
+            lhi = hi;
+            lwin = win;
+        }
+        lrn += c.rn;
+        lsn += c.sn;
+        llo = lo < llo ? lo : llo;
+        lhi = hi > lhi ? hi : lhi;
+        useful = useful || !a.join || (c.rn > 0 && c.sn > 0);
+        r0 += c.rn;
+        s0 += c.sn;
+    }
+    flush();
+    if (pass == 0) {
+        seg_count[sgi] = nleaf;
+        if (fl) atomicOr(&summary[2], (unsigned long long)fl);
+    } else {
+        atomicAdd(&summary[0], (unsigned long long)nleaf);
+        atomicAdd(&summary[1], (unsigned long long)rows_all);
+        if (fl) atomicOr(&summary[2], (unsigned long long)fl);
+    }
+}
+
+hipError_t launch_batch_leaves(const GroupDesc* groups, const ChildRec* crec, const BatchArgs& a,
+                               uint32_t* seg_count, LeafDesc* leaves, uint64_t* summary, int pass,
+                               hipStream_t st)
+{
+    if (a.nseg == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_leaves, dim3(a.nseg), dim3(64), 0, st, groups, crec, a, seg_count, leaves,
+                       (unsigned long long*)summary, pass);
+    return hipGetLastError();
+}
+
 hipError_t launch_scan(const CBlockDesc* cblocks, uint32_t ncblocks, const GroupDesc* groups,
                        uint32_t ngroups, uint32_t* hist, uint32_t* cbsum, uint32_t* ccount,
                        uint64_t* cstart, hipStream_t st)

@@ -15,6 +15,8 @@
 // (ordinal - base) so that only the bits that vary inside a bucket are used.
 #include "tj_internal.h"
 
+#include <type_traits>
+
 namespace tj {
 
 // ---------------------------------------------------------------------------
@@ -923,6 +925,25 @@ template <typename KW> struct LeafShape {
     static constexpr int CNT_WORDS = NBIN > NW * LSTRIDE ? NBIN : NW * LSTRIDE;
 };
 
+// LDS array whose element i sits at i + (i / G) * S: S spare elements after
+// every G. With G = the items per thread, a wave reading its items in blocked
+// order (lane l at l*G + i) has an odd stride in 4-byte words and so spreads
+// its lanes over the banks; consecutive-lane access stays conflict-free.
+template <typename T, int G, int S>
+struct LdsPad {
+    T* p;
+    __device__ __forceinline__ T& operator[](uint32_t i) const { return p[i + (i / G) * S]; }
+    // element t*G + i, i < G (thread t's i-th item in blocked order)
+    __device__ __forceinline__ T& blk(uint32_t t, uint32_t i) const { return p[t * (G + S) + i]; }
+    static constexpr uint32_t size(uint32_t n) { return n + (n / G) * S; }
+};
+// join blocks read their sorted items in blocked order (padded layout); the
+// sort blocks read them across lanes (plain layout)
+template <typename KW> using KeyLds = LdsPad<KW, LeafShape<KW>::KI, 1>;
+template <typename KW> using IdxLds = LdsPad<uint16_t, LeafShape<KW>::KI, 2>;
+template <typename KW> using KeyPlain = LdsPad<KW, LeafShape<KW>::KI, 0>;
+template <typename KW> using IdxPlain = LdsPad<uint16_t, LeafShape<KW>::KI, 0>;
+
 // Largest bin block_bin_sort accepts: the exact ranking inside a bin costs
 // every item of the bin one pass over it.
 constexpr uint32_t BIN_MAXC = 48;  // < 64: the bin size is packed in 6 bits
@@ -941,9 +962,9 @@ constexpr uint32_t BIN_MAXC = 48;  // < 64: the bin size is packed in 6 bits
 // The result, in lds_key / lds_idx, is exact whatever order the atomics take.
 // Returns false, having written nothing to lds_key / lds_idx, when some bin
 // holds more than BIN_MAXC items; the caller then sorts another way.
-template <typename KW, int NT, int KI, int NBB>
-__device__ __forceinline__ bool block_bin_sort(const KW (&key)[KI], int bits, uint32_t n, KW* lds_key,
-                                               uint16_t* lds_idx, uint32_t* hist, uint32_t* tmp)
+template <typename KW, int NT, int KI, int NBB, typename KA, typename IA>
+__device__ __forceinline__ bool block_bin_sort(const KW (&key)[KI], int bits, uint32_t n, KA lds_key,
+                                               IA lds_idx, uint32_t* hist, uint32_t* tmp)
 {
     constexpr int NBIN = 1 << NBB, BPT = NBIN / NT;
     static_assert(NBIN % NT == 0, "bins must split evenly over the block");
@@ -1040,9 +1061,9 @@ __device__ __forceinline__ bool block_bin_sort(const KW (&key)[KI], int bits, ui
 // ATOMIC ranks with one LDS atomic per item (in lane order on this hardware,
 // which makes every pass stable); the caller must then check that the result
 // is ordered by (key, idx) and sort again with ATOMIC = false if it is not.
-template <typename KW, int NT, int KI, bool ATOMIC = false>
+template <typename KW, int NT, int KI, bool ATOMIC = false, typename KA, typename IA>
 __device__ __forceinline__ void block_lsd_sort(KW (&key)[KI], uint16_t (&idx)[KI], int bits,
-                                               KW* lds_key, uint16_t* lds_idx, uint32_t* cnt,
+                                               KA lds_key, IA lds_idx, uint32_t* cnt,
                                                uint32_t* tmp, int lo_bit = 0)
 {
     constexpr int NW = NT / 64;
@@ -1096,19 +1117,18 @@ __device__ __forceinline__ void block_lsd_sort(KW (&key)[KI], uint16_t (&idx)[KI
 // True (the same on every thread) when the first n items of lds_key/lds_idx
 // are in strictly increasing (key, idx) order. *flag must be 0 on entry and
 // is 0 again on return; ends with a barrier.
-template <typename KW, int NT, int KI>
-__device__ __forceinline__ bool block_check_order(const KW* lds_key, const uint16_t* lds_idx, uint32_t n,
-                                                  uint32_t* flag)
+template <typename KW, int NT, int KI, typename KA, typename IA>
+__device__ __forceinline__ bool block_check_order(KA lds_key, IA lds_idx, uint32_t n, uint32_t* flag)
 {
-    const uint32_t p0 = threadIdx.x * KI;
-    KW kp = p0 ? lds_key[p0 - 1] : (KW)0;
-    uint32_t ip = p0 ? lds_idx[p0 - 1] : 0u;
+    const uint32_t t = threadIdx.x, p0 = t * KI;
+    KW kp = t ? lds_key.blk(t - 1, KI - 1) : (KW)0;
+    uint32_t ip = t ? lds_idx.blk(t - 1, KI - 1) : 0u;
     bool bad = false;
 #pragma unroll
     for (int i = 0; i < KI; i++) {
         const uint32_t p = p0 + i;
-        const KW k = lds_key[p];
-        const uint32_t x = lds_idx[p];
+        const KW k = lds_key.blk(t, i);
+        const uint32_t x = lds_idx.blk(t, i);
         bad = bad || (p > 0 && p < n && !(kp < k || (kp == k && ip < x)));
         kp = k;
         ip = x;
@@ -1128,8 +1148,10 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_leaf_sort(const LeafDesc* __restr
                                                             int32_t* __restrict__ out_r)
 {
     constexpr int NT = LeafShape<KW>::NT, KI = LeafShape<KW>::KI, NW = LeafShape<KW>::NW, C = LEAF_CAP;
-    __shared__ KW lds_key[C];
-    __shared__ uint16_t lds_idx[C];
+    __shared__ KW lds_key_raw[C];
+    __shared__ uint16_t lds_idx_raw[C];
+    const KeyPlain<KW> lds_key{lds_key_raw};
+    const IdxPlain<KW> lds_idx{lds_idx_raw};
     __shared__ uint32_t cnt[LeafShape<KW>::CNT_WORDS];
     __shared__ uint32_t tmp[NW];
     __shared__ uint64_t tmp64[NW];
@@ -1212,7 +1234,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_leaf_sort(const LeafDesc* __restr
         if (q < L.rn) out_k[L.out + q] = key_of<K>(L.base + (uint64_t)lds_key[q]);
     }
     lds_barrier();
-    int32_t* lds_rid = (int32_t*)lds_key;
+    int32_t* lds_rid = (int32_t*)lds_key_raw;
 #pragma unroll
     for (int r = 0; r < KI; r++) {
         const uint32_t q = threadIdx.x + r * NT;
@@ -1331,8 +1353,14 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_leaf_join(const LeafDesc* __restr
                                                             uint64_t capacity)
 {
     constexpr int NT = LeafShape<KW>::NT, KI = LeafShape<KW>::KI, NW = LeafShape<KW>::NW, C = LEAF_CAP;
-    __shared__ KW lds_key[C];
-    __shared__ uint16_t lds_idx[C];
+    // (padded for the count; the materialising block keeps the plain layout:
+    // the padding's address arithmetic costs it registers it does not have)
+    using KA = typename std::conditional<MAT, KeyPlain<KW>, KeyLds<KW>>::type;
+    using IA = typename std::conditional<MAT, IdxPlain<KW>, IdxLds<KW>>::type;
+    __shared__ KW lds_key_raw[KA::size(C)];
+    __shared__ uint16_t lds_idx_raw[IA::size(C)];
+    const KA lds_key{lds_key_raw};
+    const IA lds_idx{lds_idx_raw};
     __shared__ uint32_t cnt[NW * LSTRIDE];
     __shared__ uint32_t tmp[NW];
     __shared__ uint64_t tmp64[NW];
@@ -1393,12 +1421,12 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_leaf_join(const LeafDesc* __restr
     uint32_t id[KI];
 #pragma unroll
     for (int i = 0; i < KI; i++) {
-        kk[i] = lds_key[p0 + i];
-        id[i] = lds_idx[p0 + i];
+        kk[i] = lds_key.blk(threadIdx.x, i);
+        id[i] = lds_idx.blk(threadIdx.x, i);
     }
-    const KW kprev = p0 ? lds_key[p0 - 1] : (KW)0;
-    const KW knext = p0 + KI < C ? lds_key[p0 + KI] : (KW)0;
-    const uint32_t inext = p0 + KI < C ? lds_idx[p0 + KI] : 0xffffu;
+    const KW kprev = p0 ? lds_key.blk(threadIdx.x - 1, KI - 1) : (KW)0;
+    const KW knext = p0 + KI < C ? lds_key.blk(threadIdx.x + 1, 0) : (KW)0;
+    const uint32_t inext = p0 + KI < C ? lds_idx.blk(threadIdx.x + 1, 0) : 0xffffu;
     uint32_t rs[KI];
     uint32_t run_start = 0;
 #pragma unroll
@@ -1413,7 +1441,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_leaf_join(const LeafDesc* __restr
 #pragma unroll
         for (int i = 0; i < KI; i++) rs[i] = max(rs[i], carry);
     }
-    uint16_t* run_s0 = (uint16_t*)lds_key;   // the key array is free from here on
+    uint16_t* run_s0 = (uint16_t*)lds_key_raw;   // the key array is free from here on
     uint16_t* run_end = run_s0 + C;
 #pragma unroll
     for (int i = 0; i < KI; i++) {
@@ -1454,7 +1482,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_leaf_join(const LeafDesc* __restr
     if (threadIdx.x == 0) status_store(&status[li + 1], ST_AGG | (uint64_t)ltot);
     // Row ids: one coalesced load of the block's rows (R then S) into the free
     // key array, then every item picks its own from LDS.
-    int32_t* lds_w = (int32_t*)lds_key;
+    int32_t* lds_w = (int32_t*)lds_key_raw;
     {
         const int32_t* __restrict__ rr = bufs.rid[L.buf][0] + L.r0;
         const int32_t* __restrict__ sr = bufs.rid[L.buf][1] + L.s0;
@@ -1498,7 +1526,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_leaf_join(const LeafDesc* __restr
     maxslots = block_max<NT>(maxslots, tmp);
     int32_t rid[KI];
 #pragma unroll
-    for (int i = 0; i < KI; i++) rid[i] = p0 + i < n ? lds_w[lds_idx[p0 + i]] : 0;
+    for (int i = 0; i < KI; i++) rid[i] = p0 + i < n ? lds_w[lds_idx.blk(threadIdx.x, i)] : 0;
     lds_barrier();  // the key array becomes the pair staging buffer
     constexpr uint32_t OC = C / 2;  // pairs per staged chunk: two int32 columns in the key array
     if (ltot <= 8 * OC && maxslots <= 64) {

@@ -725,9 +725,10 @@ __global__ __launch_bounds__(SC_NT) void k_scatter(const ChunkDesc* __restrict__
     __shared__ uint32_t run[NB], delta[NB];
     __shared__ uint32_t tmp[NW];
     __shared__ uint32_t s_unordered;
-    __shared__ K skey[TILE];
-    __shared__ int32_t srid[RIDS ? TILE : 1];
-    __shared__ uint16_t sidx[TILE];  // the staged row's index inside the tile
+    // staging, with one spare slot per lane of a wave for rows that take no part
+    __shared__ K skey[TILE + 64];
+    __shared__ int32_t srid[RIDS ? TILE + 64 : 1];
+    __shared__ uint16_t sidx[TILE + 64];  // the staged row's index inside the tile
 
     const ChunkDesc ch = chunks[blockIdx.x];
     const GroupDesc g = groups[ch.group];
@@ -791,12 +792,10 @@ __global__ __launch_bounds__(SC_NT) void k_scatter(const ChunkDesc* __restrict__
         }
 #pragma unroll
         for (int r = 0; r < KI; r++) {
-            if (val[r]) {
-                const uint32_t p = cnt[w * SC_STRIDE + dig[r]] + rk[r];
-                skey[p] = key[r];
-                if (RIDS) srid[p] = rid[r];
-                sidx[p] = (uint16_t)((w * KI + r) * 64 + l);
-            }
+            const uint32_t p = val[r] ? cnt[w * SC_STRIDE + dig[r]] + rk[r] : TILE + l;
+            skey[p] = key[r];
+            if (RIDS) srid[p] = rid[r];
+            sidx[p] = (uint16_t)((w * KI + r) * 64 + l);
         }
         lds_barrier();
         // next tile's loads overlap the write-out of this one
@@ -810,12 +809,23 @@ __global__ __launch_bounds__(SC_NT) void k_scatter(const ChunkDesc* __restrict__
             }
         }
         bool unordered = false;
-        for (uint32_t p = threadIdx.x; p < total; p += NT) {
-            const K k = skey[p];
-            const uint32_t d = digit_of(k);
-            write_row(delta[d] + p, k, RIDS ? srid[p] : 0);
-            // cnt[d] (wave 0's entry) is where digit d starts inside the tile
-            unordered = unordered || (p > cnt[d] && sidx[p - 1] > sidx[p]);
+        if (total) {
+            // the KI rows of each thread are read together (a position past the
+            // tile's rows re-reads its last row and writes nothing)
+#pragma unroll
+            for (int j = 0; j < KI; j++) {
+                const uint32_t p = threadIdx.x + j * NT;
+                const uint32_t pc = p < total ? p : total - 1;
+                const K k = skey[pc];
+                const int32_t rv = RIDS ? srid[pc] : 0;
+                const uint32_t x = sidx[pc], xp = sidx[pc ? pc - 1 : 0];
+                const uint32_t d = digit_of(k);
+                if (p < total) {
+                    write_row(delta[d] + p, k, rv);
+                    // cnt[d] (wave 0's entry) is where digit d starts inside the tile
+                    unordered = unordered || (p > cnt[d] && xp > x);
+                }
+            }
         }
         if (unordered) s_unordered = 1;
         lds_barrier();
@@ -935,6 +945,27 @@ struct LdsPad {
     __device__ __forceinline__ T& operator[](uint32_t i) const { return p[i + (i / G) * S]; }
     // element t*G + i, i < G (thread t's i-th item in blocked order)
     __device__ __forceinline__ T& blk(uint32_t t, uint32_t i) const { return p[t * (G + S) + i]; }
+    // all G items of thread t; 16-byte loads for an unpadded 16-bit array (a
+    // wave then reads 16 bytes per lane instead of 2, with 8x fewer conflicts)
+    __device__ __forceinline__ void blk_all(uint32_t t, uint32_t (&out)[G]) const
+    {
+        if constexpr (S == 0 && sizeof(T) == 2 && (G * 2) % 16 == 0) {
+            const uint4* v = (const uint4*)(p + t * G);
+#pragma unroll
+            for (int j = 0; j < G * 2 / 16; j++) {
+                const uint4 w = v[j];
+                const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+                for (int h = 0; h < 4; h++) {
+                    out[j * 8 + 2 * h] = ws[h] & 0xffffu;
+                    out[j * 8 + 2 * h + 1] = ws[h] >> 16;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < G; i++) out[i] = p[t * (G + S) + i];
+        }
+    }
     static constexpr uint32_t size(uint32_t n) { return n + (n / G) * S; }
 };
 // join blocks read their sorted items in blocked order (padded layout); the
@@ -1123,12 +1154,14 @@ __device__ __forceinline__ bool block_check_order(KA lds_key, IA lds_idx, uint32
     const uint32_t t = threadIdx.x, p0 = t * KI;
     KW kp = t ? lds_key.blk(t - 1, KI - 1) : (KW)0;
     uint32_t ip = t ? lds_idx.blk(t - 1, KI - 1) : 0u;
+    uint32_t xs[KI];
+    lds_idx.blk_all(t, xs);
     bool bad = false;
 #pragma unroll
     for (int i = 0; i < KI; i++) {
         const uint32_t p = p0 + i;
         const KW k = lds_key.blk(t, i);
-        const uint32_t x = lds_idx.blk(t, i);
+        const uint32_t x = xs[i];
         bad = bad || (p > 0 && p < n && !(kp < k || (kp == k && ip < x)));
         kp = k;
         ip = x;
@@ -1149,7 +1182,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_leaf_sort(const LeafDesc* __restr
 {
     constexpr int NT = LeafShape<KW>::NT, KI = LeafShape<KW>::KI, NW = LeafShape<KW>::NW, C = LEAF_CAP;
     __shared__ KW lds_key_raw[C];
-    __shared__ uint16_t lds_idx_raw[C];
+    __shared__ __align__(16) uint16_t lds_idx_raw[C];
     const KeyPlain<KW> lds_key{lds_key_raw};
     const IdxPlain<KW> lds_idx{lds_idx_raw};
     __shared__ uint32_t cnt[LeafShape<KW>::CNT_WORDS];
@@ -1358,7 +1391,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_leaf_join(const LeafDesc* __restr
     using KA = typename std::conditional<MAT, KeyPlain<KW>, KeyLds<KW>>::type;
     using IA = typename std::conditional<MAT, IdxPlain<KW>, IdxLds<KW>>::type;
     __shared__ KW lds_key_raw[KA::size(C)];
-    __shared__ uint16_t lds_idx_raw[IA::size(C)];
+    __shared__ __align__(16) uint16_t lds_idx_raw[IA::size(C)];
     const KA lds_key{lds_key_raw};
     const IA lds_idx{lds_idx_raw};
     __shared__ uint32_t cnt[NW * LSTRIDE];
@@ -1419,11 +1452,9 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_leaf_join(const LeafDesc* __restr
     const uint32_t p0 = threadIdx.x * KI;
     KW kk[KI];
     uint32_t id[KI];
+    lds_idx.blk_all(threadIdx.x, id);
 #pragma unroll
-    for (int i = 0; i < KI; i++) {
-        kk[i] = lds_key.blk(threadIdx.x, i);
-        id[i] = lds_idx.blk(threadIdx.x, i);
-    }
+    for (int i = 0; i < KI; i++) kk[i] = lds_key.blk(threadIdx.x, i);
     const KW kprev = p0 ? lds_key.blk(threadIdx.x - 1, KI - 1) : (KW)0;
     const KW knext = p0 + KI < C ? lds_key.blk(threadIdx.x + 1, 0) : (KW)0;
     const uint32_t inext = p0 + KI < C ? lds_idx.blk(threadIdx.x + 1, 0) : 0xffffu;
@@ -1526,7 +1557,7 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_leaf_join(const LeafDesc* __restr
     maxslots = block_max<NT>(maxslots, tmp);
     int32_t rid[KI];
 #pragma unroll
-    for (int i = 0; i < KI; i++) rid[i] = p0 + i < n ? lds_w[lds_idx.blk(threadIdx.x, i)] : 0;
+    for (int i = 0; i < KI; i++) rid[i] = p0 + i < n ? lds_w[id[i]] : 0;
     lds_barrier();  // the key array becomes the pair staging buffer
     constexpr uint32_t OC = C / 2;  // pairs per staged chunk: two int32 columns in the key array
     if (ltot <= 8 * OC && maxslots <= 64) {

@@ -421,8 +421,13 @@ __global__ __launch_bounds__(PART_THREADS) void k_hist(const ChunkDesc* __restri
                 }
             } else if (valid) {
                 atomicAdd(&cnt[d], 1u);
-                atomicMin((unsigned long long*)&mn[d], (unsigned long long)o);
-                atomicMax((unsigned long long*)&mx[d], (unsigned long long)o);
+                // The minimum only falls and the maximum only rises, so a row
+                // that does not beat a value read (atomically) at any moment
+                // cannot change them; most rows skip the 64-bit atomics.
+                if (o < __hip_atomic_load(&mn[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+                    atomicMin((unsigned long long*)&mn[d], (unsigned long long)o);
+                if (o > __hip_atomic_load(&mx[d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+                    atomicMax((unsigned long long*)&mx[d], (unsigned long long)o);
             }
         }
     }

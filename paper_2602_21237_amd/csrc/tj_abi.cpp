@@ -41,6 +41,7 @@ constexpr uint64_t TARGET_CHUNKS = 2048;  // blocks per partition pass
 #endif
 // widest digit a partition pass uses (at most MAX_DIGIT_BITS)
 constexpr int PASS_DIGIT_BITS = TJ_PASS_DIGIT_BITS;
+constexpr size_t DEVICE_BATCH_MIN_SEGS = 16;  // segments of a pass before leaves are batched on the device
 
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
@@ -424,7 +425,10 @@ struct Exec {
             plan[i].kb_out = sh.join && write_keys && s.kb == 8 && plan[i].shift <= 32 ? 4u : s.kb;
             total_rows += filter ? (uint64_t)(i == 0 ? sh.n_r + sh.n_s : 0) : rows;
         }
-        // device batching only pays where the children are expected to be leaves
+        // Device batching pays where the children are expected to be leaves and
+        // are many: one wave walks each segment's children in turn (~0.1 ms),
+        // while the host needs about 5 ns per child.
+        if (segs.size() < DEVICE_BATCH_MIN_SEGS) dev_ok = false;
         if (dev_ok)
             for (size_t i = 0; i < segs.size(); i++)
                 if (((segs[i].rn + segs[i].sn) >> plan[i].bits) > (uint64_t)LEAF_CAP / 2) dev_ok = false;

@@ -578,21 +578,33 @@ __global__ __launch_bounds__(64) void k_batch_leaves(const GroupDesc* __restrict
                                                      LeafDesc* __restrict__ leaves,
                                                      unsigned long long* __restrict__ summary, int pass)
 {
-    __shared__ ChildRec rec[NB];
+    constexpr int RPL = NB / 64;  // child records held per lane
     const uint32_t sgi = blockIdx.x, l = threadIdx.x;
     const GroupDesc g0 = groups[sgi * a.nside];
     const uint64_t s_start = a.nside == 2 ? groups[sgi * 2 + 1].dst_start : 0;
     const uint64_t koff_s = a.nside == 2 ? groups[sgi * 2 + 1].dst_koff : 0;
     const uint32_t nb = 1u << g0.bits;
     const ChildRec* cr = crec + g0.child0 / a.nside;
-    for (uint32_t d = l; d < nb; d += 64) rec[d] = cr[d];
+    // child d = j*64 + lane sits in lane (d mod 64), slot j; the batching loop
+    // below reads it with readlane, so it runs on wave-uniform values without
+    // a memory round trip per child
+    uint32_t rrn[RPL], rsn[RPL], rlo0[RPL], rlo1[RPL], rhi0[RPL], rhi1[RPL];
+#pragma unroll
+    for (int j = 0; j < RPL; j++) {
+        const uint32_t d = j * 64 + l;
+        const ChildRec c = d < nb ? cr[d] : ChildRec{0, 0, 0, 0};
+        rrn[j] = c.rn;
+        rsn[j] = c.sn;
+        rlo0[j] = (uint32_t)c.lo;
+        rlo1[j] = (uint32_t)(c.lo >> 32);
+        rhi0[j] = (uint32_t)c.hi;
+        rhi1[j] = (uint32_t)(c.hi >> 32);
+    }
     uint64_t before = 0;
     if (pass == 1) {
         for (uint32_t i = l; i < sgi; i += 64) before += seg_count[i];
         before = wave_sum64(before);
     }
-    __syncthreads();
-    if (l != 0) return;
     uint32_t nleaf = 0;
     uint64_t rows_all = 0, fl = 0;
     bool open = false, useful = false;
@@ -602,22 +614,25 @@ __global__ __launch_bounds__(64) void k_batch_leaves(const GroupDesc* __restrict
             if (pass == 1) {
                 const uint64_t slot = a.leaf_base + before + nleaf;
                 if (slot < a.leaf_cap) {
-                    LeafDesc L;
-                    L.r0 = lr0;
-                    L.s0 = ls0;
-                    L.kr0 = lr0 + g0.dst_koff;
-                    L.ks0 = ls0 + koff_s;
-                    L.base = llo;
-                    L.out = a.join ? 0 : lr0 + a.out_delta;
-                    L.rn = (uint32_t)lrn;
-                    L.sn = (uint32_t)lsn;
                     const uint64_t span = lhi - llo;
-                    L.bits = (uint16_t)(span ? 64 - __clzll((long long)span) : 0);
-                    L.kb = (uint16_t)a.kb;
-                    L.buf = (uint16_t)a.buf;
-                    L.flags = (uint16_t)a.flags;
-                    leaves[slot] = L;
-                    if (L.bits > 32) fl |= BATCH_WIDE;
+                    const uint32_t bits = span ? 64u - (uint32_t)__clzll((long long)span) : 0u;
+                    if (l == 0) {
+                        LeafDesc L;
+                        L.r0 = lr0;
+                        L.s0 = ls0;
+                        L.kr0 = lr0 + g0.dst_koff;
+                        L.ks0 = ls0 + koff_s;
+                        L.base = llo;
+                        L.out = a.join ? 0 : lr0 + a.out_delta;
+                        L.rn = (uint32_t)lrn;
+                        L.sn = (uint32_t)lsn;
+                        L.bits = (uint16_t)bits;
+                        L.kb = (uint16_t)a.kb;
+                        L.buf = (uint16_t)a.buf;
+                        L.flags = (uint16_t)a.flags;
+                        leaves[slot] = L;
+                    }
+                    if (bits > 32) fl |= BATCH_WIDE;
                 } else {
                     fl |= BATCH_OVERFLOW;
                 }
@@ -628,43 +643,52 @@ __global__ __launch_bounds__(64) void k_batch_leaves(const GroupDesc* __restrict
         open = false;
         useful = false;
     };
-    for (uint32_t d = 0; d < nb; d++) {
-        const ChildRec c = rec[d];
-        const uint64_t rows = (uint64_t)c.rn + c.sn;
-        if (rows == 0) continue;  // occupies no rows: does not break adjacency
-        if (rows > (uint64_t)LEAF_CAP) {
-            fl |= BATCH_NEEDS_HOST;
-            flush();
-            r0 += c.rn;
-            s0 += c.sn;
-            continue;
+#pragma unroll
+    for (int j = 0; j < RPL; j++) {
+        for (uint32_t ln = 0; ln < 64 && j * 64 + ln < nb; ln++) {
+            const uint32_t rn = (uint32_t)__builtin_amdgcn_readlane((int)rrn[j], (int)ln);
+            const uint32_t sn = (uint32_t)__builtin_amdgcn_readlane((int)rsn[j], (int)ln);
+            const uint64_t rows = (uint64_t)rn + sn;
+            if (rows == 0) continue;  // occupies no rows: does not break adjacency
+            if (rows > (uint64_t)LEAF_CAP) {
+                fl |= BATCH_NEEDS_HOST;
+                flush();
+                r0 += rn;
+                s0 += sn;
+                continue;
+            }
+            uint64_t lo = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)rlo0[j], (int)ln) |
+                          ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)rlo1[j], (int)ln) << 32);
+            uint64_t hi = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)rhi0[j], (int)ln) |
+                          ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)rhi1[j], (int)ln) << 32);
+            uint64_t win = 0;
+            if (a.narrowing) {
+                const uint64_t off = lo - g0.base;
+                win = off >> 32;
+                lo = off & 0xffffffffull;
+                hi = (hi - g0.base) & 0xffffffffull;
+            }
+            if (!(open && win == lwin && lrn + lsn + rows <= (uint64_t)LEAF_CAP)) {
+                flush();
+                open = true;
+                lr0 = r0;
+                ls0 = s0;
+                lrn = lsn = 0;
+                llo = lo;
+                lhi = hi;
+                lwin = win;
+            }
+            lrn += rn;
+            lsn += sn;
+            llo = lo < llo ? lo : llo;
+            lhi = hi > lhi ? hi : lhi;
+            useful = useful || !a.join || (rn > 0 && sn > 0);
+            r0 += rn;
+            s0 += sn;
         }
-        uint64_t lo = c.lo, hi = c.hi, win = 0;
-        if (a.narrowing) {
-            const uint64_t off = lo - g0.base;
-            win = off >> 32;
-            lo = off & 0xffffffffull;
-            hi = (hi - g0.base) & 0xffffffffull;
-        }
-        if (!(open && win == lwin && lrn + lsn + rows <= (uint64_t)LEAF_CAP)) {
-            flush();
-            open = true;
-            lr0 = r0;
-            ls0 = s0;
-            lrn = lsn = 0;
-            llo = lo;
-            lhi = hi;
-            lwin = win;
-        }
-        lrn += c.rn;
-        lsn += c.sn;
-        llo = lo < llo ? lo : llo;
-        lhi = hi > lhi ? hi : lhi;
-        useful = useful || !a.join || (c.rn > 0 && c.sn > 0);
-        r0 += c.rn;
-        s0 += c.sn;
     }
     flush();
+    if (l != 0) return;
     if (pass == 0) {
         seg_count[sgi] = nleaf;
         if (fl) atomicOr(&summary[2], (unsigned long long)fl);

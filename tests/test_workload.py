@@ -62,3 +62,46 @@ def test_zipf_head_frequencies():
         assert abs(freq[r] - p[r]) < 5 * se
     u = tjgen.zipf_ranks(m, 0.0, d, 5)
     assert abs(np.bincount(u.astype(np.int64), minlength=d).std() / (m / d)) < 0.1
+
+
+def test_learned_workloads_deterministic_and_shaped():
+    n = 1 << 16
+    for d in tjgen.LEARNED_DISTS:
+        a, b = tjgen.learned(d, n), tjgen.learned(d, n)
+        for c in ("r_keys", "s_keys", "r_rids", "s_rids"):
+            assert np.array_equal(a[c], b[c]), (d, c)
+        assert a["r_keys"].dtype == np.int64 and len(a["s_keys"]) == n
+        assert (a["r_keys"] >= 0).all() and (a["s_keys"] >= 0).all()
+        # 80% of S rows copy an R key (fresh draws may add a few more matches)
+        frac = np.isin(a["s_keys"], a["r_keys"]).mean()
+        assert 0.79 <= frac <= 0.85, (d, frac)
+
+
+def test_lognormal_moments():
+    k = tjgen.lognormal_i64(1 << 18, tjgen.stream(5))
+    lk = np.log(k.astype(np.float64) + 0.5)
+    assert abs(lk.mean() - 30.0) < 0.02 and abs(lk.std() - 2.0) < 0.02
+
+
+def test_mixture_rows_stay_in_their_intervals():
+    k, comp = tjgen.mixture_i64(1 << 17, tjgen.stream(6))
+    lo, width, w = comp[:, 0], comp[:, 1], comp[:, 2]
+    assert np.all((width >= 2.0 ** 20) & (width <= 2.0 ** 50)) and np.all(lo < 2.0 ** 62)
+    inside = np.zeros(len(k), dtype=bool)
+    hits = []
+    for c in range(len(lo)):
+        m = (k >= lo[c]) & (k <= lo[c] + width[c])
+        inside |= m
+        hits.append(m.mean())
+    assert inside.all()
+    # row shares follow the Dirichlet weights (components may overlap: lower bound only)
+    assert all(h >= wc / w.sum() - 0.01 for h, wc in zip(hits, w))
+
+
+def test_seqgap_is_a_shuffled_increasing_sequence():
+    n = 1 << 16
+    k = tjgen.seqgap_i64(n, tjgen.stream(7))
+    s = np.sort(k)
+    g = np.diff(s)
+    assert g.min() >= 1 and abs(g.mean() - 8.0) < 0.1  # 1 + Geometric(1/8): mean 8
+    assert not np.array_equal(k, s)  # shuffled

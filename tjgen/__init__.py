@@ -18,6 +18,14 @@ as stated for each recipe):
   variant gives the 2^20 hottest keys multiplicity 4 in R, so the join size
   is at most 4|S|; the generator returns the exact size.
 * ``sort_uniform64`` n int64 keys uniform over the full 64-bit range.
+* ``learned``        |R| = |S| = n (2^28 at full size), int64 keys from one of
+  three non-uniform distributions: lognormal(mu = 30, sigma = 2) floored;
+  a mixture of 8 uniform intervals placed uniformly in [0, 2^62) with widths
+  2^20 ... 2^50 (log-uniform) and Dirichlet(1) weights; sequential keys with
+  1 + Geometric(1/8) gaps, shuffled. S: 80% of its rows copy the key of a
+  uniformly chosen R row, 20% are fresh draws of the same distribution (a
+  fresh draw may coincide with an R key; the join size is not known in closed
+  form). Row ids are positions.
 """
 from __future__ import annotations
 
@@ -66,6 +74,10 @@ def _load():
         lib.tjgen_r_keys40.argtypes = [_P, u64, u64, u64, u64, u64]
         lib.tjgen_s_keys40.restype = u64
         lib.tjgen_s_keys40.argtypes = [_P, u64, u64, u64, u64, u64, ctypes.c_double, u64, u64, u64]
+        lib.tjgen_lognormal_i64.argtypes = [_P, u64, u64, ctypes.c_double, ctypes.c_double]
+        lib.tjgen_mixture_i64.argtypes = [_P, u64, u64, ctypes.c_uint, ctypes.c_double, ctypes.c_double, _P]
+        lib.tjgen_seqgap_i64.argtypes = [_P, u64, u64, ctypes.c_double]
+        lib.tjgen_fk_from.argtypes = [_P, u64, u64, _P, u64, _P, u64]
         _lib = lib
     return _lib
 
@@ -190,3 +202,63 @@ def sort_uniform64(n: int = 1 << 29, seed: int = BASE_SEED, bits: int = 64) -> W
     """n int64 keys uniform over [0, 2^bits) (bits = 64: the whole signed range)."""
     w = Workload(keys=uniform_i64(n, stream(60 + bits, seed), bits), rids=iota_i32(n))
     return w
+
+
+def lognormal_i64(n: int, seed: int, mu: float = 30.0, sigma: float = 2.0) -> np.ndarray:
+    out = np.empty(n, dtype=np.int64)
+    _load().tjgen_lognormal_i64(_ptr(out), n, seed, mu, sigma)
+    return out
+
+
+def mixture_i64(n: int, seed: int, ncomp: int = 8, wlo: float = 20.0, whi: float = 50.0):
+    """Keys and the (lo, width, weight) rows of the components."""
+    out = np.empty(n, dtype=np.int64)
+    comp = np.zeros((ncomp, 3), dtype=np.float64)
+    _load().tjgen_mixture_i64(_ptr(out), n, seed, ncomp, wlo, whi, _ptr(comp))
+    return out, comp
+
+
+def seqgap_i64(n: int, seed: int, p: float = 0.125) -> np.ndarray:
+    out = np.empty(n, dtype=np.int64)
+    _load().tjgen_seqgap_i64(_ptr(out), n, seed, p)
+    return out
+
+
+LEARNED_DISTS = ("lognormal", "mixture", "seqgap")
+
+
+def _learned_keys(dist: str, n: int, seed: int) -> np.ndarray:
+    if dist == "lognormal":
+        return lognormal_i64(n, seed)
+    if dist == "mixture":
+        return mixture_i64(n, seed)[0]
+    if dist == "seqgap":
+        return seqgap_i64(n, seed)
+    raise ValueError("unknown distribution %r" % dist)
+
+
+def learned(dist: str, n: int = 1 << 28, seed: int = BASE_SEED, matched_frac: float = 0.8) -> Workload:
+    """R and S of n rows each with keys of distribution `dist` (LEARNED_DISTS)."""
+    tag = 80 + LEARNED_DISTS.index(dist)
+    rk = _learned_keys(dist, n, stream(tag * 16 + 1, seed))
+    n_matched = int(n * matched_frac)
+    if dist == "mixture":
+        # fresh S draws come from the same components (same component seed), new row counters
+        fresh = _learned_keys_offset(dist, n - n_matched, stream(tag * 16 + 1, seed), n)
+    elif dist == "seqgap":
+        # fresh keys continue the same process past R's largest key
+        fresh = seqgap_i64(n - n_matched, stream(tag * 16 + 2, seed)) + (int(rk.max()) if n else 0)
+    else:
+        fresh = _learned_keys(dist, n - n_matched, stream(tag * 16 + 2, seed))
+    sk = np.empty(n, dtype=np.int64)
+    _load().tjgen_fk_from(_ptr(sk), n, n_matched, _ptr(rk), n, _ptr(fresh), stream(tag * 16 + 3, seed))
+    w = Workload(r_keys=rk, r_rids=iota_i32(n), s_keys=sk, s_rids=iota_i32(n))
+    w.expected_count = None
+    w.dist = dist
+    return w
+
+
+def _learned_keys_offset(dist: str, n: int, seed: int, skip: int) -> np.ndarray:
+    """Rows skip .. skip + n - 1 of the mixture stream `seed` (same components)."""
+    allk = mixture_i64(skip + n, seed)[0]
+    return np.ascontiguousarray(allk[skip:])

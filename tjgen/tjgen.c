@@ -19,6 +19,7 @@
 #include <stdint.h>
 #include <math.h>
 #include <stddef.h>
+#include <stdlib.h>
 
 #define GOLDEN_GAMMA 0x9E3779B97F4A7C15ull
 
@@ -304,4 +305,141 @@ uint64_t tjgen_s_keys40(int64_t *out, uint64_t n_s, uint64_t n_matched, uint64_t
         out[i] = (int64_t)bij_apply(&f, d);
     }
     return total;
+}
+
+/* ---------------------------------------------------------------------------
+ * Learned-partitioner workloads: int64 keys with non-uniform distributions.
+ * Every value i draws from its own SplitMix64 counters (seed, 2i), (seed, 2i+1).
+ * ------------------------------------------------------------------------- */
+
+/* uniform in (0, 1]: never 0, so its logarithm is finite */
+static inline double u01_open(uint64_t r)
+{
+    return ((double)(r >> 11) + 1.0) * (1.0 / 9007199254740992.0);
+}
+
+static inline int64_t clamp_key(double v)
+{
+    if (!(v >= 0.0)) return 0;
+    if (v >= 9223372036854775807.0) return INT64_MAX;
+    return (int64_t)v;
+}
+
+/* keys_i = floor(exp(mu + sigma * z_i)), z_i standard normal (Box-Muller with
+ * two uniforms of the row's own counters), clamped to [0, INT64_MAX]. */
+void tjgen_lognormal_i64(int64_t *out, uint64_t n, uint64_t seed, double mu, double sigma)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    long long i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < (long long)n; i++) {
+        double u1 = u01_open(tjgen_splitmix64(seed, 2 * (uint64_t)i));
+        double u2 = u01(tjgen_splitmix64(seed, 2 * (uint64_t)i + 1));
+        double z = sqrt(-2.0 * log(u1)) * cos(two_pi * u2);
+        out[i] = clamp_key(floor(exp(mu + sigma * z)));
+    }
+}
+
+/* Mixture of `ncomp` (<= 64) uniform intervals. Component c starts at a
+ * uniform point of [0, 2^62), has width 2^(wlo + (whi - wlo) u) and weight
+ * proportional to -log(u) (Dirichlet(1, ..., 1) weights); all drawn from
+ * `seed` before any row. Row i picks a component by the weights and a uniform
+ * offset inside it. lo/width/weight of the components are written to comp[3*ncomp]
+ * (as doubles) when comp is not NULL. */
+void tjgen_mixture_i64(int64_t *out, uint64_t n, uint64_t seed, unsigned ncomp, double wlo, double whi,
+                       double *comp)
+{
+    uint64_t lo[64];
+    double width[64], cum[64], tot = 0.0;
+    unsigned c;
+    if (ncomp == 0 || ncomp > 64) return;
+    for (c = 0; c < ncomp; c++) {
+        uint64_t r0 = tjgen_splitmix64(seed, 3 * (uint64_t)c);
+        lo[c] = r0 >> 2;
+        width[c] = exp2(wlo + (whi - wlo) * u01(tjgen_splitmix64(seed, 3 * (uint64_t)c + 1)));
+        double w = -log(u01_open(tjgen_splitmix64(seed, 3 * (uint64_t)c + 2)));
+        tot += w;
+        cum[c] = tot;
+        if (comp) {
+            comp[3 * c] = (double)lo[c];
+            comp[3 * c + 1] = width[c];
+            comp[3 * c + 2] = w;
+        }
+    }
+    const uint64_t rs = tjgen_splitmix64(seed, 1000003);
+    long long i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < (long long)n; i++) {
+        double u = u01(tjgen_splitmix64(rs, 2 * (uint64_t)i)) * tot;
+        unsigned k = 0;
+        while (k + 1 < ncomp && u >= cum[k]) k++;
+        uint64_t off = (uint64_t)(u01(tjgen_splitmix64(rs, 2 * (uint64_t)i + 1)) * width[k]);
+        uint64_t v = lo[k] + off;
+        out[i] = v > (uint64_t)INT64_MAX ? INT64_MAX : (int64_t)v;
+    }
+}
+
+/* Sequential keys with random gaps, shuffled: the j-th smallest key is
+ * k_j = j + sum_{t <= j} g_t with g_t ~ Geometric(p) on {0, 1, ...} (so
+ * consecutive keys differ by 1 + g); row i holds k_{perm(i)}. The gaps come
+ * from a counter-based stream, the prefix sum runs in blocks. */
+void tjgen_seqgap_i64(int64_t *out, uint64_t n, uint64_t seed, double p)
+{
+    if (n == 0) return;
+    int64_t *seq = out;  /* the ordered keys are built in place, then shuffled below */
+    const double lq = log1p(-p);
+    const uint64_t gs = tjgen_splitmix64(seed, 7);
+    long long i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < (long long)n; i++) {
+        double u = u01_open(tjgen_splitmix64(gs, (uint64_t)i));
+        seq[i] = 1 + (int64_t)floor(log(u) / lq);  /* 1 + Geometric(p) */
+    }
+    /* inclusive prefix sum, two-level */
+    const uint64_t B = 1u << 16;
+    const uint64_t nb = (n + B - 1) / B;
+    int64_t *bsum = (int64_t *)malloc(nb * sizeof(int64_t));
+    long long b;
+#pragma omp parallel for schedule(static)
+    for (b = 0; b < (long long)nb; b++) {
+        uint64_t e = ((uint64_t)b + 1) * B < n ? ((uint64_t)b + 1) * B : n;
+        int64_t s = 0;
+        for (uint64_t j = (uint64_t)b * B; j < e; j++) { s += seq[j]; seq[j] = s; }
+        bsum[b] = s;
+    }
+    int64_t run = 0;
+    for (uint64_t j = 0; j < nb; j++) { int64_t t = bsum[j]; bsum[j] = run; run += t; }
+#pragma omp parallel for schedule(static)
+    for (b = 0; b < (long long)nb; b++) {
+        uint64_t e = ((uint64_t)b + 1) * B < n ? ((uint64_t)b + 1) * B : n;
+        for (uint64_t j = (uint64_t)b * B; j < e; j++) seq[j] += bsum[b];
+    }
+    free(bsum);
+    /* shuffle: cycle-walk permutation, applied out of place through a copy */
+    int64_t *tmp = (int64_t *)malloc(n * sizeof(int64_t));
+    perm_t pm = perm_make(n, tjgen_splitmix64(seed, 11));
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < (long long)n; i++) tmp[i] = seq[perm_apply(&pm, (uint64_t)i)];
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < (long long)n; i++) out[i] = tmp[i];
+    free(tmp);
+}
+
+/* S of a foreign-key pair: the first n_matched rows copy the key of a uniform
+ * random R row, the rest come from fresh[] (draws of R's distribution with
+ * another seed); then rows are shuffled by a seeded permutation. */
+void tjgen_fk_from(int64_t *out, uint64_t n_s, uint64_t n_matched, const int64_t *r, uint64_t n_r,
+                   const int64_t *fresh, uint64_t seed)
+{
+    if (n_s == 0) return;
+    int64_t *tmp = (int64_t *)malloc(n_s * sizeof(int64_t));
+    long long i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < (long long)n_s; i++)
+        tmp[i] = (uint64_t)i < n_matched ? r[below(tjgen_splitmix64(seed, (uint64_t)i), n_r)]
+                                         : fresh[(uint64_t)i - n_matched];
+    perm_t pm = perm_make(n_s, tjgen_splitmix64(seed, ~0ull));
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < (long long)n_s; i++) out[i] = tmp[perm_apply(&pm, (uint64_t)i)];
+    free(tmp);
 }

@@ -65,6 +65,9 @@ typedef struct {
     uint32_t leaves;          /* per-bucket LDS sort / join blocks */
     uint32_t single_key;      /* buckets holding a single key value */
     uint32_t key_ranges;      /* key ranges processed one at a time (1 = budget not binding) */
+    uint32_t learned;         /* 1 when the first pass used the learned bucket function */
+    uint32_t learned_overflow;/* buckets of that pass holding more than twice the mean */
+    uint64_t sample_rows;     /* keys the learned model was fitted to */
 } tj_stats_t;
 
 /*
@@ -120,6 +123,110 @@ int tj_join_materialize(int key_type, const void *r_keys, const int32_t *r_rids,
                         const void *s_keys, const int32_t *s_rids, uint64_t n_s,
                         int32_t *out_r, int32_t *out_s, uint64_t capacity, uint64_t *count,
                         void *workspace, uint64_t workspace_bytes, void *stream, tj_stats_t *stats);
+
+/*
+ * Learned CDF partitioner.
+ *
+ * The paper lets what the execution stage observes about the data decide how
+ * the tensor path runs (Sec. III.C). Here that observation is a sample of the
+ * keys, and what it decides is the bucket function of the first partition
+ * pass: a two-layer recursive model index (RMI) that estimates each key's
+ * rank replaces the radix digit, so that buckets hold similar row counts even
+ * for skewed key distributions, where radix digits over the key range leave
+ * most rows in a few buckets and need extra passes. Later passes use radix
+ * digits over each bucket's own key range (a bucket is never split by the
+ * model again), and the leaf sorts and joins are unchanged, so results are
+ * bit-identical to the radix path: the bucket function only has to be
+ * non-decreasing in the key, which the model guarantees by construction.
+ *
+ * Model (all keys as ordinals: ord(k) = k XOR 2^63 for int64, k XOR 2^31 for
+ * int32, as unsigned; every float operation is one IEEE f32 operation rounded
+ * to nearest even, never fused):
+ *   root:   j = the largest i in [0, TJ_RMI_SEGMENTS - 1] with i = 0 or
+ *           knot[i] <= x; d = clamp(x, knot[j], knot[j+1]) - knot[j];
+ *           t = f32(d) * knot_inv[j]; leaf = 4 j + min(floor(4 t), 3).
+ *   leaf l: sd = x - leaf_base[l] as a signed integer saturated to +-2^62;
+ *           y = leaf_a[l] + leaf_b[l] * f32(sd);
+ *           bucket = floor(clamp(y, leaf_lo[l], leaf_hi[l])).
+ * Training (tj_rmi_train, and the learned calls): a relation of n rows is
+ * sampled at positions floor(i n / m), i < m = max(min(n, 2048),
+ * n * permille / 1000); a join samples R and S and fits one model to the
+ * union. The sample is sorted by the plain (radix) sort path. knot[i] is the
+ * sorted sample's element floor(i (M - 1) / TJ_RMI_SEGMENTS) (M sample rows),
+ * knot_inv[i] = f32(1 / f64(knot[i+1] - knot[i])) or 0 for equal knots. Each
+ * leaf is fitted by least squares (fp64 sums) to its sample points with
+ * targets F i / M (i = rank in the sample, F = buckets), slope clamped at 0;
+ * leaf_lo/leaf_hi are the buckets of its first and last point, and a leaf
+ * without points takes the next leaf's leaf_lo for both. Hence leaf_hi[l] <=
+ * leaf_lo[l+1], which with slopes >= 0 makes the bucket non-decreasing in x.
+ */
+#define TJ_RMI_SEGMENTS 256
+#define TJ_RMI_LEAVES 1024
+typedef struct {
+    uint64_t knot[TJ_RMI_SEGMENTS + 1];  /* key ordinals, non-decreasing */
+    float knot_inv[TJ_RMI_SEGMENTS];
+    uint64_t leaf_base[TJ_RMI_LEAVES];   /* key ordinal of each leaf's first sample point */
+    float leaf_a[TJ_RMI_LEAVES];         /* intercept, in buckets */
+    float leaf_b[TJ_RMI_LEAVES];         /* slope, in buckets per ordinal step (>= 0) */
+    uint16_t leaf_lo[TJ_RMI_LEAVES];
+    uint16_t leaf_hi[TJ_RMI_LEAVES];
+    uint32_t buckets;                    /* F: buckets of the learned pass (512) */
+    uint32_t sample_rows;                /* M */
+} tj_rmi_t;
+
+enum tj_partitioner { TJ_PART_RADIX = 0, TJ_PART_LEARNED = 1 };
+typedef struct {
+    uint32_t partitioner;       /* TJ_PART_RADIX or TJ_PART_LEARNED */
+    uint32_t sample_permille;   /* sample per relation in 1/1000 of its rows; 0 means 10 (1%) */
+    uint64_t learned_min_rows;  /* rows (R + S) below which the radix digit is kept; 0 means 2^22.
+                                   Values below 8193 act as 8193 (one LDS block holds smaller inputs) */
+} tj_options_t;
+
+/*
+ * tj_sort_ex, tj_join_count_ex, tj_join_materialize_ex: tj_sort, tj_join_count
+ * and tj_join_materialize with options (opt may be NULL: radix, as the plain
+ * calls). TJ_PART_LEARNED applies when the workspace holds the full plan (at
+ * least full_bytes of tj_workspace_query) and the call has at least
+ * learned_min_rows rows; otherwise the call runs the radix path (stats.learned
+ * tells which ran). The model is trained on the call's stream inside the
+ * workspace; arguments, errors and results are those of the plain calls.
+ * Unknown partitioner values give TJ_E_ARG.
+ */
+int tj_sort_ex(int key_type, const void *keys_in, const int32_t *rids_in, uint64_t n,
+               void *keys_out, int32_t *rids_out, void *workspace, uint64_t workspace_bytes,
+               void *stream, const tj_options_t *opt, tj_stats_t *stats);
+int tj_join_count_ex(int key_type, const void *r_keys, uint64_t n_r, const void *s_keys, uint64_t n_s,
+                     uint64_t *count, void *workspace, uint64_t workspace_bytes, void *stream,
+                     const tj_options_t *opt, tj_stats_t *stats);
+int tj_join_materialize_ex(int key_type, const void *r_keys, const int32_t *r_rids, uint64_t n_r,
+                           const void *s_keys, const int32_t *s_rids, uint64_t n_s,
+                           int32_t *out_r, int32_t *out_s, uint64_t capacity, uint64_t *count,
+                           void *workspace, uint64_t workspace_bytes, void *stream,
+                           const tj_options_t *opt, tj_stats_t *stats);
+
+/*
+ * tj_rmi_workspace_query: device workspace bytes tj_rmi_train needs for
+ * relations of n_a and n_b rows (n_b = 0: one relation). Host only.
+ * tj_rmi_train: fits the model to the sample of keys_a[n_a] and, when n_b > 0,
+ * keys_b[n_b] (device key columns), on the GPU, and copies it to *model (host
+ * memory). permille 0 means 10. Synchronises `stream` before returning.
+ * Errors: TJ_E_ARG (bad key type, NULL pointers, n_a = 0), TJ_E_TOO_LARGE,
+ * TJ_E_WORKSPACE (below the queried size or misaligned), TJ_E_HIP.
+ */
+int tj_rmi_workspace_query(int key_type, uint64_t n_a, uint64_t n_b, uint32_t permille, uint64_t *bytes);
+int tj_rmi_train(int key_type, const void *keys_a, uint64_t n_a, const void *keys_b, uint64_t n_b,
+                 uint32_t permille, tj_rmi_t *model, void *workspace, uint64_t workspace_bytes,
+                 void *stream);
+/*
+ * tj_rmi_buckets: buckets[i] = bucket(ord(keys[i])) of the model *model (host
+ * memory, copied to the workspace, which needs sizeof(tj_rmi_t) bytes,
+ * 256-byte aligned) for n device keys, into the device array buckets[n].
+ * The model must satisfy the layout rules above (knots non-decreasing,
+ * 0 < buckets <= 512, leaf_lo <= leaf_hi < buckets): TJ_E_ARG otherwise.
+ * Stream-ordered; returns without synchronising.
+ */
+int tj_rmi_buckets(int key_type, const void *keys, uint64_t n, const tj_rmi_t *model,
+                   uint16_t *buckets, void *workspace, uint64_t workspace_bytes, void *stream);
 
 /*
  * Per-kernel timing (profiling hook). tj_timing(1) clears the counters and

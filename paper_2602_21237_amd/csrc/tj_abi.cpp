@@ -26,6 +26,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -42,6 +43,12 @@ constexpr uint64_t TARGET_CHUNKS = 2048;  // blocks per partition pass
 // widest digit a partition pass uses (at most MAX_DIGIT_BITS)
 constexpr int PASS_DIGIT_BITS = TJ_PASS_DIGIT_BITS;
 constexpr size_t DEVICE_BATCH_MIN_SEGS = 16;  // segments of a pass before leaves are batched on the device
+// learned partitioner defaults (tj_options_t)
+constexpr uint32_t LEARNED_BUCKETS = 512;        // buckets of the learned pass: one full-width digit
+constexpr uint32_t DEFAULT_PERMILLE = 10;        // 1% sample per relation
+constexpr uint64_t DEFAULT_LEARNED_MIN_ROWS = 1ull << 22;
+static_assert((LEARNED_BUCKETS & (LEARNED_BUCKETS - 1)) == 0 && LEARNED_BUCKETS <= (uint32_t)NB,
+              "learned buckets must be one digit of the scatter");
 
 inline uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
@@ -83,6 +90,7 @@ uint64_t table_bytes(const Caps& c)
     b += align_up((uint64_t)c.groups * 4, ALIGN);                     // leaves per segment
     const uint64_t ub = sizeof(CrossDesc) > sizeof(CopyDesc) ? sizeof(CrossDesc) : sizeof(CopyDesc);
     b += align_up((uint64_t)c.units * ub, ALIGN);
+    b += align_up(sizeof(tj_rmi_t), ALIGN);                           // learned model
     return b;
 }
 
@@ -129,9 +137,10 @@ struct Shape {
     uint64_t n_r, n_s;
 };
 
-// Data bytes of the unlimited plan: the sort keeps one buffer in the
-// workspace (its other buffer is the caller's output), the join two per side.
-uint64_t full_data_bytes(const Shape& s)
+// Bytes of the ping-pong buffers of the unlimited plan: the sort keeps one
+// buffer in the workspace (its other buffer is the caller's output), the join
+// two per side.
+uint64_t buffer_data_bytes(const Shape& s)
 {
     const int nbuf = s.join ? 2 : 1;
     uint64_t b = 0;
@@ -154,6 +163,40 @@ uint64_t min_data_bytes(const Shape& s)
 }
 
 const uint64_t kMaxRows = (1ull << 31) - 1;
+
+// Sample rows of a relation of n rows: max(min(n, 2048), n * permille / 1000).
+inline uint64_t rmi_sample_rows(uint64_t n, uint32_t permille)
+{
+    const uint64_t a = std::min<uint64_t>(n, 2048), b = n * permille / 1000;
+    return std::max(a, b);
+}
+
+// Training scratch of the learned partitioner for M sample rows: the sample,
+// its sorted copy (keys and rids), the leaf run starts, and a workspace for
+// the sample's sort (`full`: the sort's unlimited workspace, else its minimum).
+uint64_t rmi_scratch_bytes(int kb, uint64_t M, bool full)
+{
+    const Shape ss{TJ_OP_SORT, kb, false, false, true, M, 0};
+    const uint64_t sort_ws = full ? table_bytes(tier_caps(TABLE_TIERS - 1)) + buffer_data_bytes(ss)
+                                  : table_bytes(tier_caps(0)) + min_data_bytes(ss);
+    return 2 * align_up(M * (uint64_t)kb, ALIGN) + 2 * align_up(M * 4, ALIGN) +
+           align_up((TJ_RMI_LEAVES + 1) * 4, ALIGN) + sort_ws;
+}
+
+// Data bytes of the unlimited plan: the ping-pong buffers, and at least room
+// in buffer B (free until the second pass) to train the learned partitioner
+// at its default sample rate.
+uint64_t full_data_bytes(const Shape& s)
+{
+    const uint64_t buffers = buffer_data_bytes(s);
+    uint64_t b_off = 0;  // buffer B follows buffer A (join); the sort's B starts the region
+    if (s.join) {
+        const Shape a{s.op, s.kb, false, s.mat, s.rids, s.n_r, s.n_s};
+        b_off = buffer_data_bytes(a);
+    }
+    const uint64_t M = rmi_sample_rows(s.n_r, 10) + (s.join ? rmi_sample_rows(s.n_s, 10) : 0);
+    return std::max(buffers, b_off + rmi_scratch_bytes(s.kb, M, false));
+}
 
 // ---------------------------------------------------------------------------
 // The executor of one call.
@@ -196,10 +239,11 @@ struct Unit {                 // a final piece of join output, ordered by key
 // Kernel timing registry (tj_timing / tj_timing_read).
 // ---------------------------------------------------------------------------
 enum Fam { F_PROBE, F_HIST, F_SCAN, F_SCATTER, F_LEAF_SORT, F_LEAF_COUNT, F_LEAF_MAT, F_CROSS, F_COPY,
-           F_EXPAND, F_HOST_CLASSIFY, F_HOST_LEAVES, NFAM };
+           F_EXPAND, F_HOST_CLASSIFY, F_HOST_LEAVES, F_RMI_TRAIN, F_LHIST, F_LSCATTER, NFAM };
 const char* const kFamName[NFAM] = {"probe", "histogram", "scan", "scatter", "leaf_sort",
                                     "leaf_join_count", "leaf_join_mat", "cross", "copy", "expand",
-                                    "host_classify", "host_leaves"};
+                                    "host_classify", "host_leaves", "rmi_train", "learned_hist",
+                                    "learned_scatter"};
 
 struct Timing {
     std::mutex mu;
@@ -213,6 +257,10 @@ Timing& timing()
     static Timing t;
     return t;
 }
+
+// Set while a call runs the plain sort on its own sample (training of the
+// learned model): that inner call's launches are timed as part of rmi_train.
+thread_local int t_nested = 0;
 
 // Process-wide self-test flags (tj_debug_set_flags).
 std::atomic<uint32_t> g_debug_flags{0};
@@ -286,6 +334,9 @@ struct Exec {
     // scalars in the probe block: [0..1] min/max, [2] pair total, [3] ticket (low) + error (high),
     // [4..6] device batching summary (leaves, rows, flags)
     void* d_units = nullptr;
+    tj_rmi_t* d_model = nullptr;    // learned bucket function (when trained)
+    BktSet bkt{};                   // per-row buckets of the learned pass
+    bool learned_pass = false;      // the next partition pass is the learned one
 
     // data buffer capacities (rows per side) when the buffers live in the workspace
     uint64_t cap_r = 0, cap_s = 0;
@@ -392,6 +443,7 @@ struct Exec {
         d_segcount = (uint32_t*)take((uint64_t)caps.groups * 4);
         const uint64_t ub = sizeof(CrossDesc) > sizeof(CopyDesc) ? sizeof(CrossDesc) : sizeof(CopyDesc);
         d_units = take((uint64_t)caps.units * ub);
+        d_model = (tj_rmi_t*)take(sizeof(tj_rmi_t));
         return p <= end ? TJ_OK : TJ_E_WORKSPACE;
     }
 
@@ -404,6 +456,9 @@ struct Exec {
     {
         stats.passes++;
         const int nside = sh.join ? 2 : 1;
+        // the learned pass partitions the root segment(s) of an unfiltered range once
+        const bool learned = learned_pass && !filter;
+        learned_pass = false;
         // per segment digit choice
         struct Plan {
             uint32_t shift, bits, kb_out;
@@ -423,12 +478,18 @@ struct Exec {
             // join keys are narrowed to 4 bytes once every child spans at most
             // 2^32 ordinals; the sort writes its keys out and never narrows
             plan[i].kb_out = sh.join && write_keys && s.kb == 8 && plan[i].shift <= 32 ? 4u : s.kb;
+            if (learned) {
+                // the model's buckets are the digits; children keep their key width
+                plan[i].bits = nbits64(LEARNED_BUCKETS) - 1;
+                plan[i].shift = 0;
+                plan[i].kb_out = s.kb;
+            }
             total_rows += filter ? (uint64_t)(i == 0 ? sh.n_r + sh.n_s : 0) : rows;
         }
         // Device batching pays where the children are expected to be leaves and
         // are many: one wave walks each segment's children in turn (~0.1 ms),
         // while the host needs about 5 ns per child.
-        if (segs.size() < DEVICE_BATCH_MIN_SEGS) dev_ok = false;
+        if (segs.size() < DEVICE_BATCH_MIN_SEGS || learned) dev_ok = false;
         if (dev_ok)
             for (size_t i = 0; i < segs.size(); i++)
                 if (((segs[i].rn + segs[i].sn) >> plan[i].bits) > (uint64_t)LEAF_CAP / 2) dev_ok = false;
@@ -477,7 +538,7 @@ struct Exec {
                     g.start = filter ? 0 : (side ? s.s0 : s.r0);
                     g.len = len;
                     g.dst_start = filter ? 0 : (side ? s.s0 : s.r0);
-                    g.base = s.lo;
+                    g.base = learned ? 0 : s.lo;
                     g.flo = filter ? filter[0] : 0;
                     g.fhi = filter ? filter[1] : ~0ull;
                     g.shift = plan[si].shift;
@@ -531,16 +592,33 @@ struct Exec {
                 moved += g.side ? s.sn : s.rn;
             }
             const uint64_t rb = row_bytes((int)kb_in, sh.rids), wb = (write_keys ? kb_out : 0) + (sh.rids ? 4 : 0);
-            TJ_CK(timed(F_HIST, scanned * kb_in, [&] {
-                return launch_hist((int)kb_in, d_chunks, nc, d_groups, bufs, d_hist, d_gmin, d_gmax, st);
-            }));
+            if (learned) {
+                // bucket ids: 2 bytes written per row by the histogram, read by the scatter
+                TJ_CK(timed(F_LHIST, scanned * (kb_in + 2), [&] {
+                    return launch_learned_hist((int)kb_in, d_chunks, nc, d_groups, bufs, d_model, bkt, d_hist,
+                                               d_gmin, d_gmax, st);
+                }));
+                stats.bytes_written += scanned * 2;
+                stats.bytes_read += scanned * 2;
+            } else {
+                TJ_CK(timed(F_HIST, scanned * kb_in, [&] {
+                    return launch_hist((int)kb_in, d_chunks, nc, d_groups, bufs, d_hist, d_gmin, d_gmax, st);
+                }));
+            }
             TJ_CK(timed(F_SCAN, 0, [&] {
                 return launch_scan(d_cblocks, ncb, d_groups, ng, d_hist, d_cbsum, d_ccount, d_cstart, st);
             }));
-            TJ_CK(timed(F_SCATTER, scanned * rb + moved * wb, [&] {
-                return launch_scatter((int)kb_in, (int)kb_out, sh.rids, write_keys, d_chunks, nc, d_groups, d_hist, d_cbsum,
-                                      d_cstart, bufs, st);
-            }));
+            if (learned) {
+                TJ_CK(timed(F_LSCATTER, scanned * (rb + 2) + moved * wb, [&] {
+                    return launch_learned_scatter((int)kb_in, sh.rids, d_chunks, nc, d_groups, d_hist, d_cbsum,
+                                                  d_cstart, bufs, bkt, st);
+                }));
+            } else {
+                TJ_CK(timed(F_SCATTER, scanned * rb + moved * wb, [&] {
+                    return launch_scatter((int)kb_in, (int)kb_out, sh.rids, write_keys, d_chunks, nc, d_groups, d_hist,
+                                          d_cbsum, d_cstart, bufs, st);
+                }));
+            }
             // one compact record per child (both sides folded)
             const uint32_t nrec = child / (uint32_t)nside;
             TJ_CK(launch_children(d_groups, ng, nside, d_ccount, d_gmin, d_gmax, d_crec, st));
@@ -586,6 +664,13 @@ struct Exec {
             // rows start where its smaller-digit siblings end
             HostTimer ht(this, F_HOST_CLASSIFY);
             uint64_t moved_rows = 0;
+            if (learned) {
+                // buckets over twice the mean (they take further radix passes)
+                uint64_t rows = 0;
+                for (uint32_t i = 0; i < nrec; i++) rows += rec[i].rn + rec[i].sn;
+                for (uint32_t i = 0; i < nrec; i++)
+                    if ((uint64_t)(rec[i].rn + rec[i].sn) * nrec > 2 * rows) stats.learned_overflow++;
+            }
             for (uint32_t gi = 0; gi < ng; gi += (uint32_t)nside) {
                 const GroupDesc& g0 = groups[gi];
                 const uint32_t nbins = 1u << g0.bits;
@@ -734,6 +819,49 @@ struct Exec {
             return;
         }
         next.push_back(s);
+    }
+
+    // ---- learned partitioner: fit d_model to a sample of the key columns ----
+    // Gathers the sample of a (and of b, when nb > 0), sorts it with the plain
+    // sort path and runs the fit kernels, all inside scratch[0, scratch_bytes)
+    // (device memory nothing else uses meanwhile). TJ_E_WORKSPACE when the
+    // scratch cannot hold the sample and the sort's smallest workspace.
+    int train_rmi(const void* a, uint64_t na, const void* b, uint64_t nb, uint32_t permille, char* scratch,
+                  uint64_t scratch_bytes)
+    {
+        const uint64_t ma = rmi_sample_rows(na, permille), mb = nb ? rmi_sample_rows(nb, permille) : 0;
+        const uint64_t M = ma + mb;
+        if (M == 0 || M > kMaxRows) return TJ_E_ARG;
+        char* p = scratch;
+        char* end = scratch + scratch_bytes;
+        auto take = [&](uint64_t bytes) -> char* {
+            char* q = p;
+            p += align_up(bytes, ALIGN);
+            return q;
+        };
+        const int kb = sh.kb;
+        char* skeys = take(M * kb);
+        int32_t* srids = (int32_t*)take(M * 4);
+        char* okeys = take(M * kb);
+        int32_t* orids = (int32_t*)take(M * 4);
+        uint32_t* start = (uint32_t*)take((TJ_RMI_LEAVES + 1) * 4);
+        if (p >= end) return TJ_E_WORKSPACE;
+        int rc = TJ_OK;
+        const hipError_t e = timed(F_RMI_TRAIN, M * (uint64_t)(2 * kb + 8), [&]() -> hipError_t {
+            hipError_t h = launch_rmi_sample(kb, a, na, (uint32_t)ma, skeys, srids, 0, st);
+            if (h == hipSuccess && mb) h = launch_rmi_sample(kb, b, nb, (uint32_t)mb, skeys, srids, (uint32_t)ma, st);
+            if (h != hipSuccess) return h;
+            t_nested++;
+            rc = tj_sort(kb, skeys, srids, M, okeys, orids, p, (uint64_t)(end - p), st, nullptr);
+            t_nested--;
+            if (rc != TJ_OK) return hipSuccess;
+            return launch_rmi_fit(kb, okeys, (uint32_t)M, LEARNED_BUCKETS, start, d_model, st);
+        });
+        if (rc != TJ_OK) return rc;
+        TJ_CK(e);
+        stats.sample_rows = M;
+        stats.bytes_read += M * (uint64_t)kb;
+        return TJ_OK;
     }
 
     // ---- process one key range (the whole domain when the budget does not bind)
@@ -1369,11 +1497,38 @@ int tj_workspace_query(int op, int key_type, uint64_t n_r, uint64_t n_s, uint64_
     return TJ_OK;
 }
 
-int tj_sort(int key_type, const void* keys_in, const int32_t* rids_in, uint64_t n, void* keys_out,
-            int32_t* rids_out, void* workspace, uint64_t workspace_bytes, void* stream,
-            tj_stats_t* stats)
+}  // extern "C"
+
+namespace tj {
+namespace {
+
+// Learned options in effect for a call: false means the radix path.
+int learned_wanted(const tj_options_t* opt, uint64_t rows, bool& want, uint32_t& permille)
+{
+    want = false;
+    permille = DEFAULT_PERMILLE;
+    if (!opt) return TJ_OK;
+    if (opt->partitioner != TJ_PART_RADIX && opt->partitioner != TJ_PART_LEARNED) return TJ_E_ARG;
+    if (opt->partitioner == TJ_PART_RADIX) return TJ_OK;
+    if (opt->sample_permille > 1000) return TJ_E_ARG;
+    if (opt->sample_permille) permille = opt->sample_permille;
+    uint64_t min_rows = opt->learned_min_rows ? opt->learned_min_rows : DEFAULT_LEARNED_MIN_ROWS;
+    if (min_rows < (uint64_t)LEAF_CAP + 1) min_rows = (uint64_t)LEAF_CAP + 1;
+    want = rows >= min_rows;
+    return TJ_OK;
+}
+
+}  // namespace
+}  // namespace tj
+
+static int sort_impl(int key_type, const void* keys_in, const int32_t* rids_in, uint64_t n, void* keys_out,
+                     int32_t* rids_out, void* workspace, uint64_t workspace_bytes, void* stream,
+                     const tj_options_t* opt, tj_stats_t* stats)
 {
     if (validate_common(key_type) != TJ_OK) return TJ_E_ARG;
+    bool want_learned;
+    uint32_t permille;
+    TJ_RET(learned_wanted(opt, n, want_learned, permille));
     if (n > kMaxRows) return TJ_E_TOO_LARGE;
     if (stats) std::memset(stats, 0, sizeof(*stats));
     if (n == 0) return TJ_OK;
@@ -1389,7 +1544,7 @@ int tj_sort(int key_type, const void* keys_in, const int32_t* rids_in, uint64_t 
     if (overlap(keys_out, kbytes, rids_out, rbytes)) return TJ_E_ALIAS;
 
     Exec x;
-    x.timed_on = timing_enabled();
+    x.timed_on = timing_enabled() && !t_nested;
     x.sh = Shape{TJ_OP_SORT, key_type, false, false, true, n, 0};
     x.st = (hipStream_t)stream;
     int tier;
@@ -1407,10 +1562,24 @@ int tj_sort(int key_type, const void* keys_in, const int32_t* rids_in, uint64_t 
     x.bufs.rid[BUF_A][0] = rids_out;
     x.out_is_a = unlimited;
 
-    uint64_t lo, hi;
-    TJ_RET(probe(x, keys_in, n, nullptr, 0, lo, hi));
+    bool learned = false;
+    if (unlimited && want_learned) {
+        // buffer B (workspace) is free until the second pass: the training
+        // scratch, then the learned pass's bucket ids
+        char* b0 = (char*)x.bufs.key[BUF_B][0];
+        const int rc = x.train_rmi(keys_in, n, nullptr, 0, permille, b0, (uint64_t)(end - b0));
+        if (rc != TJ_OK && rc != TJ_E_WORKSPACE) return rc;
+        learned = rc == TJ_OK;
+    }
+    uint64_t lo = 0, hi = ~0ull;
+    if (!learned) TJ_RET(probe(x, keys_in, n, nullptr, 0, lo, hi));
     if (unlimited) {
         x.stats.key_ranges = 1;
+        if (learned) {
+            x.bkt.b[0] = (uint16_t*)x.bufs.key[BUF_B][0];
+            x.learned_pass = true;
+            x.stats.learned = 1;
+        }
         TJ_RET(x.process_range(lo, hi, n, 0, false, 0));
         TJ_RET(x.run_sort_leaves(keys_out, rids_out));
     } else {
@@ -1461,9 +1630,13 @@ int tj_sort(int key_type, const void* keys_in, const int32_t* rids_in, uint64_t 
 static int join_impl(int key_type, const void* r_keys, const int32_t* r_rids, uint64_t n_r,
                      const void* s_keys, const int32_t* s_rids, uint64_t n_s, int32_t* out_r,
                      int32_t* out_s, uint64_t capacity, uint64_t* count, void* workspace,
-                     uint64_t workspace_bytes, void* stream, tj_stats_t* stats, bool mat)
+                     uint64_t workspace_bytes, void* stream, tj_stats_t* stats, bool mat,
+                     const tj_options_t* opt)
 {
     if (validate_common(key_type) != TJ_OK) return TJ_E_ARG;
+    bool want_learned;
+    uint32_t permille;
+    TJ_RET(learned_wanted(opt, n_r + n_s, want_learned, permille));
     if (!count) return TJ_E_ARG;
     if (n_r > kMaxRows || n_s > kMaxRows) return TJ_E_TOO_LARGE;
     if (stats) std::memset(stats, 0, sizeof(*stats));
@@ -1486,7 +1659,7 @@ static int join_impl(int key_type, const void* r_keys, const int32_t* r_rids, ui
     }
 
     Exec x;
-    x.timed_on = timing_enabled();
+    x.timed_on = timing_enabled() && !t_nested;
     x.sh = Shape{mat ? TJ_OP_JOIN_MATERIALIZE : TJ_OP_JOIN_COUNT, key_type, true, mat, mat, n_r, n_s};
     x.st = (hipStream_t)stream;
     int tier;
@@ -1503,11 +1676,25 @@ static int join_impl(int key_type, const void* r_keys, const int32_t* r_rids, ui
     x.bufs.rid[BUF_IN][0] = r_rids;
     x.bufs.rid[BUF_IN][1] = s_rids;
 
-    uint64_t lo, hi;
-    TJ_RET(probe(x, r_keys, n_r, s_keys, n_s, lo, hi));
+    bool learned = false;
+    if (unlimited && want_learned) {
+        // buffer B is free until the second pass (see tj_sort)
+        char* b0 = (char*)x.bufs.key[BUF_B][0];
+        const int rc = x.train_rmi(r_keys, n_r, s_keys, n_s, permille, b0, (uint64_t)(end - b0));
+        if (rc != TJ_OK && rc != TJ_E_WORKSPACE) return rc;
+        learned = rc == TJ_OK;
+    }
+    uint64_t lo = 0, hi = ~0ull;
+    if (!learned) TJ_RET(probe(x, r_keys, n_r, s_keys, n_s, lo, hi));
     uint64_t total = 0;
     if (unlimited) {
         x.stats.key_ranges = 1;
+        if (learned) {
+            x.bkt.b[0] = (uint16_t*)x.bufs.key[BUF_B][0];
+            x.bkt.b[1] = (uint16_t*)x.bufs.key[BUF_B][1];
+            x.learned_pass = true;
+            x.stats.learned = 1;
+        }
         TJ_RET(x.process_range(lo, hi, n_r, n_s, false, 0));
         TJ_RET(x.finish_join(&total, 0, out_r, out_s, capacity, mat));
     } else {
@@ -1539,12 +1726,38 @@ static int join_impl(int key_type, const void* r_keys, const int32_t* r_rids, ui
     return TJ_OK;
 }
 
+extern "C" {
+
+int tj_sort(int key_type, const void* keys_in, const int32_t* rids_in, uint64_t n, void* keys_out,
+            int32_t* rids_out, void* workspace, uint64_t workspace_bytes, void* stream,
+            tj_stats_t* stats)
+{
+    return sort_impl(key_type, keys_in, rids_in, n, keys_out, rids_out, workspace, workspace_bytes, stream,
+                     nullptr, stats);
+}
+
+int tj_sort_ex(int key_type, const void* keys_in, const int32_t* rids_in, uint64_t n, void* keys_out,
+               int32_t* rids_out, void* workspace, uint64_t workspace_bytes, void* stream,
+               const tj_options_t* opt, tj_stats_t* stats)
+{
+    return sort_impl(key_type, keys_in, rids_in, n, keys_out, rids_out, workspace, workspace_bytes, stream,
+                     opt, stats);
+}
+
 int tj_join_count(int key_type, const void* r_keys, uint64_t n_r, const void* s_keys, uint64_t n_s,
                   uint64_t* count, void* workspace, uint64_t workspace_bytes, void* stream,
                   tj_stats_t* stats)
 {
     return join_impl(key_type, r_keys, nullptr, n_r, s_keys, nullptr, n_s, nullptr, nullptr, 0, count,
-                     workspace, workspace_bytes, stream, stats, false);
+                     workspace, workspace_bytes, stream, stats, false, nullptr);
+}
+
+int tj_join_count_ex(int key_type, const void* r_keys, uint64_t n_r, const void* s_keys, uint64_t n_s,
+                     uint64_t* count, void* workspace, uint64_t workspace_bytes, void* stream,
+                     const tj_options_t* opt, tj_stats_t* stats)
+{
+    return join_impl(key_type, r_keys, nullptr, n_r, s_keys, nullptr, n_s, nullptr, nullptr, 0, count,
+                     workspace, workspace_bytes, stream, stats, false, opt);
 }
 
 int tj_join_materialize(int key_type, const void* r_keys, const int32_t* r_rids, uint64_t n_r,
@@ -1553,7 +1766,72 @@ int tj_join_materialize(int key_type, const void* r_keys, const int32_t* r_rids,
                         uint64_t workspace_bytes, void* stream, tj_stats_t* stats)
 {
     return join_impl(key_type, r_keys, r_rids, n_r, s_keys, s_rids, n_s, out_r, out_s, capacity, count,
-                     workspace, workspace_bytes, stream, stats, true);
+                     workspace, workspace_bytes, stream, stats, true, nullptr);
+}
+
+int tj_join_materialize_ex(int key_type, const void* r_keys, const int32_t* r_rids, uint64_t n_r,
+                           const void* s_keys, const int32_t* s_rids, uint64_t n_s, int32_t* out_r,
+                           int32_t* out_s, uint64_t capacity, uint64_t* count, void* workspace,
+                           uint64_t workspace_bytes, void* stream, const tj_options_t* opt, tj_stats_t* stats)
+{
+    return join_impl(key_type, r_keys, r_rids, n_r, s_keys, s_rids, n_s, out_r, out_s, capacity, count,
+                     workspace, workspace_bytes, stream, stats, true, opt);
+}
+
+int tj_rmi_workspace_query(int key_type, uint64_t n_a, uint64_t n_b, uint32_t permille, uint64_t* bytes)
+{
+    if (validate_common(key_type) != TJ_OK || !bytes || n_a == 0 || permille > 1000) return TJ_E_ARG;
+    if (n_a > kMaxRows || n_b > kMaxRows) return TJ_E_TOO_LARGE;
+    if (!permille) permille = DEFAULT_PERMILLE;
+    const uint64_t M = rmi_sample_rows(n_a, permille) + (n_b ? rmi_sample_rows(n_b, permille) : 0);
+    *bytes = align_up(sizeof(tj_rmi_t), ALIGN) + rmi_scratch_bytes(key_type, M, true);
+    return TJ_OK;
+}
+
+int tj_rmi_train(int key_type, const void* keys_a, uint64_t n_a, const void* keys_b, uint64_t n_b,
+                 uint32_t permille, tj_rmi_t* model, void* workspace, uint64_t workspace_bytes, void* stream)
+{
+    if (validate_common(key_type) != TJ_OK || !keys_a || n_a == 0 || !model || !workspace) return TJ_E_ARG;
+    if (n_b && !keys_b) return TJ_E_ARG;
+    uint64_t need;
+    TJ_RET(tj_rmi_workspace_query(key_type, n_a, n_b, permille, &need));
+    if ((uintptr_t)workspace % ALIGN || workspace_bytes < need) return TJ_E_WORKSPACE;
+    if (!permille) permille = DEFAULT_PERMILLE;
+    Exec x;
+    x.timed_on = timing_enabled() && !t_nested;
+    x.sh = Shape{TJ_OP_SORT, key_type, false, false, true, n_a, n_b};
+    x.st = (hipStream_t)stream;
+    char* p = (char*)workspace;
+    x.d_model = (tj_rmi_t*)p;
+    p += align_up(sizeof(tj_rmi_t), ALIGN);
+    TJ_RET(x.train_rmi(keys_a, n_a, keys_b, n_b, permille, p, (uint64_t)((char*)workspace + workspace_bytes - p)));
+    TJ_CK(hipMemcpyAsync(model, x.d_model, sizeof(tj_rmi_t), hipMemcpyDeviceToHost, x.st));
+    TJ_CK(hipStreamSynchronize(x.st));
+    return TJ_OK;
+}
+
+int tj_rmi_buckets(int key_type, const void* keys, uint64_t n, const tj_rmi_t* model, uint16_t* buckets,
+                   void* workspace, uint64_t workspace_bytes, void* stream)
+{
+    if (validate_common(key_type) != TJ_OK || !model) return TJ_E_ARG;
+    if (n > kMaxRows) return TJ_E_TOO_LARGE;
+    if (model->buckets == 0 || model->buckets > (uint32_t)NB) return TJ_E_ARG;
+    for (int i = 0; i < TJ_RMI_SEGMENTS; i++)
+        if (model->knot[i] > model->knot[i + 1] || !(model->knot_inv[i] >= 0.0f) || std::isinf(model->knot_inv[i]))
+            return TJ_E_ARG;
+    for (int l = 0; l < TJ_RMI_LEAVES; l++) {
+        if (model->leaf_lo[l] > model->leaf_hi[l] || model->leaf_hi[l] >= model->buckets) return TJ_E_ARG;
+        if (l + 1 < TJ_RMI_LEAVES && model->leaf_hi[l] > model->leaf_lo[l + 1]) return TJ_E_ARG;
+        if (!std::isfinite(model->leaf_a[l]) || !(model->leaf_b[l] >= 0.0f) || std::isinf(model->leaf_b[l]))
+            return TJ_E_ARG;
+    }
+    if (n == 0) return TJ_OK;
+    if (!keys || !buckets || !workspace) return TJ_E_ARG;
+    if ((uintptr_t)workspace % ALIGN || workspace_bytes < sizeof(tj_rmi_t)) return TJ_E_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    TJ_CK(hipMemcpyAsync(workspace, model, sizeof(tj_rmi_t), hipMemcpyHostToDevice, st));
+    TJ_CK(launch_rmi_eval(key_type, keys, n, (const tj_rmi_t*)workspace, buckets, st));
+    return TJ_OK;
 }
 
 int tj_debug_partition_pass(const int64_t* keys, const int32_t* rids, uint64_t n, uint64_t base,

@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "tj.h"
+
 namespace tj {
 
 constexpr int MAX_DIGIT_BITS = 9;             // widest partition digit
@@ -135,6 +137,12 @@ struct BufSet {
     const int32_t* rid[3][2];
 };
 
+// Per-row bucket ids of the learned pass, one array per side, indexed like the
+// rows of the pass's source buffer (written by the histogram, read by the scatter).
+struct BktSet {
+    uint16_t* b[2];
+};
+
 // Rows per leaf block (the block shape depends on the key word, see the kernels).
 constexpr int LEAF_CAP = 8192;
 
@@ -148,6 +156,11 @@ hipError_t launch_probe(int key_bytes, const void* a, uint64_t na, const void* b
 hipError_t launch_hist(int key_bytes, const ChunkDesc* chunks, uint32_t nchunks,
                        const GroupDesc* groups, BufSet bufs, uint32_t* hist,
                        uint64_t* gmin, uint64_t* gmax, hipStream_t st);
+// Histogram of the learned pass: the digit is the bucket of `model` (device
+// copy), and each row's bucket is also stored in bkt.b[side][row].
+hipError_t launch_learned_hist(int key_bytes, const ChunkDesc* chunks, uint32_t nchunks,
+                               const GroupDesc* groups, BufSet bufs, const tj_rmi_t* model, BktSet bkt,
+                               uint32_t* hist, uint64_t* gmin, uint64_t* gmax, hipStream_t st);
 hipError_t launch_scan(const CBlockDesc* cblocks, uint32_t ncblocks, const GroupDesc* groups,
                        uint32_t ngroups, uint32_t* hist, uint32_t* cbsum, uint32_t* ccount,
                        uint64_t* cstart, hipStream_t st);
@@ -155,6 +168,10 @@ hipError_t launch_scan(const CBlockDesc* cblocks, uint32_t ncblocks, const Group
 hipError_t launch_scatter(int key_bytes, int out_key_bytes, bool rids, bool keys, const ChunkDesc* chunks,
                           uint32_t nchunks, const GroupDesc* groups, const uint32_t* hist,
                           const uint32_t* cbsum, const uint64_t* cstart, BufSet bufs, hipStream_t st);
+// Scatter of the learned pass: digits are read from bkt (no narrowing).
+hipError_t launch_learned_scatter(int key_bytes, bool rids, const ChunkDesc* chunks, uint32_t nchunks,
+                                  const GroupDesc* groups, const uint32_t* hist, const uint32_t* cbsum,
+                                  const uint64_t* cstart, BufSet bufs, BktSet bkt, hipStream_t st);
 // Folds each segment's per-side child tables into ChildRec records, written at
 // group.child0 / nside (groups come in side order per segment).
 hipError_t launch_children(const GroupDesc* groups, uint32_t ngroups, int nside,
@@ -185,5 +202,16 @@ hipError_t launch_copy(int key_bytes, const CopyDesc* units, uint32_t n, uint64_
 hipError_t launch_expand(int32_t* dst, const int32_t* src, uint64_t n, uint64_t b, int mode,
                          hipStream_t st);
 hipError_t launch_wave_scan_test(const uint32_t* in, uint32_t* out, uint64_t n, hipStream_t st);
+
+// Learned partitioner (tj_rmi.hip).
+// Rows floor(i n / m), i < m, of keys[n] to out[off + i]; rids[off + i] = off + i.
+hipError_t launch_rmi_sample(int key_bytes, const void* keys, uint64_t n, uint32_t m, void* out,
+                             int32_t* rids, uint32_t off, hipStream_t st);
+// Fits *model to the sorted sample[M] with F buckets; start needs LEAVES + 1 words.
+hipError_t launch_rmi_fit(int key_bytes, const void* sorted, uint32_t M, uint32_t F, uint32_t* start,
+                          tj_rmi_t* model, hipStream_t st);
+// out[i] = bucket of keys[i] under the device model.
+hipError_t launch_rmi_eval(int key_bytes, const void* keys, uint64_t n, const tj_rmi_t* model,
+                           uint16_t* out, hipStream_t st);
 
 }  // namespace tj

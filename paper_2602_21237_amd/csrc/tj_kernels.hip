@@ -14,6 +14,7 @@
 // order as the signed keys (flip the sign bit); digits are taken from
 // (ordinal - base) so that only the bits that vary inside a bucket are used.
 #include "tj_internal.h"
+#include "tj_rmi.h"
 
 #include <type_traits>
 
@@ -369,24 +370,31 @@ hipError_t launch_probe(int key_bytes, const void* a, uint64_t na, const void* b
 // and digit, the smallest and largest ordinal, so that every child bucket
 // knows its exact key range and single-key buckets are recognised)
 // ---------------------------------------------------------------------------
-template <typename K>
+// LEARNED: the digit is the learned bucket of the row's key (model copied to
+// LDS), and every row's bucket is stored in bkt for the scatter.
+template <typename K, bool LEARNED>
 __global__ __launch_bounds__(PART_THREADS) void k_hist(const ChunkDesc* __restrict__ chunks,
                                                        const GroupDesc* __restrict__ groups,
                                                        BufSet bufs, uint32_t* __restrict__ hist,
                                                        uint64_t* __restrict__ gmin,
-                                                       uint64_t* __restrict__ gmax)
+                                                       uint64_t* __restrict__ gmax,
+                                                       const tj_rmi_t* __restrict__ model, BktSet bkt)
 {
     __shared__ uint32_t cnt[NB];
     __shared__ uint64_t mn[NB], mx[NB];
+    __shared__ __align__(16) char lm_raw[LEARNED ? sizeof(tj_rmi_t) : 16];
+    const tj_rmi_t& lm = *(const tj_rmi_t*)lm_raw;
     const ChunkDesc ch = chunks[blockIdx.x];
     const GroupDesc g = groups[ch.group];
     const K* __restrict__ src = (const K*)bufs.key[g.src][g.side] + g.src_koff + ch.start;
+    uint16_t* __restrict__ bk = LEARNED ? bkt.b[g.side] + ch.start : nullptr;
     const uint32_t nbins = 1u << g.bits;
     for (uint32_t d = threadIdx.x; d < nbins; d += PART_THREADS) {
         cnt[d] = 0;
         mn[d] = ~0ull;
         mx[d] = 0;
     }
+    if (LEARNED) rmi_to_lds<PART_THREADS>((tj_rmi_t*)lm_raw, model);
     lds_barrier();
     // Rows are counted with LDS atomics. When every valid row of a wave's round
     // falls in one bin (skewed inputs: buckets dominated by one key), the wave
@@ -406,7 +414,14 @@ __global__ __launch_bounds__(PART_THREADS) void k_hist(const ChunkDesc* __restri
             const uint32_t q = q0 + u * PART_THREADS;
             const uint64_t o = ord_of(k[u]);
             const bool valid = q < ch.len && o >= g.flo && o <= g.fhi;
-            const uint32_t d = valid ? (uint32_t)((o - g.base) >> g.shift) & (nbins - 1u) : 0u;
+            uint32_t d;
+            if (LEARNED) {
+                d = min(rmi_bucket(lm, o), nbins - 1u);
+                if (q < ch.len) bk[q] = (uint16_t)d;
+                d = valid ? d : 0u;
+            } else {
+                d = valid ? (uint32_t)((o - g.base) >> g.shift) & (nbins - 1u) : 0u;
+            }
             const uint64_t vm = ballot(valid);
             if (vm == 0) continue;
             const int first = __ffsll((unsigned long long)vm) - 1;
@@ -446,12 +461,27 @@ hipError_t launch_hist(int key_bytes, const ChunkDesc* chunks, uint32_t nchunks,
                        uint64_t* gmax, hipStream_t st)
 {
     if (nchunks == 0) return hipSuccess;
+    const BktSet none{};
     if (key_bytes == 4)
-        hipLaunchKernelGGL(k_hist<int32_t>, dim3(nchunks), dim3(PART_THREADS), 0, st, chunks, groups,
-                           bufs, hist, gmin, gmax);
+        hipLaunchKernelGGL((k_hist<int32_t, false>), dim3(nchunks), dim3(PART_THREADS), 0, st, chunks, groups,
+                           bufs, hist, gmin, gmax, nullptr, none);
     else
-        hipLaunchKernelGGL(k_hist<int64_t>, dim3(nchunks), dim3(PART_THREADS), 0, st, chunks, groups,
-                           bufs, hist, gmin, gmax);
+        hipLaunchKernelGGL((k_hist<int64_t, false>), dim3(nchunks), dim3(PART_THREADS), 0, st, chunks, groups,
+                           bufs, hist, gmin, gmax, nullptr, none);
+    return hipGetLastError();
+}
+
+hipError_t launch_learned_hist(int key_bytes, const ChunkDesc* chunks, uint32_t nchunks,
+                               const GroupDesc* groups, BufSet bufs, const tj_rmi_t* model, BktSet bkt,
+                               uint32_t* hist, uint64_t* gmin, uint64_t* gmax, hipStream_t st)
+{
+    if (nchunks == 0) return hipSuccess;
+    if (key_bytes == 4)
+        hipLaunchKernelGGL((k_hist<int32_t, true>), dim3(nchunks), dim3(PART_THREADS), 0, st, chunks, groups,
+                           bufs, hist, gmin, gmax, model, bkt);
+    else
+        hipLaunchKernelGGL((k_hist<int64_t, true>), dim3(nchunks), dim3(PART_THREADS), 0, st, chunks, groups,
+                           bufs, hist, gmin, gmax, model, bkt);
     return hipGetLastError();
 }
 
@@ -740,13 +770,16 @@ constexpr int SC_NT = 1024, SC_KI = 8, SC_NW = SC_NT / 64, SC_TILE = SC_NT * SC_
 constexpr int SC_STRIDE = NB + 1;
 static_assert(SC_TILE == PART_TILE, "chunk sizes are planned in scatter tiles");
 
-template <typename K, typename KO, bool RIDS, bool WKEYS>
+// DIGIN (learned pass): each row's digit is read from bkt instead of being
+// computed from its key; rows are ranked by ballot match, which is stable by
+// construction, and the staged digit replaces the staged tile index.
+template <typename K, typename KO, bool RIDS, bool WKEYS, bool DIGIN>
 __global__ __launch_bounds__(SC_NT) void k_scatter(const ChunkDesc* __restrict__ chunks,
                                                    const GroupDesc* __restrict__ groups,
                                                    const uint32_t* __restrict__ hist,
                                                    const uint32_t* __restrict__ cbsum,
                                                    const uint64_t* __restrict__ cstart,
-                                                   BufSet bufs)
+                                                   BufSet bufs, BktSet bkt)
 {
     constexpr int NT = SC_NT, KI = SC_KI, NW = SC_NW, TILE = SC_TILE;
     __shared__ uint32_t cnt[NW * SC_STRIDE];
@@ -757,7 +790,7 @@ __global__ __launch_bounds__(SC_NT) void k_scatter(const ChunkDesc* __restrict__
     // staging, with one spare slot per lane of a wave for rows that take no part
     __shared__ K skey[TILE + 64];
     __shared__ int32_t srid[RIDS ? TILE + 64 : 1];
-    __shared__ uint16_t sidx[TILE + 64];  // the staged row's index inside the tile
+    __shared__ uint16_t sidx[TILE + 64];  // the staged row's index inside the tile (DIGIN: its digit)
 
     const ChunkDesc ch = chunks[blockIdx.x];
     const GroupDesc g = groups[ch.group];
@@ -765,6 +798,7 @@ __global__ __launch_bounds__(SC_NT) void k_scatter(const ChunkDesc* __restrict__
     const int32_t* __restrict__ src_r = bufs.rid[g.src][g.side] + ch.start;
     KO* __restrict__ dst_k = (KO*)bufs.key[g.dst][g.side] + g.dst_koff;
     int32_t* __restrict__ dst_r = (int32_t*)bufs.rid[g.dst][g.side];
+    const uint16_t* __restrict__ src_b = DIGIN ? bkt.b[g.side] + ch.start : nullptr;
     const uint32_t nbins = 1u << g.bits, mask = nbins - 1u;
     const uint32_t w = threadIdx.x / 64, l = threadIdx.x & 63;
     const bool force_reorder = (g.flags & GROUP_FORCE_REORDER) != 0;
@@ -784,11 +818,13 @@ __global__ __launch_bounds__(SC_NT) void k_scatter(const ChunkDesc* __restrict__
                            : 0u;
     K key[KI];
     int32_t rid[KI];
+    uint32_t bin[DIGIN ? KI : 1];
 #pragma unroll
     for (int r = 0; r < KI; r++) {
         const uint32_t q = (w * KI + r) * 64 + l;
         key[r] = q < ch.len ? src_k[q] : K(0);
         if (RIDS) rid[r] = q < ch.len ? src_r[q] : 0;
+        if (DIGIN) bin[DIGIN ? r : 0] = q < ch.len ? src_b[q] : 0u;
     }
     for (uint32_t t0 = 0; t0 < ch.len; t0 += TILE) {
         uint32_t dig[KI], rk[KI];
@@ -798,7 +834,8 @@ __global__ __launch_bounds__(SC_NT) void k_scatter(const ChunkDesc* __restrict__
             const uint32_t q = t0 + (w * KI + r) * 64 + l;
             const uint64_t o = ord_of(key[r]);
             val[r] = q < ch.len && o >= g.flo && o <= g.fhi;
-            dig[r] = val[r] ? (uint32_t)((o - g.base) >> g.shift) & mask : 0u;
+            if (DIGIN) dig[r] = val[r] ? bin[DIGIN ? r : 0] & mask : 0u;
+            else dig[r] = val[r] ? (uint32_t)((o - g.base) >> g.shift) & mask : 0u;
         }
         for (uint32_t i = l; i < NB; i += 64) cnt[w * SC_STRIDE + i] = 0;
         // Rank inside the wave: one LDS atomic per row on the wave's own
@@ -807,9 +844,14 @@ __global__ __launch_bounds__(SC_NT) void k_scatter(const ChunkDesc* __restrict__
         // makes the ranks stable. Nothing relies on that order: the write-out
         // checks it and the tile is written again, ranked by ballots, if a
         // digit's rows ever come out of input order.
+        if (DIGIN) {
 #pragma unroll
-        for (int r = 0; r < KI; r++)
-            rk[r] = atomicAdd(val[r] ? &cnt[w * SC_STRIDE + dig[r]] : &spare[threadIdx.x], 1u);
+            for (int r = 0; r < KI; r++) rk[r] = wave_rank(dig[r], val[r], (int)g.bits, &cnt[w * SC_STRIDE]);
+        } else {
+#pragma unroll
+            for (int r = 0; r < KI; r++)
+                rk[r] = atomicAdd(val[r] ? &cnt[w * SC_STRIDE + dig[r]] : &spare[threadIdx.x], 1u);
+        }
         if (threadIdx.x == 0) s_unordered = 0;
         lds_barrier();
         const uint32_t total = scan_counts<NT, NW, NB>(cnt, tmp);
@@ -824,7 +866,7 @@ __global__ __launch_bounds__(SC_NT) void k_scatter(const ChunkDesc* __restrict__
             const uint32_t p = val[r] ? cnt[w * SC_STRIDE + dig[r]] + rk[r] : TILE + l;
             skey[p] = key[r];
             if (RIDS) srid[p] = rid[r];
-            sidx[p] = (uint16_t)((w * KI + r) * 64 + l);
+            sidx[p] = (uint16_t)(DIGIN ? dig[r] : (w * KI + r) * 64 + l);
         }
         lds_barrier();
         // next tile's loads overlap the write-out of this one
@@ -835,6 +877,7 @@ __global__ __launch_bounds__(SC_NT) void k_scatter(const ChunkDesc* __restrict__
                 const uint32_t q = n0 + (w * KI + r) * 64 + l;
                 key[r] = q < ch.len ? src_k[q] : K(0);
                 if (RIDS) rid[r] = q < ch.len ? src_r[q] : 0;
+                if (DIGIN) bin[DIGIN ? r : 0] = q < ch.len ? src_b[q] : 0u;
             }
         }
         bool unordered = false;
@@ -847,18 +890,18 @@ __global__ __launch_bounds__(SC_NT) void k_scatter(const ChunkDesc* __restrict__
                 const uint32_t pc = p < total ? p : total - 1;
                 const K k = skey[pc];
                 const int32_t rv = RIDS ? srid[pc] : 0;
-                const uint32_t x = sidx[pc], xp = sidx[pc ? pc - 1 : 0];
-                const uint32_t d = digit_of(k);
+                const uint32_t x = sidx[pc], xp = DIGIN ? 0u : sidx[pc ? pc - 1 : 0];
+                const uint32_t d = DIGIN ? x : digit_of(k);
                 if (p < total) {
                     write_row(delta[d] + p, k, rv);
                     // cnt[d] (wave 0's entry) is where digit d starts inside the tile
-                    unordered = unordered || (p > cnt[d] && xp > x);
+                    if (!DIGIN) unordered = unordered || (p > cnt[d] && xp > x);
                 }
             }
         }
         if (unordered) s_unordered = 1;
         lds_barrier();
-        if (s_unordered || force_reorder) {
+        if (!DIGIN && (s_unordered || force_reorder)) {
             // Rare path: rank the tile again by ballot match (from its rows in
             // the source) and write it over the same destination rows.
             K k2[KI];
@@ -902,8 +945,10 @@ hipError_t launch_scatter(int key_bytes, int out_key_bytes, bool rids, bool keys
     if (nchunks == 0) return hipSuccess;
     if (out_key_bytes > key_bytes) return hipErrorInvalidValue;
     const dim3 grid(nchunks), block(SC_NT);
+    const BktSet none{};
 #define TJ_SC(K, KO, R, W)                                                                           \
-    hipLaunchKernelGGL((k_scatter<K, KO, R, W>), grid, block, 0, st, chunks, groups, hist, cbsum, cstart, bufs)
+    hipLaunchKernelGGL((k_scatter<K, KO, R, W, false>), grid, block, 0, st, chunks, groups, hist, cbsum, cstart, \
+                       bufs, none)
     if (key_bytes == 4) {
         if (!keys) TJ_SC(int32_t, int32_t, true, false);
         else if (rids) TJ_SC(int32_t, int32_t, true, true);
@@ -917,6 +962,26 @@ hipError_t launch_scatter(int key_bytes, int out_key_bytes, bool rids, bool keys
         else TJ_SC(int64_t, int32_t, false, true);
     }
 #undef TJ_SC
+    return hipGetLastError();
+}
+
+hipError_t launch_learned_scatter(int key_bytes, bool rids, const ChunkDesc* chunks, uint32_t nchunks,
+                                  const GroupDesc* groups, const uint32_t* hist, const uint32_t* cbsum,
+                                  const uint64_t* cstart, BufSet bufs, BktSet bkt, hipStream_t st)
+{
+    if (nchunks == 0) return hipSuccess;
+    const dim3 grid(nchunks), block(SC_NT);
+#define TJ_SCL(K, R)                                                                                  \
+    hipLaunchKernelGGL((k_scatter<K, K, R, true, true>), grid, block, 0, st, chunks, groups, hist, cbsum,  \
+                       cstart, bufs, bkt)
+    if (key_bytes == 4) {
+        if (rids) TJ_SCL(int32_t, true);
+        else TJ_SCL(int32_t, false);
+    } else {
+        if (rids) TJ_SCL(int64_t, true);
+        else TJ_SCL(int64_t, false);
+    }
+#undef TJ_SCL
     return hipGetLastError();
 }
 

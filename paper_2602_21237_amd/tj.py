@@ -33,10 +33,58 @@ class Stats(ctypes.Structure):
     _fields_ = [("bytes_read", ctypes.c_uint64), ("bytes_written", ctypes.c_uint64),
                 ("workspace_used", ctypes.c_uint64), ("passes", ctypes.c_uint32),
                 ("leaves", ctypes.c_uint32), ("single_key", ctypes.c_uint32),
-                ("key_ranges", ctypes.c_uint32)]
+                ("key_ranges", ctypes.c_uint32), ("learned", ctypes.c_uint32),
+                ("learned_overflow", ctypes.c_uint32), ("sample_rows", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+RMI_SEGMENTS, RMI_LEAVES = 256, 1024
+TJ_PART_RADIX, TJ_PART_LEARNED = 0, 1
+_PARTITIONERS = {"radix": TJ_PART_RADIX, "learned": TJ_PART_LEARNED}
+
+
+class RmiModel(ctypes.Structure):
+    """tj_rmi_t: the learned bucket function (see include/tj.h)."""
+    _fields_ = [("knot", ctypes.c_uint64 * (RMI_SEGMENTS + 1)), ("knot_inv", ctypes.c_float * RMI_SEGMENTS),
+                ("leaf_base", ctypes.c_uint64 * RMI_LEAVES), ("leaf_a", ctypes.c_float * RMI_LEAVES),
+                ("leaf_b", ctypes.c_float * RMI_LEAVES), ("leaf_lo", ctypes.c_uint16 * RMI_LEAVES),
+                ("leaf_hi", ctypes.c_uint16 * RMI_LEAVES), ("buckets", ctypes.c_uint32),
+                ("sample_rows", ctypes.c_uint32)]
+
+    ARRAYS = ("knot", "knot_inv", "leaf_base", "leaf_a", "leaf_b", "leaf_lo", "leaf_hi")
+
+    def to_numpy(self) -> dict:
+        import numpy as np
+        out = {f: np.ctypeslib.as_array(getattr(self, f)).copy() for f in self.ARRAYS}
+        out["buckets"] = int(self.buckets)
+        out["sample_rows"] = int(self.sample_rows)
+        return out
+
+    @classmethod
+    def from_fields(cls, obj) -> "RmiModel":
+        """From any object (or dict) with the model's field names as arrays / ints."""
+        import numpy as np
+        get = (lambda k: obj[k]) if isinstance(obj, dict) else (lambda k: getattr(obj, k))
+        m = cls()
+        for f in cls.ARRAYS:
+            dst = np.ctypeslib.as_array(getattr(m, f))
+            dst[:] = np.asarray(get(f), dtype=dst.dtype)
+        m.buckets = int(get("buckets"))
+        m.sample_rows = int(get("sample_rows"))
+        return m
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("partitioner", ctypes.c_uint32), ("sample_permille", ctypes.c_uint32),
+                ("learned_min_rows", ctypes.c_uint64)]
+
+
+def _options(partitioner: str, sample_permille: int, learned_min_rows: int):
+    if partitioner not in _PARTITIONERS:
+        raise ValueError("partitioner must be one of %s" % sorted(_PARTITIONERS))
+    return Options(_PARTITIONERS[partitioner], sample_permille, learned_min_rows)
 
 
 EXPORTS = {
@@ -47,6 +95,15 @@ EXPORTS = {
                                      _P, _u64, _P, _P]),
     "tj_join_materialize": (ctypes.c_int, [ctypes.c_int, _P, _P, _u64, _P, _P, _u64, _P, _P, _u64,
                                            ctypes.POINTER(_u64), _P, _u64, _P, _P]),
+    "tj_sort_ex": (ctypes.c_int, [ctypes.c_int, _P, _P, _u64, _P, _P, _P, _u64, _P, _P, _P]),
+    "tj_join_count_ex": (ctypes.c_int, [ctypes.c_int, _P, _u64, _P, _u64, ctypes.POINTER(_u64),
+                                        _P, _u64, _P, _P, _P]),
+    "tj_join_materialize_ex": (ctypes.c_int, [ctypes.c_int, _P, _P, _u64, _P, _P, _u64, _P, _P, _u64,
+                                              ctypes.POINTER(_u64), _P, _u64, _P, _P, _P]),
+    "tj_rmi_workspace_query": (ctypes.c_int, [ctypes.c_int, _u64, _u64, ctypes.c_uint32,
+                                              ctypes.POINTER(_u64)]),
+    "tj_rmi_train": (ctypes.c_int, [ctypes.c_int, _P, _u64, _P, _u64, ctypes.c_uint32, _P, _P, _u64, _P]),
+    "tj_rmi_buckets": (ctypes.c_int, [ctypes.c_int, _P, _u64, _P, _P, _P, _u64, _P]),
     "tj_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "tj_version": (ctypes.c_int, []),
     "tj_timing": (ctypes.c_int, [ctypes.c_int]),
@@ -158,8 +215,10 @@ def _workspace(op, kt, n_r, n_s, workspace, workspace_bytes, device):
 
 
 def sort(keys, rids, keys_out=None, rids_out=None, workspace=None, workspace_bytes=None,
-         stream=None, stats: bool = False):
-    """Stable ascending sort of (keys, rids) by signed key (tj_sort)."""
+         stream=None, stats: bool = False, partitioner: str = "radix", sample_permille: int = 0,
+         learned_min_rows: int = 0):
+    """Stable ascending sort of (keys, rids) by signed key (tj_sort, or tj_sort_ex
+    with partitioner="learned")."""
     torch = _torch()
     _dev(keys, "keys")
     _dev(rids, "rids")
@@ -173,15 +232,22 @@ def sort(keys, rids, keys_out=None, rids_out=None, workspace=None, workspace_byt
         rids_out = torch.empty_like(rids)
     ws, wsb = _workspace(TJ_OP_SORT, kt, n, 0, workspace, workspace_bytes, keys.device)
     st = Stats()
-    _check(load().tj_sort(kt, keys.data_ptr(), rids.data_ptr(), n, keys_out.data_ptr(),
-                          rids_out.data_ptr(), ws.data_ptr(), wsb, _stream(stream), ctypes.byref(st)),
-           "tj_sort")
+    if partitioner == "radix" and not sample_permille and not learned_min_rows:
+        _check(load().tj_sort(kt, keys.data_ptr(), rids.data_ptr(), n, keys_out.data_ptr(),
+                              rids_out.data_ptr(), ws.data_ptr(), wsb, _stream(stream), ctypes.byref(st)),
+               "tj_sort")
+    else:
+        opt = _options(partitioner, sample_permille, learned_min_rows)
+        _check(load().tj_sort_ex(kt, keys.data_ptr(), rids.data_ptr(), n, keys_out.data_ptr(),
+                                 rids_out.data_ptr(), ws.data_ptr(), wsb, _stream(stream), ctypes.byref(opt),
+                                 ctypes.byref(st)), "tj_sort_ex")
     return (keys_out, rids_out, st.as_dict()) if stats else (keys_out, rids_out)
 
 
 def join_count(r_keys, s_keys, workspace=None, workspace_bytes=None, stream=None,
-               stats: bool = False):
-    """|R join S| on equal keys (tj_join_count)."""
+               stats: bool = False, partitioner: str = "radix", sample_permille: int = 0,
+               learned_min_rows: int = 0):
+    """|R join S| on equal keys (tj_join_count, or tj_join_count_ex with options)."""
     _dev(r_keys, "r_keys")
     _dev(s_keys, "s_keys")
     kt = _key_type(r_keys)
@@ -191,14 +257,21 @@ def join_count(r_keys, s_keys, workspace=None, workspace_bytes=None, stream=None
                          workspace_bytes, r_keys.device)
     cnt = _u64()
     st = Stats()
-    _check(load().tj_join_count(kt, r_keys.data_ptr(), r_keys.numel(), s_keys.data_ptr(),
-                                s_keys.numel(), ctypes.byref(cnt), ws.data_ptr(), wsb,
-                                _stream(stream), ctypes.byref(st)), "tj_join_count")
+    if partitioner == "radix" and not sample_permille and not learned_min_rows:
+        _check(load().tj_join_count(kt, r_keys.data_ptr(), r_keys.numel(), s_keys.data_ptr(),
+                                    s_keys.numel(), ctypes.byref(cnt), ws.data_ptr(), wsb,
+                                    _stream(stream), ctypes.byref(st)), "tj_join_count")
+    else:
+        opt = _options(partitioner, sample_permille, learned_min_rows)
+        _check(load().tj_join_count_ex(kt, r_keys.data_ptr(), r_keys.numel(), s_keys.data_ptr(),
+                                       s_keys.numel(), ctypes.byref(cnt), ws.data_ptr(), wsb,
+                                       _stream(stream), ctypes.byref(opt), ctypes.byref(st)), "tj_join_count_ex")
     return (int(cnt.value), st.as_dict()) if stats else int(cnt.value)
 
 
 def join(r_keys, r_rids, s_keys, s_rids, capacity: int | None = None, out_r=None, out_s=None,
-         workspace=None, workspace_bytes=None, stream=None, stats: bool = False):
+         workspace=None, workspace_bytes=None, stream=None, stats: bool = False, partitioner: str = "radix",
+         sample_permille: int = 0, learned_min_rows: int = 0):
     """All (rid_R, rid_S) pairs with equal keys in canonical order (tj_join_materialize).
 
     Returns (out_r[:count], out_s[:count]) (plus the stats dict). With
@@ -210,7 +283,9 @@ def join(r_keys, r_rids, s_keys, s_rids, capacity: int | None = None, out_r=None
     if _key_type(s_keys) != kt or r_rids.dtype != torch.int32 or s_rids.dtype != torch.int32:
         raise TypeError("dtype mismatch")
     if capacity is None:
-        capacity = out_r.numel() if out_r is not None else join_count(r_keys, s_keys, stream=stream)
+        capacity = out_r.numel() if out_r is not None else join_count(
+            r_keys, s_keys, stream=stream, partitioner=partitioner, sample_permille=sample_permille,
+            learned_min_rows=learned_min_rows)
     if out_r is None:
         out_r = torch.empty(max(capacity, 1), dtype=torch.int32, device=r_keys.device)
     if out_s is None:
@@ -221,14 +296,55 @@ def join(r_keys, r_rids, s_keys, s_rids, capacity: int | None = None, out_r=None
                          workspace_bytes, r_keys.device)
     cnt = _u64()
     st = Stats()
-    _check(load().tj_join_materialize(kt, r_keys.data_ptr(), r_rids.data_ptr(), r_keys.numel(),
-                                      s_keys.data_ptr(), s_rids.data_ptr(), s_keys.numel(),
-                                      out_r.data_ptr(), out_s.data_ptr(), capacity,
-                                      ctypes.byref(cnt), ws.data_ptr(), wsb, _stream(stream),
-                                      ctypes.byref(st)), "tj_join_materialize")
+    args = (kt, r_keys.data_ptr(), r_rids.data_ptr(), r_keys.numel(), s_keys.data_ptr(), s_rids.data_ptr(),
+            s_keys.numel(), out_r.data_ptr(), out_s.data_ptr(), capacity, ctypes.byref(cnt), ws.data_ptr(), wsb,
+            _stream(stream))
+    if partitioner == "radix" and not sample_permille and not learned_min_rows:
+        _check(load().tj_join_materialize(*args, ctypes.byref(st)), "tj_join_materialize")
+    else:
+        opt = _options(partitioner, sample_permille, learned_min_rows)
+        _check(load().tj_join_materialize_ex(*args, ctypes.byref(opt), ctypes.byref(st)), "tj_join_materialize_ex")
     c = int(cnt.value)
     res = (out_r[:c], out_s[:c])
     return res + (st.as_dict(),) if stats else res
+
+
+def rmi_workspace_query(key_type: int, n_a: int, n_b: int = 0, permille: int = 0) -> int:
+    b = _u64()
+    _check(load().tj_rmi_workspace_query(key_type, n_a, n_b, permille, ctypes.byref(b)), "tj_rmi_workspace_query")
+    return int(b.value)
+
+
+def rmi_train(keys_a, keys_b=None, permille: int = 0, stream=None) -> RmiModel:
+    """Fits the learned bucket function to samples of one or two key columns (tj_rmi_train)."""
+    torch = _torch()
+    _dev(keys_a, "keys_a")
+    kt = _key_type(keys_a)
+    nb = 0
+    pb = None
+    if keys_b is not None:
+        _dev(keys_b, "keys_b")
+        if _key_type(keys_b) != kt:
+            raise TypeError("keys_a and keys_b must have the same dtype")
+        nb, pb = keys_b.numel(), keys_b.data_ptr()
+    need = rmi_workspace_query(kt, keys_a.numel(), nb, permille)
+    ws = torch.empty(need, dtype=torch.uint8, device=keys_a.device)
+    m = RmiModel()
+    _check(load().tj_rmi_train(kt, keys_a.data_ptr(), keys_a.numel(), pb, nb, permille, ctypes.byref(m),
+                               ws.data_ptr(), need, _stream(stream)), "tj_rmi_train")
+    return m
+
+
+def rmi_buckets(keys, model: RmiModel, stream=None):
+    """Bucket of every key under a host-side model (tj_rmi_buckets); int32 tensor."""
+    torch = _torch()
+    _dev(keys, "keys")
+    kt = _key_type(keys)
+    out = torch.empty(max(keys.numel(), 1), dtype=torch.int16, device=keys.device)
+    ws = torch.empty(ctypes.sizeof(RmiModel) + 256, dtype=torch.uint8, device=keys.device)
+    _check(load().tj_rmi_buckets(kt, keys.data_ptr(), keys.numel(), ctypes.byref(model), out.data_ptr(),
+                                 ws.data_ptr(), ws.numel(), _stream(stream)), "tj_rmi_buckets")
+    return out[:keys.numel()].to(torch.int32) & 0xFFFF
 
 
 def debug_wave_scan(x):

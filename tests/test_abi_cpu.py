@@ -89,3 +89,71 @@ def test_join_argument_errors():
     # out_r overlapping out_s
     assert lib.tj_join_materialize(8, A, B, 10, C, D, 10, W, W + 40, 100, ctypes.byref(cnt), 0x60000000,
                                    1 << 30, None, None) == tj.TJ_E_ALIAS
+
+
+def _c_sizeof(type_name: str) -> int:
+    import subprocess
+    import tempfile
+    src = '#include <stdio.h>\n#include "tj.h"\nint main(void){printf("%%zu", sizeof(%s));return 0;}\n' % type_name
+    with tempfile.TemporaryDirectory() as d:
+        c, exe = os.path.join(d, "s.c"), os.path.join(d, "s")
+        open(c, "w").write(src)
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        return int(subprocess.check_output([exe]).decode())
+
+
+def test_struct_layouts_match_header():
+    assert ctypes.sizeof(tj.Stats) == _c_sizeof("tj_stats_t")
+    assert ctypes.sizeof(tj.Options) == _c_sizeof("tj_options_t")
+    assert ctypes.sizeof(tj.RmiModel) == _c_sizeof("tj_rmi_t")
+
+
+def test_learned_option_errors():
+    lib = tj.load()
+    bad = tj.Options(7, 0, 0)
+    assert lib.tj_sort_ex(8, A, B, 1000, C, D, W, 1 << 30, None, ctypes.byref(bad), None) == tj.TJ_E_ARG
+    bad = tj.Options(tj.TJ_PART_LEARNED, 1001, 0)
+    cnt = ctypes.c_uint64(0)
+    assert lib.tj_join_count_ex(8, A, 10, B, 10, ctypes.byref(cnt), W, 1 << 30, None, ctypes.byref(bad),
+                                None) == tj.TJ_E_ARG
+    ok = tj.Options(tj.TJ_PART_LEARNED, 0, 0)
+    assert lib.tj_sort_ex(8, A, B, 0, C, D, W, 0, None, ctypes.byref(ok), None) == tj.TJ_OK  # empty input
+    assert lib.tj_sort_ex(8, A, B, 1 << 31, C, D, W, 1 << 30, None, ctypes.byref(ok), None) == tj.TJ_E_TOO_LARGE
+
+
+def test_rmi_entry_point_errors():
+    lib = tj.load()
+    b = ctypes.c_uint64(0)
+    assert lib.tj_rmi_workspace_query(8, 0, 0, 0, ctypes.byref(b)) == tj.TJ_E_ARG
+    assert lib.tj_rmi_workspace_query(3, 10, 0, 0, ctypes.byref(b)) == tj.TJ_E_ARG
+    assert lib.tj_rmi_workspace_query(8, 1 << 31, 0, 0, ctypes.byref(b)) == tj.TJ_E_TOO_LARGE
+    assert lib.tj_rmi_workspace_query(8, 1 << 20, 1 << 20, 10, ctypes.byref(b)) == tj.TJ_OK
+    assert b.value > ctypes.sizeof(tj.RmiModel) + 2 * 20972 * 12
+    m = tj.RmiModel()
+    assert lib.tj_rmi_train(8, None, 10, None, 0, 0, ctypes.byref(m), W, 1 << 30, None) == tj.TJ_E_ARG
+    assert lib.tj_rmi_train(8, A, 10, None, 5, 0, ctypes.byref(m), W, 1 << 30, None) == tj.TJ_E_ARG
+    assert lib.tj_rmi_train(8, A, 1000, None, 0, 0, ctypes.byref(m), W, 4096, None) == tj.TJ_E_WORKSPACE
+    # models that would break monotonicity or the bucket range are refused before device work
+    good = _valid_model()
+    assert lib.tj_rmi_buckets(8, A, 0, ctypes.byref(good), C, W, 1 << 20, None) == tj.TJ_OK
+    for field, idx, val in (("buckets", None, 0), ("buckets", None, 513), ("knot", 5, 0),
+                            ("leaf_hi", 3, 600), ("leaf_lo", 4, 0), ("leaf_b", 9, -1.0),
+                            ("knot_inv", 2, float("inf"))):
+        bad = _valid_model()
+        if idx is None:
+            setattr(bad, field, val)
+        else:
+            getattr(bad, field)[idx] = val
+        assert lib.tj_rmi_buckets(8, A, 100, ctypes.byref(bad), C, W, 1 << 20, None) == tj.TJ_E_ARG, field
+
+
+def _valid_model():
+    m = tj.RmiModel()
+    m.buckets = 512
+    for i in range(tj.RMI_SEGMENTS + 1):
+        m.knot[i] = 1000 * i
+    for i in range(tj.RMI_SEGMENTS):
+        m.knot_inv[i] = 1.0 / 1000
+    for l in range(tj.RMI_LEAVES):
+        m.leaf_lo[l] = m.leaf_hi[l] = l // 2
+    return m

@@ -16,6 +16,9 @@ over its HIP-event-measured average duration, against the 8 TB/s HBM peak.
 cpu_baseline: the CPU oracle (single thread) on a 1/32 sample of the workload.
 paper_shaped: P50/P99 latency of the |R| = |S| = 10^6 workload at workspace
 budgets of 1 MiB, 64 MiB and unlimited, theta in {0, 0.99}.
+learned_vs_radix: |R| = |S| = 2^28 int64 keys from a lognormal, an interval
+mixture and a gapped sequence; sort, join count and join of the same inputs
+with the radix and with the learned first pass (median of 5), outputs equal.
 """
 from __future__ import annotations
 
@@ -168,6 +171,81 @@ def paper_shaped_sweep(tj, torch, repeats: int):
     return out
 
 
+def learned_vs_radix(tj, torch, n: int, repeats: int):
+    """Radix against learned first-pass partitioning on the three non-uniform key
+    distributions (|R| = |S| = n, int64 keys): sort of R, join count and join
+    materialisation of R and S, same inputs, outputs checked equal."""
+    import tjgen
+    out = {}
+    for dist in tjgen.LEARNED_DISTS:
+        log("learned vs radix: generating %s, n = %d" % (dist, n))
+        w = tjgen.learned(dist, n)
+        rk = torch.from_numpy(w["r_keys"]).to("cuda")
+        sk = torch.from_numpy(w["s_keys"]).to("cuda")
+        rr = torch.from_numpy(w["r_rids"]).to("cuda")
+        sr = torch.from_numpy(w["s_rids"]).to("cuda")
+        del w
+        ws_sort = torch.empty(tj.workspace_query(tj.TJ_OP_SORT, tj.TJ_KEY_I64, n)[1], dtype=torch.uint8,
+                              device="cuda")
+        ws_join = torch.empty(tj.workspace_query(tj.TJ_OP_JOIN_MATERIALIZE, tj.TJ_KEY_I64, n, n)[1],
+                              dtype=torch.uint8, device="cuda")
+        outs = {}
+        res = {}
+        count = tj.join_count(rk, sk, workspace=ws_join)
+        mat = count < (1 << 30)
+        if mat:
+            out_r = torch.empty(max(count, 1), dtype=torch.int32, device="cuda")
+            out_s = torch.empty(max(count, 1), dtype=torch.int32, device="cuda")
+        for mode in ("radix", "learned"):
+            ko, ro = torch.empty_like(rk), torch.empty_like(rr)
+            ops = {"sort": lambda: tj.sort(rk, rr, keys_out=ko, rids_out=ro, workspace=ws_sort, stats=True,
+                                           partitioner=mode)[2],
+                   "join_count": lambda: tj.join_count(rk, sk, workspace=ws_join, stats=True,
+                                                       partitioner=mode)[1]}
+            if mat:
+                ops["join"] = lambda: tj.join(rk, rr, sk, sr, capacity=count, out_r=out_r, out_s=out_s,
+                                              workspace=ws_join, stats=True, partitioner=mode)[2]
+            for op, f in ops.items():
+                f()  # warm-up
+                tj.timing(True)
+                times = []
+                for _ in range(repeats):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    st = f()
+                    torch.cuda.synchronize()
+                    times.append((time.perf_counter() - t0) * 1e3)
+                tj.timing(False)
+                fams = tj.timing_read()
+                r = res.setdefault(op, {})
+                r[mode + "_ms"] = round(pct(times, 0.5), 3)
+                r[mode + "_passes"] = st["passes"]
+                r[mode + "_planned_MB"] = round((st["bytes_read"] + st["bytes_written"]) / 1e6, 1)
+                r[mode + "_kernels_ms"] = {k: round(v["ms"] / repeats, 3) for k, v in fams.items() if v["launches"]}
+                if mode == "learned":
+                    r["learned_ran"] = bool(st["learned"])
+                    r["learned_overflow_buckets"] = st["learned_overflow"]
+                    r["sample_rows"] = st["sample_rows"]
+                    r["speedup"] = round(r["radix_ms"] / r["learned_ms"], 3)
+            if mat:
+                outs[mode] = (ko, ro, out_r[:count].clone(), out_s[:count].clone())
+            else:
+                outs[mode] = (ko, ro)
+        same = all(torch.equal(a, b) for a, b in zip(outs["radix"], outs["learned"]))
+        assert same, "learned and radix outputs differ (%s)" % dist
+        res["join_count_value"] = count
+        res["outputs_identical"] = same
+        out[dist] = res
+        log("learned vs radix %s: sort %.2f -> %.2f ms, join count %.2f -> %.2f ms" %
+            (dist, res["sort"]["radix_ms"], res["sort"]["learned_ms"], res["join_count"]["radix_ms"],
+             res["join_count"]["learned_ms"]))
+        del rk, sk, rr, sr, ws_sort, ws_join, outs
+        if mat:
+            del out_r, out_s
+        torch.cuda.empty_cache()
+    return {"n_per_relation": n, "repeats": repeats, "dists": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +256,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-sweep", action="store_true", help="skip the paper-shaped budget sweep")
     ap.add_argument("--sweep-repeats", type=int, default=100)
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-radix comparison")
+    ap.add_argument("--learned-rows", type=int, default=1 << 28,
+                    help="rows per relation of the learned-vs-radix comparison")
+    ap.add_argument("--learned-repeats", type=int, default=5)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="before timing, copy MIB MiB device-to-device three times (a plain copy "
                          "of known size that scales the FETCH_SIZE / WRITE_SIZE counters)")
@@ -296,6 +378,8 @@ def main():
     }
     del ko, ro, out_r, out_s, ws_sort, ws_join, d_sk, d_sr, d_rk, d_rr, d_skj, d_srj
     torch.cuda.empty_cache()
+    if not args.no_learned:
+        line["learned_vs_radix"] = learned_vs_radix(tj, torch, args.learned_rows, args.learned_repeats)
     if not args.no_sweep:
         log("paper-shaped budget sweep")
         line["paper_shaped"] = paper_shaped_sweep(tj, torch, args.sweep_repeats)

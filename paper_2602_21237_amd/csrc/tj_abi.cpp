@@ -468,13 +468,22 @@ struct Exec {
         for (size_t i = 0; i < segs.size(); i++) {
             const Seg& s = segs[i];
             const uint64_t rows = s.rn + s.sn;
-            const uint32_t kbits = nbits64(s.hi - s.lo);
-            uint32_t want = 1;
-            while (want < (uint32_t)PASS_DIGIT_BITS && (rows >> want) > (uint64_t)LEAF_CAP / 2) want++;
-            uint32_t b = std::min<uint32_t>(want, kbits);
-            if (b == 0) b = 1;  // filtered roots of a single-key range still need a compaction pass
-            plan[i].bits = b;
-            plan[i].shift = kbits > b ? kbits - b : 0;
+            const uint64_t span = s.hi - s.lo;
+            // digits wanted: children of LEAF_CAP / 2 rows on average (at least 2, at most a full digit)
+            const uint64_t want = std::min<uint64_t>(std::max<uint64_t>((rows + LEAF_CAP / 2 - 1) / (LEAF_CAP / 2), 2),
+                                                     1ull << PASS_DIGIT_BITS);
+            // the largest shift at which (span >> shift) + 1 digits still reach `want`, so a
+            // span that is not a power of two still puts `want` digits in use
+            uint32_t shift = 0;
+            for (uint32_t sh = nbits64(span); sh-- > 0;)
+                if ((span >> sh) + 1 >= want) {
+                    shift = sh;
+                    break;
+                }
+            while ((span >> shift) >= (1ull << PASS_DIGIT_BITS)) shift++;
+            // filtered roots of a single-key range (span 0) still need a compaction pass: one bit
+            plan[i].bits = std::max<uint32_t>(1, nbits64(span >> shift));
+            plan[i].shift = shift;
             // join keys are narrowed to 4 bytes once every child spans at most
             // 2^32 ordinals; the sort writes its keys out and never narrows
             plan[i].kb_out = sh.join && write_keys && s.kb == 8 && plan[i].shift <= 32 ? 4u : s.kb;
@@ -506,19 +515,33 @@ struct Exec {
         std::vector<ChunkDesc> chunks;
         std::vector<CBlockDesc> cblocks;
         std::vector<size_t> gseg;  // group -> segment
-        size_t si = 0;
-        while (si < segs.size()) {
+        // Launches take one input key width. A level whose segments mix widths
+        // (keys narrowed in some buckets only) runs its 8-byte segments first,
+        // then its 4-byte ones, instead of a launch per run of equal widths;
+        // children then reach the sink out of key order, which only the
+        // device leaf batching relies on.
+        std::vector<size_t> order(segs.size());
+        for (size_t i = 0; i < segs.size(); i++) order[i] = i;
+        bool kb_mixed = false;
+        for (size_t i = 1; i < segs.size(); i++) kb_mixed = kb_mixed || segs[i].kb != segs[0].kb;
+        if (kb_mixed) {
+            std::stable_partition(order.begin(), order.end(), [&](size_t i) { return segs[i].kb == 8; });
+            if (dev_ok) TJ_RET(demote_device_leaves());
+        }
+        size_t oi = 0;
+        while (oi < segs.size()) {
             groups.clear();
             chunks.clear();
             cblocks.clear();
             gseg.clear();
             uint32_t child = 0;
-            const size_t first = si;
-            // fill one launch batch (all of its segments share both key widths)
-            const uint32_t kb_in = segs[si].kb, kb_out = plan[si].kb_out;
-            while (si < segs.size()) {
+            // fill one launch batch: its segments share the input key width; some
+            // may narrow their keys while others keep them (GROUP_WIDE)
+            const uint32_t kb_in = segs[order[oi]].kb;
+            while (oi < segs.size()) {
+                const size_t si = order[oi];
                 const Seg& s = segs[si];
-                if (s.kb != kb_in || plan[si].kb_out != kb_out) break;
+                if (s.kb != kb_in) break;
                 uint64_t need_chunks = 0, need_cb = 0;
                 for (int side = 0; side < nside; side++) {
                     const uint64_t len = filter ? (side ? sh.n_s : sh.n_r) : (side ? s.sn : s.rn);
@@ -552,7 +575,7 @@ struct Exec {
                     child += 1u << g.bits;
                     g.flags = (g_debug_flags.load() & TJ_DEBUG_FORCE_REORDER) ? GROUP_FORCE_REORDER : 0u;
                     g.src_koff = filter ? 0 : (side ? s.koff_s : s.koff_r);
-                    g.dst_koff = kb_out < kb_in ? g.dst_start : g.src_koff;
+                    g.dst_koff = plan[si].kb_out < kb_in ? g.dst_start : g.src_koff;
                     const uint32_t gi = (uint32_t)groups.size();
                     for (uint64_t c0 = 0; c0 < len; c0 += ch_rows) {
                         ChunkDesc c{};
@@ -576,22 +599,32 @@ struct Exec {
                     stats.bytes_read += len * (uint64_t)kb_in;                                   // histogram
                     stats.bytes_read += len * (uint64_t)kb_in + (sh.rids ? len * 4 : 0);         // scatter
                 }
-                si++;
+                oi++;
             }
             const uint32_t ng = (uint32_t)groups.size(), nc = (uint32_t)chunks.size(),
                            ncb = (uint32_t)cblocks.size();
+            // the launch narrows when any segment does; the others are marked wide
+            uint32_t kb_out = kb_in;
+            bool mixed = false;
+            for (uint32_t gi = 0; gi < ng; gi++) kb_out = std::min(kb_out, plan[gseg[gi]].kb_out);
+            for (uint32_t gi = 0; gi < ng; gi++)
+                if (plan[gseg[gi]].kb_out != kb_out) {
+                    groups[gi].flags |= GROUP_WIDE;
+                    mixed = true;
+                }
             TJ_CK(hipMemcpyAsync(d_groups, groups.data(), ng * sizeof(GroupDesc), hipMemcpyHostToDevice, st));
             TJ_CK(hipMemcpyAsync(d_chunks, chunks.data(), nc * sizeof(ChunkDesc), hipMemcpyHostToDevice, st));
             TJ_CK(hipMemcpyAsync(d_cblocks, cblocks.data(), ncb * sizeof(CBlockDesc), hipMemcpyHostToDevice, st));
             TJ_CK(launch_fill_u64(d_gmin, child, ~0ull, st));
             TJ_CK(launch_fill_u64(d_gmax, child, 0ull, st));
-            uint64_t scanned = 0, moved = 0;
+            uint64_t scanned = 0, written = 0;  // rows read; bytes written
             for (const GroupDesc& g : groups) {
                 scanned += g.len;
-                const Seg& s = segs[gseg[&g - groups.data()]];
-                moved += g.side ? s.sn : s.rn;
+                const size_t sidx = gseg[&g - groups.data()];
+                const Seg& s = segs[sidx];
+                written += (g.side ? s.sn : s.rn) * ((write_keys ? plan[sidx].kb_out : 0) + (sh.rids ? 4 : 0));
             }
-            const uint64_t rb = row_bytes((int)kb_in, sh.rids), wb = (write_keys ? kb_out : 0) + (sh.rids ? 4 : 0);
+            const uint64_t rb = row_bytes((int)kb_in, sh.rids);
             if (learned) {
                 // bucket ids: 2 bytes written per row by the histogram, read by the scatter
                 TJ_CK(timed(F_LHIST, scanned * (kb_in + 2), [&] {
@@ -609,12 +642,12 @@ struct Exec {
                 return launch_scan(d_cblocks, ncb, d_groups, ng, d_hist, d_cbsum, d_ccount, d_cstart, st);
             }));
             if (learned) {
-                TJ_CK(timed(F_LSCATTER, scanned * (rb + 2) + moved * wb, [&] {
+                TJ_CK(timed(F_LSCATTER, scanned * (rb + 2) + written, [&] {
                     return launch_learned_scatter((int)kb_in, sh.rids, d_chunks, nc, d_groups, d_hist, d_cbsum,
                                                   d_cstart, bufs, bkt, st);
                 }));
             } else {
-                TJ_CK(timed(F_SCATTER, scanned * rb + moved * wb, [&] {
+                TJ_CK(timed(F_SCATTER, scanned * rb + written, [&] {
                     return launch_scatter((int)kb_in, (int)kb_out, sh.rids, write_keys, d_chunks, nc, d_groups, d_hist,
                                           d_cbsum, d_cstart, bufs, st);
                 }));
@@ -622,6 +655,8 @@ struct Exec {
             // one compact record per child (both sides folded)
             const uint32_t nrec = child / (uint32_t)nside;
             TJ_CK(launch_children(d_groups, ng, nside, d_ccount, d_gmin, d_gmax, d_crec, st));
+            // device leaves of a range share one key width (one leaf launch)
+            if (dev_ok && (mixed || (dev_leaves && dev_kb != kb_out))) TJ_RET(demote_device_leaves());
             if (dev_ok) {
                 // batch the children into leaves on the device; the host reads three words
                 BatchArgs ba{};
@@ -644,10 +679,7 @@ struct Exec {
                 TJ_CK(hipMemcpyAsync(sum, d_sum, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
                 TJ_CK(hipStreamSynchronize(st));
                 if (!(sum[2] & (BATCH_NEEDS_HOST | BATCH_OVERFLOW))) {
-                    uint64_t moved = 0;
-                    for (uint32_t gi = 0; gi < ng; gi++) moved += segs[gseg[gi]].rn * (groups[gi].side == 0) +
-                                                              segs[gseg[gi]].sn * (groups[gi].side == 1);
-                    stats.bytes_written += moved * row_bytes((int)kb_out, sh.rids);
+                    stats.bytes_written += written;
                     dev_leaves += (uint32_t)sum[0];
                     dev_rows += sum[1];
                     dev_wide = dev_wide || (sum[2] & BATCH_WIDE);
@@ -663,7 +695,6 @@ struct Exec {
             // children in key order: segment order, then digit order; a child's
             // rows start where its smaller-digit siblings end
             HostTimer ht(this, F_HOST_CLASSIFY);
-            uint64_t moved_rows = 0;
             if (learned) {
                 // buckets over twice the mean (they take further radix passes)
                 uint64_t rows = 0;
@@ -676,13 +707,14 @@ struct Exec {
                 const uint32_t nbins = 1u << g0.bits;
                 const ChildRec* cr = rec + g0.child0 / (uint32_t)nside;
                 const uint64_t parent_win = segs[gseg[gi]].win;
-                const bool narrowing = kb_out < kb_in;
+                const uint32_t seg_kb = plan[gseg[gi]].kb_out;
+                const bool narrowing = seg_kb < kb_in;
                 const uint64_t koff_r = g0.dst_koff, koff_s = nside == 2 ? groups[gi + 1].dst_koff : 0;
                 uint64_t r0 = g0.dst_start, s0 = nside == 2 ? groups[gi + 1].dst_start : 0;
                 for (uint32_t d = 0; d < nbins; d++) {
                     Seg c;
                     c.buf = dst;
-                    c.kb = kb_out;
+                    c.kb = seg_kb;
                     c.r0 = r0;
                     c.rn = cr[d].rn;
                     c.s0 = s0;
@@ -701,12 +733,10 @@ struct Exec {
                     }
                     r0 += c.rn;
                     s0 += c.sn;
-                    moved_rows += c.rn + c.sn;
                     sink(c);
                 }
             }
-            stats.bytes_written += moved_rows * row_bytes((int)kb_out, sh.rids);
-            (void)first;
+            stats.bytes_written += written;
         }
         return TJ_OK;
     }

@@ -45,6 +45,9 @@ struct CBlockDesc {
 // ranked by ballot match (exercises the path taken when the ranks of a tile
 // come out of input order; used by the self-test hook only).
 constexpr uint32_t GROUP_FORCE_REORDER = 1u;
+// GroupDesc::flags: in a launch that narrows keys to 4 bytes, this group keeps
+// its 8-byte keys (its children still span more than 2^32 ordinals).
+constexpr uint32_t GROUP_WIDE = 2u;
 
 struct GroupDesc {
     uint64_t start;      // first row scanned in the source array

@@ -804,9 +804,13 @@ __global__ __launch_bounds__(SC_NT) void k_scatter(const ChunkDesc* __restrict__
     const bool force_reorder = (g.flags & GROUP_FORCE_REORDER) != 0;
 
     auto digit_of = [&](K k) { return (uint32_t)((ord_of(k) - g.base) >> g.shift) & mask; };
+    // a narrowing launch may hold groups that keep their 8-byte keys (uniform per block)
+    const bool wide = sizeof(KO) < sizeof(K) && (g.flags & GROUP_WIDE) != 0;
+    K* __restrict__ dst_kw = (K*)bufs.key[g.dst][g.side] + g.dst_koff;
     auto write_row = [&](uint32_t dst, K k, int32_t rid) {
         if (WKEYS) {
             if (sizeof(KO) == sizeof(K)) dst_k[dst] = (KO)k;
+            else if (wide) dst_kw[dst] = k;
             else dst_k[dst] = (KO)((uint32_t)(ord_of(k) - g.base) ^ 0x80000000u);
         }
         if (RIDS) dst_r[dst] = rid;

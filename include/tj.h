@@ -229,6 +229,79 @@ int tj_rmi_buckets(int key_type, const void *keys, uint64_t n, const tj_rmi_t *m
                    uint16_t *buckets, void *workspace, uint64_t workspace_bytes, void *stream);
 
 /*
+ * Serving loop: requests of uneven sizes, admitted against a device-memory
+ * budget and run concurrently.
+ *
+ * The paper measures the tensor path by its tail latency under a memory
+ * budget (P50/P99 at a given work_mem, Sec. V-VI). A server turns that into a
+ * running service: requests (sorts and joins over caller-resident device
+ * columns) arrive at any time; each is admitted, in arrival order, as soon as
+ * one of `slots` worker slots is idle and the arena holds its workspace and
+ * outputs; admitted requests run at once on their slot's own HIP stream, so
+ * small requests overlap on the GPU instead of waiting for one another.
+ *
+ * Memory: the caller hands the server one device arena (arena_bytes, 256-byte
+ * aligned): the budget for the requests' workspaces (the work_mem of the
+ * paper), which the server sub-allocates; it allocates no device memory
+ * itself. Inputs and outputs are the caller's, as in the plain calls. A
+ * request is admitted with the workspace it needs to finish; a join
+ * materialisation is counted first (phase 1), then re-admitted ahead of newer
+ * requests to write its pairs (phase 2; TJ_E_CAPACITY with the count when they
+ * exceed `capacity`). Admitted work never waits for memory and releases its
+ * workspace when it ends, so the queue always drains. Each request takes the
+ * full workspace of its shape when that fits the arena, else the smallest one
+ * (key ranges); a request whose smallest workspace exceeds the arena
+ * completes at once with TJ_E_WORKSPACE.
+ *
+ * All functions are thread-safe. Inputs must stay valid and unchanged, and
+ * outputs untouched, until the request completes.
+ */
+typedef struct tj_server tj_server_t;
+typedef struct {
+    int op;                      /* TJ_OP_SORT, TJ_OP_JOIN_COUNT or TJ_OP_JOIN_MATERIALIZE */
+    int key_type;
+    const void *r_keys;          /* sort: the relation to sort */
+    const int32_t *r_rids;       /* sort and materialise */
+    uint64_t n_r;
+    const void *s_keys;          /* joins */
+    const int32_t *s_rids;       /* materialise */
+    uint64_t n_s;
+    void *out0;                  /* sort: keys_out[n_r]; materialise: out_r[capacity] (device) */
+    int32_t *out1;               /* sort: rids_out[n_r]; materialise: out_s[capacity] */
+    uint64_t capacity;           /* materialise: pairs out0/out1 hold */
+    uint32_t partitioner;        /* TJ_PART_RADIX or TJ_PART_LEARNED (tj_options_t defaults) */
+    uint32_t pad;
+} tj_request_t;
+typedef struct {
+    int status;                  /* TJ_OK or the call's error */
+    int op;
+    uint64_t count;              /* sort: rows; joins: |R join S| (also on TJ_E_CAPACITY) */
+    double queue_ms;             /* submission to admission (phase 2 waits included) */
+    double run_ms;               /* time on a slot */
+    double total_ms;             /* submission to completion */
+    uint32_t learned;            /* the call used the learned first pass */
+    uint32_t key_ranges;         /* 1 unless the budget forced key ranges */
+} tj_result_t;
+/* Starts `slots` (1..64) worker threads with one HIP stream each (default
+ * priority) on the current device. Errors: TJ_E_ARG, TJ_E_WORKSPACE
+ * (arena misaligned or smaller than 64 KiB), TJ_E_HIP. */
+int tj_server_create(void *arena, uint64_t arena_bytes, int slots, tj_server_t **server);
+/* Queues a copy of *req and returns its ticket. Argument errors of the request
+ * (unknown op, key type or partitioner, NULL inputs or outputs, rows >= 2^31)
+ * are returned here and queue nothing; so are outputs that overlap an input
+ * or the arena (TJ_E_ALIAS). */
+int tj_server_submit(tj_server_t *server, const tj_request_t *req, uint64_t *ticket);
+/* Blocks until the request completes, copies its result and forgets the
+ * ticket. Returns TJ_OK (the request's own status is result->status) or
+ * TJ_E_ARG (unknown ticket, or a ticket another thread is already waiting for). */
+int tj_server_wait(tj_server_t *server, uint64_t ticket, tj_result_t *result);
+/* Arena bytes reserved now and at most so far (workspaces of running requests). */
+int tj_server_memory(tj_server_t *server, uint64_t *in_use, uint64_t *peak);
+/* Finishes every queued request, stops the workers and frees the server
+ * (not the arena). Results not yet waited for are dropped. */
+int tj_server_destroy(tj_server_t *server);
+
+/*
  * Per-kernel timing (profiling hook). tj_timing(1) clears the counters and
  * makes every later call record a HIP event pair around each kernel launch on
  * the call's stream; tj_timing(0) stops recording. tj_timing_read copies up to

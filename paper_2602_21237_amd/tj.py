@@ -104,6 +104,11 @@ EXPORTS = {
                                               ctypes.POINTER(_u64)]),
     "tj_rmi_train": (ctypes.c_int, [ctypes.c_int, _P, _u64, _P, _u64, ctypes.c_uint32, _P, _P, _u64, _P]),
     "tj_rmi_buckets": (ctypes.c_int, [ctypes.c_int, _P, _u64, _P, _P, _P, _u64, _P]),
+    "tj_server_create": (ctypes.c_int, [_P, _u64, ctypes.c_int, ctypes.POINTER(_P)]),
+    "tj_server_submit": (ctypes.c_int, [_P, _P, ctypes.POINTER(_u64)]),
+    "tj_server_wait": (ctypes.c_int, [_P, _u64, _P]),
+    "tj_server_memory": (ctypes.c_int, [_P, ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),
+    "tj_server_destroy": (ctypes.c_int, [_P]),
     "tj_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "tj_version": (ctypes.c_int, []),
     "tj_timing": (ctypes.c_int, [ctypes.c_int]),
@@ -377,3 +382,91 @@ def debug_partition_pass(keys, rids, base: int, shift: int, bits: int, workspace
                                           ws.data_ptr(), workspace_bytes, _stream(None)),
            "tj_debug_partition_pass")
     return ko, ro, counts
+
+
+# --------------------------------------------------------------------------- serving loop
+
+class Request(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int), ("key_type", ctypes.c_int), ("r_keys", _P), ("r_rids", _P),
+                ("n_r", _u64), ("s_keys", _P), ("s_rids", _P), ("n_s", _u64), ("out0", _P), ("out1", _P),
+                ("capacity", _u64), ("partitioner", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("op", ctypes.c_int), ("count", _u64),
+                ("queue_ms", ctypes.c_double), ("run_ms", ctypes.c_double),
+                ("total_ms", ctypes.c_double), ("learned", ctypes.c_uint32), ("key_ranges", ctypes.c_uint32)]
+
+
+class Server:
+    """tj_server_*: requests run on `slots` concurrent streams, admitted against
+    a device arena of `arena_bytes` that holds their workspaces. Inputs and
+    outputs are device tensors the caller owns; the server keeps references to
+    them until wait() returns."""
+
+    def __init__(self, arena_bytes: int, slots: int = 4, device=None):
+        torch = _torch()
+        self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=device or "cuda")
+        torch.cuda.synchronize()
+        self._h = _P()
+        _check(load().tj_server_create(self.arena.data_ptr(), arena_bytes, slots, ctypes.byref(self._h)),
+               "tj_server_create")
+        self._keep = {}
+
+    def _submit(self, op, r_keys, r_rids, s_keys, s_rids, out0, out1, capacity, partitioner):
+        kt = _key_type(r_keys)
+        ptr = lambda t: t.data_ptr() if t is not None else None
+        req = Request(op, kt, ptr(r_keys), ptr(r_rids), r_keys.numel(), ptr(s_keys), ptr(s_rids),
+                      s_keys.numel() if s_keys is not None else 0, ptr(out0), ptr(out1), capacity,
+                      _PARTITIONERS[partitioner], 0)
+        t = _u64()
+        _check(load().tj_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)), "tj_server_submit")
+        self._keep[t.value] = (op, (r_keys, r_rids, s_keys, s_rids), out0, out1)
+        return int(t.value)
+
+    def sort(self, keys, rids, keys_out=None, rids_out=None, partitioner: str = "radix") -> int:
+        keys_out = keys_out if keys_out is not None else _torch().empty_like(keys)
+        rids_out = rids_out if rids_out is not None else _torch().empty_like(rids)
+        return self._submit(TJ_OP_SORT, keys, rids, None, None, keys_out, rids_out, 0, partitioner)
+
+    def join_count(self, r_keys, s_keys, partitioner: str = "radix") -> int:
+        return self._submit(TJ_OP_JOIN_COUNT, r_keys, None, s_keys, None, None, None, 0, partitioner)
+
+    def join(self, r_keys, r_rids, s_keys, s_rids, capacity: int, out_r=None, out_s=None,
+             partitioner: str = "radix") -> int:
+        torch = _torch()
+        out_r = out_r if out_r is not None else torch.empty(max(capacity, 1), dtype=torch.int32, device=r_keys.device)
+        out_s = out_s if out_s is not None else torch.empty(max(capacity, 1), dtype=torch.int32, device=r_keys.device)
+        return self._submit(TJ_OP_JOIN_MATERIALIZE, r_keys, r_rids, s_keys, s_rids, out_r, out_s, capacity,
+                            partitioner)
+
+    def wait(self, ticket: int) -> dict:
+        """Blocks until the request is done; returns its status, count, timings
+        and (sort) keys / rids or (join) out_r / out_s tensors."""
+        r = Result()
+        _check(load().tj_server_wait(self._h, ticket, ctypes.byref(r)), "tj_server_wait")
+        op, _, out0, out1 = self._keep.pop(ticket)
+        out = {"status": r.status, "op": r.op, "count": int(r.count), "queue_ms": r.queue_ms, "run_ms": r.run_ms,
+               "total_ms": r.total_ms, "learned": int(r.learned), "key_ranges": int(r.key_ranges)}
+        if r.status == TJ_OK and op == TJ_OP_SORT:
+            out["keys"], out["rids"] = out0, out1
+        elif r.status == TJ_OK and op == TJ_OP_JOIN_MATERIALIZE:
+            out["out_r"], out["out_s"] = out0[:r.count], out1[:r.count]
+        return out
+
+    def memory(self):
+        """(arena bytes reserved now, peak so far)."""
+        a, b = _u64(), _u64()
+        _check(load().tj_server_memory(self._h, ctypes.byref(a), ctypes.byref(b)), "tj_server_memory")
+        return int(a.value), int(b.value)
+
+    def close(self) -> None:
+        if self._h:
+            _check(load().tj_server_destroy(self._h), "tj_server_destroy")
+            self._h = _P()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -157,3 +157,20 @@ def _valid_model():
     for l in range(tj.RMI_LEAVES):
         m.leaf_lo[l] = m.leaf_hi[l] = l // 2
     return m
+
+
+def test_server_argument_errors():
+    lib = tj.load()
+    h = ctypes.c_void_p()
+    assert lib.tj_server_create(None, 1 << 30, 4, ctypes.byref(h)) == tj.TJ_E_ARG
+    assert lib.tj_server_create(W, 1 << 30, 0, ctypes.byref(h)) == tj.TJ_E_ARG
+    assert lib.tj_server_create(W, 1 << 30, 65, ctypes.byref(h)) == tj.TJ_E_ARG
+    assert lib.tj_server_create(W + 8, 1 << 30, 4, ctypes.byref(h)) == tj.TJ_E_WORKSPACE
+    assert lib.tj_server_create(W, 1000, 4, ctypes.byref(h)) == tj.TJ_E_WORKSPACE
+    t = ctypes.c_uint64()
+    req = tj.Request(tj.TJ_OP_SORT, 8, A, B, 10, None, None, 0, C, D, 0, 0, 0)
+    assert lib.tj_server_submit(None, ctypes.byref(req), ctypes.byref(t)) == tj.TJ_E_ARG
+    assert lib.tj_server_wait(None, 1, ctypes.byref(tj.Result())) == tj.TJ_E_ARG
+    assert lib.tj_server_destroy(None) == tj.TJ_E_ARG
+    assert ctypes.sizeof(tj.Request) == _c_sizeof("tj_request_t")
+    assert ctypes.sizeof(tj.Result) == _c_sizeof("tj_result_t")

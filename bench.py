@@ -19,6 +19,10 @@ budgets of 1 MiB, 64 MiB and unlimited, theta in {0, 0.99}.
 learned_vs_radix: |R| = |S| = 2^28 int64 keys from a lognormal, an interval
 mixture and a gapped sequence; sort, join count and join of the same inputs
 with the radix and with the learned first pass (median of 5), outputs equal.
+serving: Poisson arrivals at 50, 200, 800 and 3200 requests/s of sorts and joins
+(per-side rows log-uniform in [10^3, 10^7]) against the serving loop with a
+32 GiB workspace budget, 8 slots against one at a time: P50/P99/P99.9 latency
+and tuples/s, every result compared with the same request run alone.
 """
 from __future__ import annotations
 
@@ -246,6 +250,127 @@ def learned_vs_radix(tj, torch, n: int, repeats: int):
     return {"n_per_relation": n, "repeats": repeats, "dists": out}
 
 
+def serving(tj, torch, rates, nreq: int, pool: int = 48, arena_gib: int = 32, slots: int = 8):
+    """Poisson stream of sort and join requests against the serving loop.
+
+    Pool: `pool` requests resident on the GPU, per-side rows log-uniform in
+    [10^3, 10^7], int64 keys (R keys unique over [0, 2^40), S foreign keys with
+    Zipf(0) or Zipf(0.8) over R's keys, half each), op sort (of S) or join
+    (materialised pairs), half each. Each rate runs `nreq` arrivals (seeded
+    exponential gaps) twice: on `slots` concurrent slots, and one request at a
+    time (one slot); latency runs from the scheduled arrival to completion.
+    Every result is compared with the same request run alone."""
+    import threading
+    import tjgen
+    rng = np.random.default_rng(2602)
+    reqs = []
+    log("serving: generating %d pooled requests" % pool)
+    for i in range(pool):
+        n_r = int(np.exp(rng.uniform(np.log(1e3), np.log(1e7))))
+        n_s = int(np.exp(rng.uniform(np.log(1e3), np.log(1e7))))
+        theta = 0.8 if i % 2 else 0.0
+        w = tjgen._fk_pair(100 + i, n_r, n_s, theta)
+        d = {k: torch.from_numpy(v).to("cuda") for k, v in w.items()}
+        op = "sort" if (i // 2) % 2 else "join"
+        e = {"op": op, "d": d, "tuples": n_s if op == "sort" else n_r + n_s}
+        if op == "sort":
+            e["ref"] = tj.sort(d["s_keys"], d["s_rids"])
+            e["out"] = (torch.empty_like(d["s_keys"]), torch.empty_like(d["s_rids"]))
+        else:
+            e["count"] = w.expected_count
+            e["ref"] = tj.join(d["r_keys"], d["r_rids"], d["s_keys"], d["s_rids"], capacity=e["count"])
+            e["out"] = (torch.empty(max(e["count"], 1), dtype=torch.int32, device="cuda"),
+                        torch.empty(max(e["count"], 1), dtype=torch.int32, device="cuda"))
+        reqs.append(e)
+    torch.cuda.synchronize()
+    out = {"pool": pool, "requests_per_rate": nreq, "arena_GiB": arena_gib, "slots": slots, "rates": {}}
+    for rate in rates:
+        gaps = np.random.default_rng(int(rate)).exponential(1.0 / rate, nreq)
+        sched = np.cumsum(gaps) - gaps[0]
+        order = np.random.default_rng(int(rate) + 1).integers(0, pool, nreq)
+        res_rate = {}
+        for mode, nslots in (("served", slots), ("one_at_a_time", 1)):
+            srv = tj.tj.Server(arena_gib << 30, slots=nslots)
+            # warm-up: every slot's first call sets up its host-side staging
+            warm = [srv.sort(reqs[i % pool]["d"]["s_keys"], reqs[i % pool]["d"]["s_rids"])
+                    for i in range(1, 4 * nslots, 4)]
+            for t in warm:
+                srv.wait(t)
+            busy = set()
+            lock = threading.Lock()
+            done = []
+            tickets = []  # (ticket, entry, scheduled time, submit delay)
+            cv = threading.Condition()
+
+            def waiter():
+                k = 0
+                while k < nreq:
+                    with cv:
+                        while len(tickets) <= k:
+                            cv.wait()
+                        t, ei, ts, delay = tickets[k]
+                    r = srv.wait(t)
+                    e = reqs[ei]
+                    ok = r["status"] == 0
+                    if ok and e["op"] == "sort":
+                        ok = torch.equal(r["keys"], e["ref"][0]) and torch.equal(r["rids"], e["ref"][1])
+                    elif ok:
+                        ok = torch.equal(r["out_r"], e["ref"][0]) and torch.equal(r["out_s"], e["ref"][1])
+                    with lock:
+                        busy.discard(ei)
+                    done.append((delay + r["total_ms"], r["queue_ms"], r["run_ms"], ok, e["tuples"],
+                                 ts * 1e3 + delay + r["total_ms"]))
+                    k += 1
+
+            th = threading.Thread(target=waiter)
+            th.start()
+            t0 = time.perf_counter()
+            for i in range(nreq):
+                ei = int(order[i])
+                while True:  # an entry's output buffers serve one request at a time
+                    with lock:
+                        free = [x for x in range(pool) if (ei + x) % pool not in busy]
+                        if free:
+                            ei = (ei + free[0]) % pool
+                            busy.add(ei)
+                            break
+                    time.sleep(0.0005)  # every entry in flight: the arrival waits (counted in its latency)
+                now = time.perf_counter() - t0
+                if sched[i] > now:
+                    time.sleep(sched[i] - now)
+                delay = (time.perf_counter() - t0 - sched[i]) * 1e3
+                e = reqs[ei]
+                d = e["d"]
+                if e["op"] == "sort":
+                    t = srv.sort(d["s_keys"], d["s_rids"], keys_out=e["out"][0], rids_out=e["out"][1])
+                else:
+                    t = srv.join(d["r_keys"], d["r_rids"], d["s_keys"], d["s_rids"], capacity=e["count"],
+                                 out_r=e["out"][0], out_s=e["out"][1])
+                with cv:
+                    tickets.append((t, ei, sched[i], delay))
+                    cv.notify()
+            th.join()
+            peak = srv.memory()[1]
+            srv.close()
+            lat = [x[0] for x in done]
+            makespan_ms = max(x[5] for x in done)
+            tuples = sum(x[4] for x in done)
+            assert all(x[3] for x in done), "a served result differs from the same request run alone"
+            res_rate[mode] = {"p50_ms": round(pct(lat, 0.5), 3), "p99_ms": round(pct(lat, 0.99), 3),
+                              "p999_ms": round(pct(lat, 0.999), 3), "mean_ms": round(float(np.mean(lat)), 3),
+                              "tuples_per_s": round(tuples / (makespan_ms * 1e-3), 1),
+                              "mean_queue_ms": round(float(np.mean([x[1] for x in done])), 3),
+                              "mean_run_ms": round(float(np.mean([x[2] for x in done])), 3),
+                              "peak_arena_GB": round(peak / 1e9, 3), "results_identical": True}
+            log("serving %g req/s %s: P50 %.2f P99 %.2f P99.9 %.2f ms, %.3g tuples/s" %
+                (rate, mode, res_rate[mode]["p50_ms"], res_rate[mode]["p99_ms"], res_rate[mode]["p999_ms"],
+                 res_rate[mode]["tuples_per_s"]))
+        out["rates"]["%g" % rate] = res_rate
+    del reqs
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -260,6 +385,9 @@ def main():
     ap.add_argument("--learned-rows", type=int, default=1 << 28,
                     help="rows per relation of the learned-vs-radix comparison")
     ap.add_argument("--learned-repeats", type=int, default=5)
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
+    ap.add_argument("--serve-requests", type=int, default=1000, help="arrivals per rate")
+    ap.add_argument("--serve-rates", default="50,200,800,3200", help="arrival rates, requests/s")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="before timing, copy MIB MiB device-to-device three times (a plain copy "
                          "of known size that scales the FETCH_SIZE / WRITE_SIZE counters)")
@@ -380,6 +508,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_learned:
         line["learned_vs_radix"] = learned_vs_radix(tj, torch, args.learned_rows, args.learned_repeats)
+    if not args.no_serving:
+        line["serving"] = serving(tj, torch, [float(r) for r in args.serve_rates.split(",")], args.serve_requests)
     if not args.no_sweep:
         log("paper-shaped budget sweep")
         line["paper_shaped"] = paper_shaped_sweep(tj, torch, args.sweep_repeats)

@@ -371,9 +371,11 @@ hipError_t launch_probe(int key_bytes, const void* a, uint64_t na, const void* b
 // knows its exact key range and single-key buckets are recognised)
 // ---------------------------------------------------------------------------
 // LEARNED: the digit is the learned bucket of the row's key (model copied to
-// LDS), and every row's bucket is stored in bkt for the scatter.
-template <typename K, bool LEARNED>
-__global__ __launch_bounds__(PART_THREADS) void k_hist(const ChunkDesc* __restrict__ chunks,
+// LDS), and every row's bucket is stored in bkt for the scatter. The learned
+// variant runs 1024-thread blocks: its 34 KiB of LDS per block would cap
+// 256-thread blocks at half the waves a CU can hold.
+template <typename K, bool LEARNED, int NT = PART_THREADS>
+__global__ __launch_bounds__(NT) void k_hist(const ChunkDesc* __restrict__ chunks,
                                                        const GroupDesc* __restrict__ groups,
                                                        BufSet bufs, uint32_t* __restrict__ hist,
                                                        uint64_t* __restrict__ gmin,
@@ -389,39 +391,46 @@ __global__ __launch_bounds__(PART_THREADS) void k_hist(const ChunkDesc* __restri
     const K* __restrict__ src = (const K*)bufs.key[g.src][g.side] + g.src_koff + ch.start;
     uint16_t* __restrict__ bk = LEARNED ? bkt.b[g.side] + ch.start : nullptr;
     const uint32_t nbins = 1u << g.bits;
-    for (uint32_t d = threadIdx.x; d < nbins; d += PART_THREADS) {
+    for (uint32_t d = threadIdx.x; d < nbins; d += NT) {
         cnt[d] = 0;
         mn[d] = ~0ull;
         mx[d] = 0;
     }
-    if (LEARNED) rmi_to_lds<PART_THREADS>((tj_rmi_t*)lm_raw, model);
+    if (LEARNED) rmi_to_lds<NT>((tj_rmi_t*)lm_raw, model);
     lds_barrier();
     // Rows are counted with LDS atomics. When every valid row of a wave's round
     // falls in one bin (skewed inputs: buckets dominated by one key), the wave
     // reduces them first and one lane updates the bin.
     constexpr int U = 4;
     const uint32_t lane = threadIdx.x & 63;
-    for (uint32_t b0 = 0; b0 < ch.len; b0 += PART_THREADS * U) {  // trip count uniform over the block
+    for (uint32_t b0 = 0; b0 < ch.len; b0 += NT * U) {  // trip count uniform over the block
         const uint32_t q0 = b0 + threadIdx.x;
         K k[U];
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            const uint32_t q = q0 + u * PART_THREADS;
+            const uint32_t q = q0 + u * NT;
             k[u] = ld_clamp(src, q, ch.len);  // rows past the chunk are masked below
+        }
+        // learned buckets of the round's rows first: independent chains of LDS
+        // reads that the compiler interleaves
+        uint32_t lb[LEARNED ? U : 1];
+        if (LEARNED) {
+#pragma unroll
+            for (int u = 0; u < U; u++) lb[LEARNED ? u : 0] = min(rmi_bucket(lm, ord_of(k[u])), nbins - 1u);
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const uint32_t q = q0 + u * NT;
+                if (q < ch.len) bk[q] = (uint16_t)lb[LEARNED ? u : 0];
+            }
         }
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            const uint32_t q = q0 + u * PART_THREADS;
+            const uint32_t q = q0 + u * NT;
             const uint64_t o = ord_of(k[u]);
             const bool valid = q < ch.len && o >= g.flo && o <= g.fhi;
             uint32_t d;
-            if (LEARNED) {
-                d = min(rmi_bucket(lm, o), nbins - 1u);
-                if (q < ch.len) bk[q] = (uint16_t)d;
-                d = valid ? d : 0u;
-            } else {
-                d = valid ? (uint32_t)((o - g.base) >> g.shift) & (nbins - 1u) : 0u;
-            }
+            if (LEARNED) d = valid ? lb[LEARNED ? u : 0] : 0u;
+            else d = valid ? (uint32_t)((o - g.base) >> g.shift) & (nbins - 1u) : 0u;
             const uint64_t vm = ballot(valid);
             if (vm == 0) continue;
             const int first = __ffsll((unsigned long long)vm) - 1;
@@ -447,7 +456,7 @@ __global__ __launch_bounds__(PART_THREADS) void k_hist(const ChunkDesc* __restri
         }
     }
     lds_barrier();
-    for (uint32_t d = threadIdx.x; d < nbins; d += PART_THREADS) {
+    for (uint32_t d = threadIdx.x; d < nbins; d += NT) {
         hist[(uint64_t)blockIdx.x * NB + d] = cnt[d];
         if (cnt[d]) {
             atomicMin((unsigned long long*)&gmin[g.child0 + d], (unsigned long long)mn[d]);
@@ -471,16 +480,20 @@ hipError_t launch_hist(int key_bytes, const ChunkDesc* chunks, uint32_t nchunks,
     return hipGetLastError();
 }
 
+constexpr int LEARNED_HIST_THREADS = 1024;
+
 hipError_t launch_learned_hist(int key_bytes, const ChunkDesc* chunks, uint32_t nchunks,
                                const GroupDesc* groups, BufSet bufs, const tj_rmi_t* model, BktSet bkt,
                                uint32_t* hist, uint64_t* gmin, uint64_t* gmax, hipStream_t st)
 {
     if (nchunks == 0) return hipSuccess;
     if (key_bytes == 4)
-        hipLaunchKernelGGL((k_hist<int32_t, true>), dim3(nchunks), dim3(PART_THREADS), 0, st, chunks, groups,
+        hipLaunchKernelGGL((k_hist<int32_t, true, LEARNED_HIST_THREADS>), dim3(nchunks), dim3(LEARNED_HIST_THREADS), 0, st,
+                           chunks, groups,
                            bufs, hist, gmin, gmax, model, bkt);
     else
-        hipLaunchKernelGGL((k_hist<int64_t, true>), dim3(nchunks), dim3(PART_THREADS), 0, st, chunks, groups,
+        hipLaunchKernelGGL((k_hist<int64_t, true, LEARNED_HIST_THREADS>), dim3(nchunks), dim3(LEARNED_HIST_THREADS), 0, st,
+                           chunks, groups,
                            bufs, hist, gmin, gmax, model, bkt);
     return hipGetLastError();
 }
@@ -828,7 +841,7 @@ __global__ __launch_bounds__(SC_NT) void k_scatter(const ChunkDesc* __restrict__
         const uint32_t q = (w * KI + r) * 64 + l;
         key[r] = q < ch.len ? src_k[q] : K(0);
         if (RIDS) rid[r] = q < ch.len ? src_r[q] : 0;
-        if (DIGIN) bin[DIGIN ? r : 0] = q < ch.len ? src_b[q] : 0u;
+        if (DIGIN) bin[DIGIN ? r : 0] = ld_clamp(src_b, q, ch.len);  // rows past the chunk are masked
     }
     for (uint32_t t0 = 0; t0 < ch.len; t0 += TILE) {
         uint32_t dig[KI], rk[KI];
@@ -881,7 +894,7 @@ __global__ __launch_bounds__(SC_NT) void k_scatter(const ChunkDesc* __restrict__
                 const uint32_t q = n0 + (w * KI + r) * 64 + l;
                 key[r] = q < ch.len ? src_k[q] : K(0);
                 if (RIDS) rid[r] = q < ch.len ? src_r[q] : 0;
-                if (DIGIN) bin[DIGIN ? r : 0] = q < ch.len ? src_b[q] : 0u;
+                if (DIGIN) bin[DIGIN ? r : 0] = ld_clamp(src_b, q, ch.len);
             }
         }
         bool unordered = false;

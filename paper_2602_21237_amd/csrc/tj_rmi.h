@@ -18,6 +18,12 @@ constexpr uint32_t RMI_SUB = TJ_RMI_LEAVES / TJ_RMI_SEGMENTS;
 static_assert(RMI_SUB == 4, "four leaves per root segment");
 static_assert(sizeof(tj_rmi_t) % 16 == 0, "the model is copied in 16-byte words");
 
+// Both layers are written without branches (selects, min/max), so that the
+// evaluations of several rows interleave: each is a chain of dependent LDS
+// reads.
+__device__ __forceinline__ uint64_t rmi_min(uint64_t a, uint64_t b) { return a < b ? a : b; }
+__device__ __forceinline__ uint64_t rmi_max(uint64_t a, uint64_t b) { return a > b ? a : b; }
+
 // Root layer: the leaf of ordinal x. `m` may live in LDS or global memory.
 __device__ __forceinline__ uint32_t rmi_leaf(const tj_rmi_t& m, uint64_t x)
 {
@@ -26,9 +32,9 @@ __device__ __forceinline__ uint32_t rmi_leaf(const tj_rmi_t& m, uint64_t x)
     uint32_t j = 0;
 #pragma unroll
     for (uint32_t step = TJ_RMI_SEGMENTS / 2; step >= 1; step >>= 1)
-        if (m.knot[j + step] <= x) j += step;
+        j = m.knot[j + step] <= x ? j + step : j;
     const uint64_t lo = m.knot[j], hi = m.knot[j + 1];
-    const uint64_t xc = x < lo ? lo : (x > hi ? hi : x);
+    const uint64_t xc = rmi_min(rmi_max(x, lo), hi);
     const float t = (float)(xc - lo) * m.knot_inv[j];
     const float q = t * (float)RMI_SUB;  // exact: a power of two
     const uint32_t sub = q >= (float)(RMI_SUB - 1) ? RMI_SUB - 1 : (uint32_t)q;
@@ -41,13 +47,13 @@ __device__ __forceinline__ uint32_t rmi_bucket(const tj_rmi_t& m, uint64_t x)
 #pragma clang fp contract(off)
     const uint32_t l = rmi_leaf(m, x);
     const uint64_t base = m.leaf_base[l];
-    const uint64_t up = x - base, down = base - x;  // one of them is the distance
-    const int64_t sd = x >= base ? (int64_t)(up < RMI_SAT ? up : RMI_SAT)
-                                 : -(int64_t)(down < RMI_SAT ? down : RMI_SAT);
+    const bool ge = x >= base;
+    const uint64_t dist = rmi_min(ge ? x - base : base - x, RMI_SAT);
+    const int64_t sd = ge ? (int64_t)dist : -(int64_t)dist;
     const float prod = m.leaf_b[l] * (float)sd;
     const float y = m.leaf_a[l] + prod;
     const float lo = (float)m.leaf_lo[l], hi = (float)m.leaf_hi[l];
-    const float yc = y < lo ? lo : (y > hi ? hi : y);
+    const float yc = fminf(fmaxf(y, lo), hi);  // y is never NaN
     return (uint32_t)yc;  // yc >= 0: truncation is floor
 }
 

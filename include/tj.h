@@ -229,6 +229,53 @@ int tj_rmi_buckets(int key_type, const void *keys, uint64_t n, const tj_rmi_t *m
                    uint16_t *buckets, void *workspace, uint64_t workspace_bytes, void *stream);
 
 /*
+ * Composite (multi-column) keys.
+ *
+ * A relation keyed by m columns is a set of points in an m-dimensional key
+ * space (Sec. III.B); the sort orders them lexicographically, column 0 first
+ * (the row-major linearisation of that space), and the join matches rows
+ * whose points coincide in every column (Sec. IV.A, a join condition over
+ * several common attributes). Columns may mix int32 and int64 (signed); a
+ * column's type must be the same in R and S.
+ *
+ * Method: the minimum and maximum of every column give its bit width b_c
+ * (of max - min). Columns whose widths sum to at most 64 bits are packed
+ * into one key (column minimum subtracted, most significant column first),
+ * which orders and matches exactly like the tuple; the packed key is 4 bytes
+ * when it fits 32 bits. Sort: one stable sort on the packed key, or, when
+ * the widths exceed 64 bits, stable sorts on groups of columns of at most 64
+ * bits each, least significant group first (LSD), carrying the permutation.
+ * Join: one join on the packed keys; beyond 64 bits, R and S are sorted
+ * together by their tuples, each distinct tuple is numbered in order (a
+ * dense rank), and the join runs on the ranks. Results are those of the
+ * single-key calls on the tuples: stable lexicographic order; canonical pair
+ * order (tuple, then R position, then S position).
+ *
+ *   ncols: 1 .. TJ_MAX_KEY_COLS; key_types[c]: TJ_KEY_I32 or TJ_KEY_I64;
+ *   keys_in[c] / r_keys[c] / s_keys[c]: device key columns;
+ *   keys_out[c]: device output columns (same types), rids as in tj_sort.
+ * Workspace: tj_multi_workspace_query gives the bytes at which no budget
+ * binds; smaller workspaces are accepted down to the fixed arrays of the call
+ * plus the minimum of its inner sort or join (TJ_E_WORKSPACE below that).
+ * Errors as for the single-key calls; outputs must not overlap inputs or the
+ * workspace (TJ_E_ALIAS).
+ */
+#define TJ_MAX_KEY_COLS 8
+int tj_multi_workspace_query(int op, int ncols, const int *key_types, uint64_t n_r, uint64_t n_s,
+                             uint64_t *bytes);
+int tj_sort_multi(int ncols, const int *key_types, const void *const *keys_in, const int32_t *rids_in,
+                  uint64_t n, void *const *keys_out, int32_t *rids_out, void *workspace,
+                  uint64_t workspace_bytes, void *stream, tj_stats_t *stats);
+int tj_join_count_multi(int ncols, const int *key_types, const void *const *r_keys, uint64_t n_r,
+                        const void *const *s_keys, uint64_t n_s, uint64_t *count, void *workspace,
+                        uint64_t workspace_bytes, void *stream, tj_stats_t *stats);
+int tj_join_materialize_multi(int ncols, const int *key_types, const void *const *r_keys,
+                              const int32_t *r_rids, uint64_t n_r, const void *const *s_keys,
+                              const int32_t *s_rids, uint64_t n_s, int32_t *out_r, int32_t *out_s,
+                              uint64_t capacity, uint64_t *count, void *workspace,
+                              uint64_t workspace_bytes, void *stream, tj_stats_t *stats);
+
+/*
  * Serving loop: requests of uneven sizes, admitted against a device-memory
  * budget and run concurrently.
  *

@@ -206,6 +206,31 @@ hipError_t launch_expand(int32_t* dst, const int32_t* src, uint64_t n, uint64_t 
                          hipStream_t st);
 hipError_t launch_wave_scan_test(const uint32_t* in, uint32_t* out, uint64_t n, hipStream_t st);
 
+// Composite keys (tj_multi.hip). Rows r < n_a come from the col_a columns,
+// rows n_a.. from col_b (a relation pair seen as one set of rows).
+constexpr int MAX_KEY_COLS = 8;
+struct PackArgs {
+    const void* col_a[MAX_KEY_COLS];
+    const void* col_b[MAX_KEY_COLS];
+    uint64_t min[MAX_KEY_COLS];     // column minimum (ordinal), subtracted before the shift
+    uint32_t shift[MAX_KEY_COLS];   // bit position of the column in the packed key; 64: no bits
+    int32_t kb[MAX_KEY_COLS];       // key bytes of the column (4 or 8)
+    uint64_t n_a;
+    int32_t ncols;
+    int32_t pad;
+};
+// out[i] = packed key of row perm[i] (perm NULL: row i), stored as a signed
+// key of out_bytes (4 or 8) bytes that orders like the packed unsigned value.
+hipError_t launch_pack(const PackArgs& a, const int32_t* perm, uint64_t n, void* out, int out_bytes, hipStream_t st);
+// flag[i] = 1 if the key tuple of row perm[i] differs from that of row perm[i - 1] (flag[0] = 1).
+hipError_t launch_tuple_flags(const PackArgs& a, const int32_t* perm, uint64_t n, uint32_t* flag, hipStream_t st);
+hipError_t launch_gather(int elem_bytes, const void* in, const int32_t* perm, uint64_t n, void* out, hipStream_t st);
+hipError_t launch_iota(int32_t* out, uint64_t n, hipStream_t st);
+hipError_t launch_scatter_back(const uint32_t* src, const int32_t* perm, uint64_t n, int32_t* dst, hipStream_t st);
+// Inclusive prefix sum of n uint32 values; scratch needs scan_scratch_words(n) words.
+uint64_t scan_scratch_words(uint64_t n);
+hipError_t launch_incl_scan(const uint32_t* in, uint64_t n, uint32_t* scratch, uint32_t* out, hipStream_t st);
+
 // Learned partitioner (tj_rmi.hip).
 // Rows floor(i n / m), i < m, of keys[n] to out[off + i]; rids[off + i] = off + i.
 hipError_t launch_rmi_sample(int key_bytes, const void* keys, uint64_t n, uint32_t m, void* out,

@@ -104,6 +104,12 @@ EXPORTS = {
                                               ctypes.POINTER(_u64)]),
     "tj_rmi_train": (ctypes.c_int, [ctypes.c_int, _P, _u64, _P, _u64, ctypes.c_uint32, _P, _P, _u64, _P]),
     "tj_rmi_buckets": (ctypes.c_int, [ctypes.c_int, _P, _u64, _P, _P, _P, _u64, _P]),
+    "tj_multi_workspace_query": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _P, _u64, _u64, ctypes.POINTER(_u64)]),
+    "tj_sort_multi": (ctypes.c_int, [ctypes.c_int, _P, _P, _P, _u64, _P, _P, _P, _u64, _P, _P]),
+    "tj_join_count_multi": (ctypes.c_int, [ctypes.c_int, _P, _P, _u64, _P, _u64, ctypes.POINTER(_u64), _P, _u64,
+                                           _P, _P]),
+    "tj_join_materialize_multi": (ctypes.c_int, [ctypes.c_int, _P, _P, _P, _u64, _P, _P, _u64, _P, _P, _u64,
+                                                 ctypes.POINTER(_u64), _P, _u64, _P, _P]),
     "tj_server_create": (ctypes.c_int, [_P, _u64, ctypes.c_int, ctypes.POINTER(_P)]),
     "tj_server_submit": (ctypes.c_int, [_P, _P, ctypes.POINTER(_u64)]),
     "tj_server_wait": (ctypes.c_int, [_P, _u64, _P]),
@@ -309,6 +315,84 @@ def join(r_keys, r_rids, s_keys, s_rids, capacity: int | None = None, out_r=None
     else:
         opt = _options(partitioner, sample_permille, learned_min_rows)
         _check(load().tj_join_materialize_ex(*args, ctypes.byref(opt), ctypes.byref(st)), "tj_join_materialize_ex")
+    c = int(cnt.value)
+    res = (out_r[:c], out_s[:c])
+    return res + (st.as_dict(),) if stats else res
+
+
+# --------------------------------------------------------------------------- composite keys
+
+def _col_arrays(cols):
+    cols = list(cols)
+    for i, c in enumerate(cols):
+        _dev(c, "key column %d" % i)
+    types = (ctypes.c_int * len(cols))(*[_key_type(c) for c in cols])
+    ptrs = (ctypes.c_void_p * len(cols))(*[c.data_ptr() for c in cols])
+    return types, ptrs
+
+
+def multi_workspace_query(op: int, cols, n_r: int, n_s: int = 0) -> int:
+    types = (ctypes.c_int * len(cols))(*[_key_type(c) for c in cols])
+    b = _u64()
+    _check(load().tj_multi_workspace_query(op, len(cols), types, n_r, n_s, ctypes.byref(b)),
+           "tj_multi_workspace_query")
+    return int(b.value)
+
+
+def sort_multi(cols, rids, workspace_bytes=None, stream=None, stats: bool = False):
+    """Stable lexicographic sort of rows by key columns cols[0], cols[1], ...
+    (tj_sort_multi). Returns (sorted columns, rids)."""
+    torch = _torch()
+    types, ptrs = _col_arrays(cols)
+    _dev(rids, "rids")
+    n = rids.numel()
+    outs = [torch.empty_like(c) for c in cols]
+    optrs = (ctypes.c_void_p * len(cols))(*[o.data_ptr() for o in outs])
+    rout = torch.empty_like(rids)
+    need = multi_workspace_query(TJ_OP_SORT, cols, n) if workspace_bytes is None else workspace_bytes
+    ws = torch.empty(max(need, 256), dtype=torch.uint8, device=rids.device)
+    st = Stats()
+    _check(load().tj_sort_multi(len(cols), types, ptrs, rids.data_ptr(), n, optrs, rout.data_ptr(), ws.data_ptr(),
+                                need, _stream(stream), ctypes.byref(st)), "tj_sort_multi")
+    return (outs, rout, st.as_dict()) if stats else (outs, rout)
+
+
+def join_count_multi(r_cols, s_cols, workspace_bytes=None, stream=None, stats: bool = False):
+    """Equi-join size on all key columns (tj_join_count_multi)."""
+    torch = _torch()
+    rt, rp = _col_arrays(r_cols)
+    _, sp = _col_arrays(s_cols)
+    n_r, n_s = r_cols[0].numel(), s_cols[0].numel()
+    need = multi_workspace_query(TJ_OP_JOIN_COUNT, r_cols, n_r, n_s) if workspace_bytes is None else workspace_bytes
+    ws = torch.empty(max(need, 256), dtype=torch.uint8, device=r_cols[0].device)
+    cnt = _u64()
+    st = Stats()
+    _check(load().tj_join_count_multi(len(r_cols), rt, rp, n_r, sp, n_s, ctypes.byref(cnt), ws.data_ptr(), need,
+                                      _stream(stream), ctypes.byref(st)), "tj_join_count_multi")
+    return (int(cnt.value), st.as_dict()) if stats else int(cnt.value)
+
+
+def join_multi(r_cols, r_rids, s_cols, s_rids, capacity: int | None = None, workspace_bytes=None, stream=None,
+               stats: bool = False):
+    """All (rid_R, rid_S) pairs equal on every key column, canonical order
+    (tj_join_materialize_multi)."""
+    torch = _torch()
+    rt, rp = _col_arrays(r_cols)
+    _, sp = _col_arrays(s_cols)
+    n_r, n_s = r_cols[0].numel(), s_cols[0].numel()
+    if capacity is None:
+        capacity = join_count_multi(r_cols, s_cols, stream=stream)
+    out_r = torch.empty(max(capacity, 1), dtype=torch.int32, device=r_rids.device)
+    out_s = torch.empty(max(capacity, 1), dtype=torch.int32, device=r_rids.device)
+    need = (multi_workspace_query(TJ_OP_JOIN_MATERIALIZE, r_cols, n_r, n_s) if workspace_bytes is None
+            else workspace_bytes)
+    ws = torch.empty(max(need, 256), dtype=torch.uint8, device=r_rids.device)
+    cnt = _u64()
+    st = Stats()
+    _check(load().tj_join_materialize_multi(len(r_cols), rt, rp, r_rids.data_ptr(), n_r, sp, s_rids.data_ptr(), n_s,
+                                            out_r.data_ptr(), out_s.data_ptr(), capacity, ctypes.byref(cnt),
+                                            ws.data_ptr(), need, _stream(stream), ctypes.byref(st)),
+           "tj_join_materialize_multi")
     c = int(cnt.value)
     res = (out_r[:c], out_s[:c])
     return res + (st.as_dict(),) if stats else res

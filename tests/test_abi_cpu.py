@@ -174,3 +174,30 @@ def test_server_argument_errors():
     assert lib.tj_server_destroy(None) == tj.TJ_E_ARG
     assert ctypes.sizeof(tj.Request) == _c_sizeof("tj_request_t")
     assert ctypes.sizeof(tj.Result) == _c_sizeof("tj_result_t")
+
+
+def test_multi_argument_errors():
+    lib = tj.load()
+    two = (ctypes.c_int * 2)(8, 4)
+    bad = (ctypes.c_int * 2)(8, 5)
+    cols = (ctypes.c_void_p * 2)(A, B)
+    outs = (ctypes.c_void_p * 2)(C, C + 8000)
+    b = ctypes.c_uint64()
+    assert lib.tj_multi_workspace_query(0, 0, two, 10, 0, ctypes.byref(b)) == tj.TJ_E_ARG
+    assert lib.tj_multi_workspace_query(0, 9, two, 10, 0, ctypes.byref(b)) == tj.TJ_E_ARG
+    assert lib.tj_multi_workspace_query(0, 2, bad, 10, 0, ctypes.byref(b)) == tj.TJ_E_ARG
+    assert lib.tj_multi_workspace_query(3, 2, two, 10, 0, ctypes.byref(b)) == tj.TJ_E_ARG
+    assert lib.tj_multi_workspace_query(2, 2, two, 1 << 30, 1 << 30, ctypes.byref(b)) == tj.TJ_E_TOO_LARGE
+    assert lib.tj_multi_workspace_query(0, 2, two, 1000, 0, ctypes.byref(b)) == tj.TJ_OK and b.value > 24000
+    n = 1000
+    assert lib.tj_sort_multi(2, bad, cols, D, n, outs, W, W + (1 << 20), 1 << 30, None, None) == tj.TJ_E_ARG
+    assert lib.tj_sort_multi(2, two, cols, D, 1 << 31, outs, W, W + (1 << 20), 1 << 30, None, None) == tj.TJ_E_TOO_LARGE
+    assert lib.tj_sort_multi(2, two, None, D, n, outs, W, W + (1 << 20), 1 << 30, None, None) == tj.TJ_E_ARG
+    assert lib.tj_sort_multi(2, two, cols, D, n, outs, W, W + 8 + (1 << 20), 1 << 30, None, None) == tj.TJ_E_WORKSPACE
+    aliased = (ctypes.c_void_p * 2)(A + 8, C + 8000)
+    assert lib.tj_sort_multi(2, two, cols, D, n, aliased, W, W + (1 << 20), 1 << 30, None, None) == tj.TJ_E_ALIAS
+    assert lib.tj_sort_multi(2, two, cols, D, 0, outs, W, W + (1 << 20), 1 << 30, None, None) == tj.TJ_OK
+    cnt = ctypes.c_uint64(5)
+    assert lib.tj_join_count_multi(2, two, cols, 10, cols, 10, None, W, 1 << 30, None, None) == tj.TJ_E_ARG
+    assert lib.tj_join_count_multi(2, two, cols, 0, cols, 10, ctypes.byref(cnt), W, 1 << 30, None, None) == tj.TJ_OK
+    assert cnt.value == 0

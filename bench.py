@@ -19,6 +19,8 @@ budgets of 1 MiB, 64 MiB and unlimited, theta in {0, 0.99}.
 learned_vs_radix: |R| = |S| = 2^28 int64 keys from a lognormal, an interval
 mixture and a gapped sequence; sort, join count and join of the same inputs
 with the radix and with the learned first pass (median of 5), outputs equal.
+composite_keys: sort and join on two key columns, 2^26 rows per relation,
+packed into one key (60 bits) or wide (128 bits: LSD groups / dense ranks).
 serving: Poisson arrivals at 50, 200, 800 and 3200 requests/s of sorts and joins
 (per-side rows log-uniform in [10^3, 10^7]) against the serving loop with a
 32 GiB workspace budget, 8 slots against one at a time: P50/P99/P99.9 latency
@@ -371,6 +373,61 @@ def serving(tj, torch, rates, nreq: int, pool: int = 48, arena_gib: int = 32, sl
     return out
 
 
+def composite_keys(tj, torch, n: int, repeats: int = 3):
+    """Composite-key sort (n rows) and join (n x n rows) through tj_*_multi:
+    'packed' = an int32 column in [0, 2^20) and an int64 column in [0, 2^40)
+    (60 bits: one 8-byte sort key); 'wide' = two int64 columns over the full
+    range (128 bits: two stable sorts; the join through dense ranks). S copies
+    the tuples of uniformly chosen R rows for 80% of its rows."""
+    rng = np.random.default_rng(31)
+    specs = {"packed": [(0, 1 << 20, np.int32), (0, 1 << 40, np.int64)],
+             "wide": [(np.iinfo(np.int64).min, np.iinfo(np.int64).max, np.int64)] * 2}
+    out = {"rows": n, "repeats": repeats}
+    for name, spec in specs.items():
+        log("composite keys: %s, n = %d" % (name, n))
+        rc = [rng.integers(lo, hi, n, dtype=np.int64).astype(dt) for lo, hi, dt in spec]
+        sc = [rng.integers(lo, hi, n, dtype=np.int64).astype(dt) for lo, hi, dt in spec]
+        m = int(0.8 * n)
+        idx = rng.integers(0, n, m)
+        for a, b in zip(rc, sc):
+            b[:m] = a[idx]
+        drc = [torch.from_numpy(c).to("cuda") for c in rc]
+        dsc = [torch.from_numpy(c).to("cuda") for c in sc]
+        del rc, sc
+        rid = torch.arange(n, dtype=torch.int32, device="cuda")
+        res = {}
+        for op in ("sort", "join"):
+            times = []
+            for i in range(repeats + 1):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                if op == "sort":
+                    outs, rout, st = tj.sort_multi(drc, rid, stats=True)
+                else:
+                    pr, ps, st = tj.join_multi(drc, rid, dsc, rid, stats=True)
+                torch.cuda.synchronize()
+                if i:
+                    times.append((time.perf_counter() - t0) * 1e3)
+            if op == "sort":
+                k0, k1 = outs
+                ok = bool(((k0[1:] > k0[:-1]) | ((k0[1:] == k0[:-1]) & (k1[1:] >= k1[:-1]))).all().item())
+                assert ok, "composite sort output not ordered"
+                res["sort"] = {"ms": round(pct(times, 0.5), 3), "rows_per_s": round(n / (pct(times, 0.5) * 1e-3), 1),
+                               "sort_passes": st["passes"]}
+                del outs, rout
+            else:
+                ok = all(torch.equal(a[pr.long()], b[ps.long()]) for a, b in zip(drc, dsc))
+                assert ok, "composite join pairs do not match"
+                res["join"] = {"ms": round(pct(times, 0.5), 3), "pairs": int(pr.numel()),
+                               "tuples_per_s": round(2 * n / (pct(times, 0.5) * 1e-3), 1),
+                               "note": "count, then materialise (two calls)"}
+                del pr, ps
+        out[name] = res
+        del drc, dsc, rid
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -386,6 +443,8 @@ def main():
                     help="rows per relation of the learned-vs-radix comparison")
     ap.add_argument("--learned-repeats", type=int, default=5)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
+    ap.add_argument("--no-multi", action="store_true", help="skip the composite-key measurement")
+    ap.add_argument("--multi-rows", type=int, default=1 << 26)
     ap.add_argument("--serve-requests", type=int, default=1000, help="arrivals per rate")
     ap.add_argument("--serve-rates", default="50,200,800,3200", help="arrival rates, requests/s")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -508,6 +567,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_learned:
         line["learned_vs_radix"] = learned_vs_radix(tj, torch, args.learned_rows, args.learned_repeats)
+    if not args.no_multi:
+        line["composite_keys"] = composite_keys(tj, torch, args.multi_rows)
     if not args.no_serving:
         line["serving"] = serving(tj, torch, [float(r) for r in args.serve_rates.split(",")], args.serve_requests)
     if not args.no_sweep:

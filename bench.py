@@ -18,7 +18,8 @@ paper_shaped: P50/P99 latency of the |R| = |S| = 10^6 workload at workspace
 budgets of 1 MiB, 64 MiB and unlimited, theta in {0, 0.99}.
 learned_vs_radix: |R| = |S| = 2^28 int64 keys from a lognormal, an interval
 mixture and a gapped sequence; sort, join count and join of the same inputs
-with the radix and with the learned first pass (median of 5), outputs equal.
+with the radix, the learned and the auto first pass (median of 5), outputs
+equal.
 composite_keys: sort and join on two key columns, 2^26 rows per relation,
 packed into one key (60 bits) or wide (128 bits: LSD groups / dense ranks).
 serving: Poisson arrivals at 50, 200, 800 and 3200 requests/s of sorts and joins
@@ -202,7 +203,7 @@ def learned_vs_radix(tj, torch, n: int, repeats: int):
         if mat:
             out_r = torch.empty(max(count, 1), dtype=torch.int32, device="cuda")
             out_s = torch.empty(max(count, 1), dtype=torch.int32, device="cuda")
-        for mode in ("radix", "learned"):
+        for mode in ("radix", "learned", "auto"):
             ko, ro = torch.empty_like(rk), torch.empty_like(rr)
             ops = {"sort": lambda: tj.sort(rk, rr, keys_out=ko, rids_out=ro, workspace=ws_sort, stats=True,
                                            partitioner=mode)[2],
@@ -228,6 +229,9 @@ def learned_vs_radix(tj, torch, n: int, repeats: int):
                 r[mode + "_passes"] = st["passes"]
                 r[mode + "_planned_MB"] = round((st["bytes_read"] + st["bytes_written"]) / 1e6, 1)
                 r[mode + "_kernels_ms"] = {k: round(v["ms"] / repeats, 3) for k, v in fams.items() if v["launches"]}
+                if mode == "auto":
+                    r["auto_chose"] = "learned" if st["learned"] else "radix"
+                    r["auto_speedup"] = round(r["radix_ms"] / r["auto_ms"], 3)
                 if mode == "learned":
                     r["learned_ran"] = bool(st["learned"])
                     r["learned_overflow_buckets"] = st["learned_overflow"]
@@ -237,7 +241,7 @@ def learned_vs_radix(tj, torch, n: int, repeats: int):
                 outs[mode] = (ko, ro, out_r[:count].clone(), out_s[:count].clone())
             else:
                 outs[mode] = (ko, ro)
-        same = all(torch.equal(a, b) for a, b in zip(outs["radix"], outs["learned"]))
+        same = all(torch.equal(a, b) for m in ("learned", "auto") for a, b in zip(outs["radix"], outs[m]))
         assert same, "learned and radix outputs differ (%s)" % dist
         res["join_count_value"] = count
         res["outputs_identical"] = same

@@ -174,9 +174,18 @@ typedef struct {
     uint32_t sample_rows;                /* M */
 } tj_rmi_t;
 
-enum tj_partitioner { TJ_PART_RADIX = 0, TJ_PART_LEARNED = 1 };
+/*
+ * TJ_PART_AUTO decides at execution time from the data: the call starts the
+ * radix path, and once the first pass's histogram is known (before anything
+ * is moved) it counts the rows in buckets holding more than 8 times the mean
+ * bucket size. If they are more than half of all rows, the radix digit would
+ * leave them for further passes: the call trains the learned model and
+ * partitions with it instead. Otherwise it continues with radix, at the cost
+ * of one read-back of the bucket counts.
+ */
+enum tj_partitioner { TJ_PART_RADIX = 0, TJ_PART_LEARNED = 1, TJ_PART_AUTO = 2 };
 typedef struct {
-    uint32_t partitioner;       /* TJ_PART_RADIX or TJ_PART_LEARNED */
+    uint32_t partitioner;       /* TJ_PART_RADIX, TJ_PART_LEARNED or TJ_PART_AUTO */
     uint32_t sample_permille;   /* sample per relation in 1/1000 of its rows; 0 means 10 (1%) */
     uint64_t learned_min_rows;  /* rows (R + S) below which the radix digit is kept; 0 means 2^22.
                                    Values below 8193 act as 8193 (one LDS block holds smaller inputs) */
@@ -316,7 +325,7 @@ typedef struct {
     void *out0;                  /* sort: keys_out[n_r]; materialise: out_r[capacity] (device) */
     int32_t *out1;               /* sort: rids_out[n_r]; materialise: out_s[capacity] */
     uint64_t capacity;           /* materialise: pairs out0/out1 hold */
-    uint32_t partitioner;        /* TJ_PART_RADIX or TJ_PART_LEARNED (tj_options_t defaults) */
+    uint32_t partitioner;        /* a tj_partitioner value (tj_options_t defaults otherwise) */
     uint32_t pad;
 } tj_request_t;
 typedef struct {

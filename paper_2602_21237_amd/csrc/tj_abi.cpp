@@ -47,6 +47,8 @@ constexpr size_t DEVICE_BATCH_MIN_SEGS = 16;  // segments of a pass before leave
 constexpr uint32_t LEARNED_BUCKETS = 512;        // buckets of the learned pass: one full-width digit
 constexpr uint32_t DEFAULT_PERMILLE = 10;        // 1% sample per relation
 constexpr uint64_t DEFAULT_LEARNED_MIN_ROWS = 1ull << 22;
+constexpr uint64_t AUTO_HEAVY = 8;               // a radix bucket over 8x the mean counts as heavy
+constexpr int TJ_SWITCH_LEARNED = 100;           // internal: the auto partitioner hands over
 static_assert((LEARNED_BUCKETS & (LEARNED_BUCKETS - 1)) == 0 && LEARNED_BUCKETS <= (uint32_t)NB,
               "learned buckets must be one digit of the scatter");
 
@@ -337,6 +339,7 @@ struct Exec {
     tj_rmi_t* d_model = nullptr;    // learned bucket function (when trained)
     BktSet bkt{};                   // per-row buckets of the learned pass
     bool learned_pass = false;      // the next partition pass is the learned one
+    bool auto_probe = false;        // the next pass may hand over to the learned partitioner
 
     // data buffer capacities (rows per side) when the buffers live in the workspace
     uint64_t cap_r = 0, cap_s = 0;
@@ -641,6 +644,29 @@ struct Exec {
             TJ_CK(timed(F_SCAN, 0, [&] {
                 return launch_scan(d_cblocks, ncb, d_groups, ng, d_hist, d_cbsum, d_ccount, d_cstart, st);
             }));
+            if (auto_probe) {
+                // The radix digit's bucket sizes decide: when most rows sit in
+                // buckets over AUTO_HEAVY times the mean, the digit leaves them
+                // for further passes and the learned partitioner takes over
+                // (nothing has been scattered yet).
+                auto_probe = false;
+                std::vector<uint32_t> cnt(child);
+                TJ_CK(hipMemcpyAsync(cnt.data(), d_ccount, (size_t)child * 4, hipMemcpyDeviceToHost, st));
+                TJ_CK(hipStreamSynchronize(st));
+                uint64_t rows = 0, heavy = 0;
+                std::vector<uint64_t> per(child / nside, 0);
+                for (uint32_t gi = 0; gi < ng; gi++)
+                    for (uint32_t d = 0; d < (1u << groups[gi].bits); d++)
+                        per[groups[gi - gi % nside].child0 / nside + d] += cnt[groups[gi].child0 + d];
+                for (uint64_t c : per) rows += c;
+                const uint64_t nb = per.empty() ? 1 : per.size();
+                for (uint64_t c : per)
+                    if (c * nb > AUTO_HEAVY * rows) heavy += c;
+                if (2 * heavy > rows) {
+                    stats.passes--;  // histogram only
+                    return TJ_SWITCH_LEARNED;
+                }
+            }
             if (learned) {
                 TJ_CK(timed(F_LSCATTER, scanned * (rb + 2) + written, [&] {
                     return launch_learned_scatter((int)kb_in, sh.rids, d_chunks, nc, d_groups, d_hist, d_cbsum,
@@ -1533,12 +1559,15 @@ namespace tj {
 namespace {
 
 // Learned options in effect for a call: false means the radix path.
-int learned_wanted(const tj_options_t* opt, uint64_t rows, bool& want, uint32_t& permille)
+int learned_wanted(const tj_options_t* opt, uint64_t rows, bool& want, bool& is_auto, uint32_t& permille)
 {
     want = false;
+    is_auto = opt && opt->partitioner == TJ_PART_AUTO;
     permille = DEFAULT_PERMILLE;
     if (!opt) return TJ_OK;
-    if (opt->partitioner != TJ_PART_RADIX && opt->partitioner != TJ_PART_LEARNED) return TJ_E_ARG;
+    if (opt->partitioner != TJ_PART_RADIX && opt->partitioner != TJ_PART_LEARNED &&
+        opt->partitioner != TJ_PART_AUTO)
+        return TJ_E_ARG;
     if (opt->partitioner == TJ_PART_RADIX) return TJ_OK;
     if (opt->sample_permille > 1000) return TJ_E_ARG;
     if (opt->sample_permille) permille = opt->sample_permille;
@@ -1556,9 +1585,9 @@ static int sort_impl(int key_type, const void* keys_in, const int32_t* rids_in, 
                      const tj_options_t* opt, tj_stats_t* stats)
 {
     if (validate_common(key_type) != TJ_OK) return TJ_E_ARG;
-    bool want_learned;
+    bool want_learned, is_auto;
     uint32_t permille;
-    TJ_RET(learned_wanted(opt, n, want_learned, permille));
+    TJ_RET(learned_wanted(opt, n, want_learned, is_auto, permille));
     if (n > kMaxRows) return TJ_E_TOO_LARGE;
     if (stats) std::memset(stats, 0, sizeof(*stats));
     if (n == 0) return TJ_OK;
@@ -1592,12 +1621,21 @@ static int sort_impl(int key_type, const void* keys_in, const int32_t* rids_in, 
     x.bufs.rid[BUF_A][0] = rids_out;
     x.out_is_a = unlimited;
 
-    bool learned = false;
-    if (unlimited && want_learned) {
-        // buffer B (workspace) is free until the second pass: the training
-        // scratch, then the learned pass's bucket ids
+    // buffer B (workspace) is free until the second pass: the training
+    // scratch, then the learned pass's bucket ids
+    auto train = [&]() -> int {
         char* b0 = (char*)x.bufs.key[BUF_B][0];
         const int rc = x.train_rmi(keys_in, n, nullptr, 0, permille, b0, (uint64_t)(end - b0));
+        if (rc == TJ_OK) {
+            x.bkt.b[0] = (uint16_t*)b0;
+            x.learned_pass = true;
+            x.stats.learned = 1;
+        }
+        return rc;
+    };
+    bool learned = false;
+    if (unlimited && want_learned && !is_auto) {
+        const int rc = train();
         if (rc != TJ_OK && rc != TJ_E_WORKSPACE) return rc;
         learned = rc == TJ_OK;
     }
@@ -1605,12 +1643,15 @@ static int sort_impl(int key_type, const void* keys_in, const int32_t* rids_in, 
     if (!learned) TJ_RET(probe(x, keys_in, n, nullptr, 0, lo, hi));
     if (unlimited) {
         x.stats.key_ranges = 1;
-        if (learned) {
-            x.bkt.b[0] = (uint16_t*)x.bufs.key[BUF_B][0];
-            x.learned_pass = true;
-            x.stats.learned = 1;
+        x.auto_probe = want_learned && is_auto;
+        int rc = learned ? x.process_range(0, ~0ull, n, 0, false, 0) : x.process_range(lo, hi, n, 0, false, 0);
+        if (rc == TJ_SWITCH_LEARNED) {
+            const int tr = train();
+            if (tr != TJ_OK && tr != TJ_E_WORKSPACE) return tr;
+            x.auto_probe = false;
+            rc = tr == TJ_OK ? x.process_range(0, ~0ull, n, 0, false, 0) : x.process_range(lo, hi, n, 0, false, 0);
         }
-        TJ_RET(x.process_range(lo, hi, n, 0, false, 0));
+        TJ_RET(rc);
         TJ_RET(x.run_sort_leaves(keys_out, rids_out));
     } else {
         // ranges: buffer A and B both live in the workspace; outputs are written
@@ -1664,9 +1705,9 @@ static int join_impl(int key_type, const void* r_keys, const int32_t* r_rids, ui
                      const tj_options_t* opt)
 {
     if (validate_common(key_type) != TJ_OK) return TJ_E_ARG;
-    bool want_learned;
+    bool want_learned, is_auto;
     uint32_t permille;
-    TJ_RET(learned_wanted(opt, n_r + n_s, want_learned, permille));
+    TJ_RET(learned_wanted(opt, n_r + n_s, want_learned, is_auto, permille));
     if (!count) return TJ_E_ARG;
     if (n_r > kMaxRows || n_s > kMaxRows) return TJ_E_TOO_LARGE;
     if (stats) std::memset(stats, 0, sizeof(*stats));
@@ -1706,11 +1747,21 @@ static int join_impl(int key_type, const void* r_keys, const int32_t* r_rids, ui
     x.bufs.rid[BUF_IN][0] = r_rids;
     x.bufs.rid[BUF_IN][1] = s_rids;
 
-    bool learned = false;
-    if (unlimited && want_learned) {
-        // buffer B is free until the second pass (see tj_sort)
+    // buffer B is free until the second pass (see tj_sort)
+    auto train = [&]() -> int {
         char* b0 = (char*)x.bufs.key[BUF_B][0];
         const int rc = x.train_rmi(r_keys, n_r, s_keys, n_s, permille, b0, (uint64_t)(end - b0));
+        if (rc == TJ_OK) {
+            x.bkt.b[0] = (uint16_t*)x.bufs.key[BUF_B][0];
+            x.bkt.b[1] = (uint16_t*)x.bufs.key[BUF_B][1];
+            x.learned_pass = true;
+            x.stats.learned = 1;
+        }
+        return rc;
+    };
+    bool learned = false;
+    if (unlimited && want_learned && !is_auto) {
+        const int rc = train();
         if (rc != TJ_OK && rc != TJ_E_WORKSPACE) return rc;
         learned = rc == TJ_OK;
     }
@@ -1719,13 +1770,16 @@ static int join_impl(int key_type, const void* r_keys, const int32_t* r_rids, ui
     uint64_t total = 0;
     if (unlimited) {
         x.stats.key_ranges = 1;
-        if (learned) {
-            x.bkt.b[0] = (uint16_t*)x.bufs.key[BUF_B][0];
-            x.bkt.b[1] = (uint16_t*)x.bufs.key[BUF_B][1];
-            x.learned_pass = true;
-            x.stats.learned = 1;
+        x.auto_probe = want_learned && is_auto;
+        int rc = learned ? x.process_range(0, ~0ull, n_r, n_s, false, 0) : x.process_range(lo, hi, n_r, n_s, false, 0);
+        if (rc == TJ_SWITCH_LEARNED) {
+            const int tr = train();
+            if (tr != TJ_OK && tr != TJ_E_WORKSPACE) return tr;
+            x.auto_probe = false;
+            rc = tr == TJ_OK ? x.process_range(0, ~0ull, n_r, n_s, false, 0)
+                             : x.process_range(lo, hi, n_r, n_s, false, 0);
         }
-        TJ_RET(x.process_range(lo, hi, n_r, n_s, false, 0));
+        TJ_RET(rc);
         TJ_RET(x.finish_join(&total, 0, out_r, out_s, capacity, mat));
     } else {
         // Ranges in key order; each range is counted, then written at the

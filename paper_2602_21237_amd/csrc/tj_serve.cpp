@@ -271,7 +271,8 @@ int tj_server_submit(tj_server_t* s, const tj_request_t* req, uint64_t* ticket)
     if (!s || !req || !ticket) return TJ_E_ARG;
     const tj_request_t& r = *req;
     if (r.key_type != TJ_KEY_I32 && r.key_type != TJ_KEY_I64) return TJ_E_ARG;
-    if (r.partitioner != TJ_PART_RADIX && r.partitioner != TJ_PART_LEARNED) return TJ_E_ARG;
+    if (r.partitioner != TJ_PART_RADIX && r.partitioner != TJ_PART_LEARNED && r.partitioner != TJ_PART_AUTO)
+        return TJ_E_ARG;
     if (r.n_r > kMaxRows || r.n_s > kMaxRows) return TJ_E_TOO_LARGE;
     const uint64_t kb = (uint64_t)r.key_type;
     auto overlap = [](const void* a, uint64_t an, const void* b, uint64_t bn) {

@@ -41,8 +41,8 @@ class Stats(ctypes.Structure):
 
 
 RMI_SEGMENTS, RMI_LEAVES = 256, 1024
-TJ_PART_RADIX, TJ_PART_LEARNED = 0, 1
-_PARTITIONERS = {"radix": TJ_PART_RADIX, "learned": TJ_PART_LEARNED}
+TJ_PART_RADIX, TJ_PART_LEARNED, TJ_PART_AUTO = 0, 1, 2
+_PARTITIONERS = {"radix": TJ_PART_RADIX, "learned": TJ_PART_LEARNED, "auto": TJ_PART_AUTO}
 
 
 class RmiModel(ctypes.Structure):

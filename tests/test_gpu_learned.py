@@ -169,3 +169,31 @@ def test_learned_equals_radix_large(tj, name):
     c1 = tj.join_count(rk, sk)
     c2, st = tj.join_count(rk, sk, stats=True, partitioner="learned")
     assert c1 == c2 and st["learned"] == 1
+
+
+@pytest.mark.parametrize("name,expect", [("lognormal", 1), ("seqgap", 0)])
+def test_auto_partitioner_decides_from_the_histogram(tj, name, expect):
+    """Auto: lognormal keys crowd the radix digit's buckets, so the call hands
+    over to the learned pass; gapped sequential keys spread evenly, so it stays
+    radix. Results equal the radix path's either way."""
+    w = tjgen.learned(name, 1 << 24)
+    rk, sk, rid = dev(w["r_keys"]), dev(w["s_keys"]), dev(w["r_rids"])
+    k1, r1 = tj.sort(rk, rid)
+    k2, r2, st = tj.sort(rk, rid, stats=True, partitioner="auto")
+    assert st["learned"] == expect, st
+    assert torch.equal(k1, k2) and torch.equal(r1, r2)
+    c, st = tj.join_count(rk, sk, stats=True, partitioner="auto")
+    assert st["learned"] == expect and c == tj.join_count(rk, sk)
+
+
+@pytest.mark.parametrize("name", list(tjgen.LEARNED_DISTS))
+def test_auto_partitioner_matches_oracle(tj, name):
+    w = tjgen.learned(name, 300_001)
+    rr = tjgen.perm_i32(300_001, 3)
+    exp_r, exp_s, cnt = oracle.join_pairs(w["r_keys"], rr, w["s_keys"], w["s_rids"])
+    pr, ps = tj.join(dev(w["r_keys"]), dev(rr), dev(w["s_keys"]), dev(w["s_rids"]), capacity=cnt,
+                     partitioner="auto", learned_min_rows=1)
+    assert np.array_equal(host(pr), exp_r) and np.array_equal(host(ps), exp_s)
+    ek, er = oracle.sort(w["r_keys"], rr)
+    ko, ro = tj.sort(dev(w["r_keys"]), dev(rr), partitioner="auto", learned_min_rows=1)
+    assert np.array_equal(host(ko), ek) and np.array_equal(host(ro), er)

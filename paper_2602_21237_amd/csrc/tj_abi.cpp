@@ -92,7 +92,6 @@ uint64_t table_bytes(const Caps& c)
     b += align_up((uint64_t)c.groups * 4, ALIGN);                     // leaves per segment
     const uint64_t ub = sizeof(CrossDesc) > sizeof(CopyDesc) ? sizeof(CrossDesc) : sizeof(CopyDesc);
     b += align_up((uint64_t)c.units * ub, ALIGN);
-    b += align_up(sizeof(tj_rmi_t), ALIGN);                           // learned model
     return b;
 }
 
@@ -185,6 +184,10 @@ uint64_t rmi_scratch_bytes(int kb, uint64_t M, bool full)
            align_up((TJ_RMI_LEAVES + 1) * 4, ALIGN) + sort_ws;
 }
 
+// Buffer B during a learned call: [model][per-row buckets of R][of S] for the
+// learned pass, the training scratch after the model before it.
+uint64_t rmi_model_bytes() { return align_up(sizeof(tj_rmi_t), ALIGN); }
+
 // Data bytes of the unlimited plan: the ping-pong buffers, and at least room
 // in buffer B (free until the second pass) to train the learned partitioner
 // at its default sample rate.
@@ -197,7 +200,11 @@ uint64_t full_data_bytes(const Shape& s)
         b_off = buffer_data_bytes(a);
     }
     const uint64_t M = rmi_sample_rows(s.n_r, 10) + (s.join ? rmi_sample_rows(s.n_s, 10) : 0);
-    return std::max(buffers, b_off + rmi_scratch_bytes(s.kb, M, false));
+    const uint64_t n = s.n_r + (s.join ? s.n_s : 0);
+    const uint64_t need = rmi_model_bytes() + std::max(rmi_scratch_bytes(s.kb, M, false),
+                                                       align_up(s.n_r * 2, ALIGN) + align_up(s.n_s * 2, ALIGN));
+    (void)n;
+    return std::max(buffers, b_off + need);
 }
 
 // ---------------------------------------------------------------------------
@@ -446,7 +453,6 @@ struct Exec {
         d_segcount = (uint32_t*)take((uint64_t)caps.groups * 4);
         const uint64_t ub = sizeof(CrossDesc) > sizeof(CopyDesc) ? sizeof(CrossDesc) : sizeof(CopyDesc);
         d_units = take((uint64_t)caps.units * ub);
-        d_model = (tj_rmi_t*)take(sizeof(tj_rmi_t));
         return p <= end ? TJ_OK : TJ_E_WORKSPACE;
     }
 
@@ -1625,9 +1631,11 @@ static int sort_impl(int key_type, const void* keys_in, const int32_t* rids_in, 
     // scratch, then the learned pass's bucket ids
     auto train = [&]() -> int {
         char* b0 = (char*)x.bufs.key[BUF_B][0];
-        const int rc = x.train_rmi(keys_in, n, nullptr, 0, permille, b0, (uint64_t)(end - b0));
+        x.d_model = (tj_rmi_t*)b0;
+        char* s0 = b0 + rmi_model_bytes();
+        const int rc = x.train_rmi(keys_in, n, nullptr, 0, permille, s0, (uint64_t)(end - s0));
         if (rc == TJ_OK) {
-            x.bkt.b[0] = (uint16_t*)b0;
+            x.bkt.b[0] = (uint16_t*)s0;
             x.learned_pass = true;
             x.stats.learned = 1;
         }
@@ -1750,10 +1758,12 @@ static int join_impl(int key_type, const void* r_keys, const int32_t* r_rids, ui
     // buffer B is free until the second pass (see tj_sort)
     auto train = [&]() -> int {
         char* b0 = (char*)x.bufs.key[BUF_B][0];
-        const int rc = x.train_rmi(r_keys, n_r, s_keys, n_s, permille, b0, (uint64_t)(end - b0));
+        x.d_model = (tj_rmi_t*)b0;
+        char* s0 = b0 + rmi_model_bytes();
+        const int rc = x.train_rmi(r_keys, n_r, s_keys, n_s, permille, s0, (uint64_t)(end - s0));
         if (rc == TJ_OK) {
-            x.bkt.b[0] = (uint16_t*)x.bufs.key[BUF_B][0];
-            x.bkt.b[1] = (uint16_t*)x.bufs.key[BUF_B][1];
+            x.bkt.b[0] = (uint16_t*)s0;
+            x.bkt.b[1] = (uint16_t*)(s0 + align_up(n_r * 2, ALIGN));
             x.learned_pass = true;
             x.stats.learned = 1;
         }

@@ -289,9 +289,9 @@ int tj_multi_workspace_query(int op, int ncols, const int* key_types, uint64_t n
     return TJ_OK;
 }
 
-int tj_sort_multi(int ncols, const int* key_types, const void* const* keys_in, const int32_t* rids_in, uint64_t n,
-                  void* const* keys_out, int32_t* rids_out, void* workspace, uint64_t workspace_bytes, void* stream,
-                  tj_stats_t* stats)
+static int sort_multi_body(int ncols, const int* key_types, const void* const* keys_in, const int32_t* rids_in,
+                           uint64_t n, void* const* keys_out, int32_t* rids_out, void* workspace,
+                           uint64_t workspace_bytes, void* stream, tj_stats_t* stats)
 {
     MK_RET(check_cols(ncols, key_types));
     if (n > kMaxRows) return TJ_E_TOO_LARGE;
@@ -345,12 +345,28 @@ int tj_sort_multi(int ncols, const int* key_types, const void* const* keys_in, c
     return TJ_OK;
 }
 
+int tj_sort_multi(int ncols, const int* key_types, const void* const* keys_in, const int32_t* rids_in, uint64_t n,
+                  void* const* keys_out, int32_t* rids_out, void* workspace, uint64_t workspace_bytes, void* stream,
+                  tj_stats_t* stats)
+{
+    try {  // host-side containers may throw; nothing crosses the C ABI
+        return sort_multi_body(ncols, key_types, keys_in, rids_in, n, keys_out, rids_out, workspace, workspace_bytes,
+                               stream, stats);
+    } catch (...) {
+        return TJ_E_INTERNAL;
+    }
+}
+
 int tj_join_count_multi(int ncols, const int* key_types, const void* const* r_keys, uint64_t n_r,
                         const void* const* s_keys, uint64_t n_s, uint64_t* count, void* workspace,
                         uint64_t workspace_bytes, void* stream, tj_stats_t* stats)
 {
-    return join_impl(ncols, key_types, r_keys, nullptr, n_r, s_keys, nullptr, n_s, nullptr, nullptr, 0, count,
-                     workspace, workspace_bytes, stream, stats, false);
+    try {
+        return join_impl(ncols, key_types, r_keys, nullptr, n_r, s_keys, nullptr, n_s, nullptr, nullptr, 0, count,
+                         workspace, workspace_bytes, stream, stats, false);
+    } catch (...) {
+        return TJ_E_INTERNAL;
+    }
 }
 
 int tj_join_materialize_multi(int ncols, const int* key_types, const void* const* r_keys, const int32_t* r_rids,
@@ -358,8 +374,12 @@ int tj_join_materialize_multi(int ncols, const int* key_types, const void* const
                               int32_t* out_r, int32_t* out_s, uint64_t capacity, uint64_t* count, void* workspace,
                               uint64_t workspace_bytes, void* stream, tj_stats_t* stats)
 {
-    return join_impl(ncols, key_types, r_keys, r_rids, n_r, s_keys, s_rids, n_s, out_r, out_s, capacity, count,
-                     workspace, workspace_bytes, stream, stats, true);
+    try {
+        return join_impl(ncols, key_types, r_keys, r_rids, n_r, s_keys, s_rids, n_s, out_r, out_s, capacity, count,
+                         workspace, workspace_bytes, stream, stats, true);
+    } catch (...) {
+        return TJ_E_INTERNAL;
+    }
 }
 
 }  // extern "C"

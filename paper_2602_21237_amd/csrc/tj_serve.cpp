@@ -16,6 +16,7 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <new>
 #include <thread>
 #include <vector>
 
@@ -245,7 +246,8 @@ int tj_server_create(void* arena, uint64_t arena_bytes, int slots, tj_server_t**
 {
     if (!arena || !server || slots < 1 || slots > 64) return TJ_E_ARG;
     if ((uintptr_t)arena % kAlign || arena_bytes < (64ull << 10)) return TJ_E_WORKSPACE;
-    tj_server* s = new tj_server();
+    tj_server* s = new (std::nothrow) tj_server();
+    if (!s) return TJ_E_INTERNAL;
     if (hipGetDevice(&s->device) != hipSuccess) {
         delete s;
         return TJ_E_HIP;
@@ -261,7 +263,19 @@ int tj_server_create(void* arena, uint64_t arena_bytes, int slots, tj_server_t**
         }
         s->streams.push_back(st);
     }
-    for (int i = 0; i < slots; i++) s->workers.emplace_back([s, i] { s->worker(i); });
+    try {
+        for (int i = 0; i < slots; i++) s->workers.emplace_back([s, i] { s->worker(i); });
+    } catch (...) {  // no thread could be started: stop the ones that were
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->stopping = true;
+        }
+        s->cv_work.notify_all();
+        for (std::thread& t : s->workers) t.join();
+        for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+        delete s;
+        return TJ_E_INTERNAL;
+    }
     *server = s;
     return TJ_OK;
 }
@@ -309,7 +323,8 @@ int tj_server_submit(tj_server_t* s, const tj_request_t* req, uint64_t* ticket)
         }
         if (overlap(outs[0], osz[0], outs[1], osz[1])) return TJ_E_ALIAS;
     }
-    Job* j = new Job();
+    Job* j = new (std::nothrow) Job();
+    if (!j) return TJ_E_INTERNAL;
     j->req = r;
     j->phase = r.op == TJ_OP_JOIN_MATERIALIZE ? 1 : 0;
     j->submitted = Clock::now();

@@ -49,6 +49,9 @@ constexpr uint32_t DEFAULT_PERMILLE = 10;        // 1% sample per relation
 constexpr uint64_t DEFAULT_LEARNED_MIN_ROWS = 1ull << 22;
 constexpr uint64_t AUTO_HEAVY = 8;               // a radix bucket over 8x the mean counts as heavy
 constexpr int TJ_SWITCH_LEARNED = 100;           // internal: the auto partitioner hands over
+constexpr int TJ_RANGE_MISS = 101;               // internal: a row fell outside the sampled range
+constexpr uint64_t SAMPLED_PROBE_MIN_ROWS = 1ull << 22;  // rows from which the range is sampled
+constexpr uint64_t SAMPLED_PROBE_STEP = 4096;            // every 4096th key
 static_assert((LEARNED_BUCKETS & (LEARNED_BUCKETS - 1)) == 0 && LEARNED_BUCKETS <= (uint32_t)NB,
               "learned buckets must be one digit of the scatter");
 
@@ -164,6 +167,26 @@ uint64_t min_data_bytes(const Shape& s)
 }
 
 const uint64_t kMaxRows = (1ull << 31) - 1;
+
+// Digit of a pass over a segment of `rows` rows whose ordinals span `span`:
+// enough digits that a child averages LEAF_CAP / 2 rows (at least 2, at most a
+// full digit), at the largest shift at which (span >> shift) + 1 digits still
+// reach that many, so a span that is not a power of two still puts them to
+// use. A span of 0 (filtered roots of a single-key range, which still need a
+// compaction pass) gets one bit.
+inline void plan_digit(uint64_t span, uint64_t rows, uint32_t& shift, uint32_t& bits)
+{
+    const uint64_t want = std::min<uint64_t>(std::max<uint64_t>((rows + LEAF_CAP / 2 - 1) / (LEAF_CAP / 2), 2),
+                                             1ull << PASS_DIGIT_BITS);
+    shift = 0;
+    for (uint32_t sh = nbits64(span); sh-- > 0;)
+        if ((span >> sh) + 1 >= want) {
+            shift = sh;
+            break;
+        }
+    while ((span >> shift) >= (1ull << PASS_DIGIT_BITS)) shift++;
+    bits = std::max<uint32_t>(1, nbits64(span >> shift));
+}
 
 // Sample rows of a relation of n rows: max(min(n, 2048), n * permille / 1000).
 inline uint64_t rmi_sample_rows(uint64_t n, uint32_t permille)
@@ -347,6 +370,7 @@ struct Exec {
     BktSet bkt{};                   // per-row buckets of the learned pass
     bool learned_pass = false;      // the next partition pass is the learned one
     bool auto_probe = false;        // the next pass may hand over to the learned partitioner
+    bool spec_range = false;        // the next pass's digit range comes from a sampled probe
 
     // data buffer capacities (rows per side) when the buffers live in the workspace
     uint64_t cap_r = 0, cap_s = 0;
@@ -468,6 +492,8 @@ struct Exec {
         // the learned pass partitions the root segment(s) of an unfiltered range once
         const bool learned = learned_pass && !filter;
         learned_pass = false;
+        const bool spec = spec_range && !filter && !learned;
+        spec_range = false;
         // per segment digit choice
         struct Plan {
             uint32_t shift, bits, kb_out;
@@ -476,23 +502,7 @@ struct Exec {
         uint64_t total_rows = 0;
         for (size_t i = 0; i < segs.size(); i++) {
             const Seg& s = segs[i];
-            const uint64_t rows = s.rn + s.sn;
-            const uint64_t span = s.hi - s.lo;
-            // digits wanted: children of LEAF_CAP / 2 rows on average (at least 2, at most a full digit)
-            const uint64_t want = std::min<uint64_t>(std::max<uint64_t>((rows + LEAF_CAP / 2 - 1) / (LEAF_CAP / 2), 2),
-                                                     1ull << PASS_DIGIT_BITS);
-            // the largest shift at which (span >> shift) + 1 digits still reach `want`, so a
-            // span that is not a power of two still puts `want` digits in use
-            uint32_t shift = 0;
-            for (uint32_t sh = nbits64(span); sh-- > 0;)
-                if ((span >> sh) + 1 >= want) {
-                    shift = sh;
-                    break;
-                }
-            while ((span >> shift) >= (1ull << PASS_DIGIT_BITS)) shift++;
-            // filtered roots of a single-key range (span 0) still need a compaction pass: one bit
-            plan[i].bits = std::max<uint32_t>(1, nbits64(span >> shift));
-            plan[i].shift = shift;
+            plan_digit(s.hi - s.lo, s.rn + s.sn, plan[i].shift, plan[i].bits);
             // join keys are narrowed to 4 bytes once every child spans at most
             // 2^32 ordinals; the sort writes its keys out and never narrows
             plan[i].kb_out = sh.join && write_keys && s.kb == 8 && plan[i].shift <= 32 ? 4u : s.kb;
@@ -502,7 +512,7 @@ struct Exec {
                 plan[i].shift = 0;
                 plan[i].kb_out = s.kb;
             }
-            total_rows += filter ? (uint64_t)(i == 0 ? sh.n_r + sh.n_s : 0) : rows;
+            total_rows += filter ? (uint64_t)(i == 0 ? sh.n_r + sh.n_s : 0) : s.rn + s.sn;
         }
         // Device batching pays where the children are expected to be leaves and
         // are many: one wave walks each segment's children in turn (~0.1 ms),
@@ -583,6 +593,7 @@ struct Exec {
                     g.child0 = child;
                     child += 1u << g.bits;
                     g.flags = (g_debug_flags.load() & TJ_DEBUG_FORCE_REORDER) ? GROUP_FORCE_REORDER : 0u;
+                    if (spec) g.flags |= GROUP_CHECK_RANGE;
                     g.src_koff = filter ? 0 : (side ? s.koff_s : s.koff_r);
                     g.dst_koff = plan[si].kb_out < kb_in ? g.dst_start : g.src_koff;
                     const uint32_t gi = (uint32_t)groups.size();
@@ -643,9 +654,23 @@ struct Exec {
                 stats.bytes_written += scanned * 2;
                 stats.bytes_read += scanned * 2;
             } else {
+                uint32_t* miss = (uint32_t*)(d_probe + 7);
+                if (spec) TJ_CK(launch_fill_u64(d_probe + 7, 1, 0, st));
                 TJ_CK(timed(F_HIST, scanned * kb_in, [&] {
-                    return launch_hist((int)kb_in, d_chunks, nc, d_groups, bufs, d_hist, d_gmin, d_gmax, st);
+                    return launch_hist((int)kb_in, d_chunks, nc, d_groups, bufs, d_hist, d_gmin, d_gmax, miss, st);
                 }));
+                if (spec) {
+                    // a row outside the sampled digit range: nothing moved yet, the
+                    // caller probes the exact range and starts again
+                    uint64_t* flag = (uint64_t*)pinned_down(sizeof(uint64_t));
+                    if (!flag) return TJ_E_HIP;
+                    TJ_CK(hipMemcpyAsync(flag, d_probe + 7, 8, hipMemcpyDeviceToHost, st));
+                    TJ_CK(hipStreamSynchronize(st));
+                    if (*flag) {
+                        stats.passes--;
+                        return TJ_RANGE_MISS;
+                    }
+                }
             }
             TJ_CK(timed(F_SCAN, 0, [&] {
                 return launch_scan(d_cblocks, ncb, d_groups, ng, d_hist, d_cbsum, d_ccount, d_cstart, st);
@@ -1325,7 +1350,7 @@ struct Exec {
         TJ_CK(hipMemcpyAsync(d_chunks, chunks.data(), nc * sizeof(ChunkDesc), hipMemcpyHostToDevice, st));
         TJ_CK(launch_fill_u64(d_gmin, child, ~0ull, st));
         TJ_CK(launch_fill_u64(d_gmax, child, 0ull, st));
-        TJ_CK(launch_hist(sh.kb, d_chunks, nc, d_groups, bufs, d_hist, d_gmin, d_gmax, st));
+        TJ_CK(launch_hist(sh.kb, d_chunks, nc, d_groups, bufs, d_hist, d_gmin, d_gmax, nullptr, st));
         std::vector<uint32_t> h((size_t)nc * NB);
         TJ_CK(hipMemcpyAsync(h.data(), d_hist, h.size() * 4, hipMemcpyDeviceToHost, st));
         TJ_CK(hipStreamSynchronize(st));
@@ -1490,6 +1515,34 @@ int probe(Exec& x, const void* a, uint64_t na, const void* b, uint64_t nb, uint6
     return TJ_OK;
 }
 
+// Digit range of a first pass from every SAMPLED_PROBE_STEP-th key instead of
+// all of them: the sample's minimum is rounded down to a whole digit, so rows
+// a little beyond the sample's extremes still take correct digits; the first
+// histogram checks every row against the range (GROUP_CHECK_RANGE).
+int sampled_range(Exec& x, const void* a, uint64_t na, const void* b, uint64_t nb, uint64_t& lo, uint64_t& hi)
+{
+    uint64_t mm[2];
+    const uint64_t sampled = (na + SAMPLED_PROBE_STEP - 1) / SAMPLED_PROBE_STEP +
+                             (nb + SAMPLED_PROBE_STEP - 1) / SAMPLED_PROBE_STEP;
+    TJ_CK(x.timed(F_PROBE, sampled * (uint64_t)x.sh.kb, [&] {
+        return launch_probe_step(x.sh.kb, a, na, b, nb, SAMPLED_PROBE_STEP, x.d_probe, x.st);
+    }));
+    TJ_CK(hipMemcpyAsync(mm, x.d_probe, 16, hipMemcpyDeviceToHost, x.st));
+    TJ_CK(hipStreamSynchronize(x.st));
+    x.stats.bytes_read += sampled * (uint64_t)x.sh.kb;
+    hi = mm[1];
+    lo = mm[0];
+    // the digit width depends on the span, which depends on the rounded minimum
+    for (int it = 0; it < 3; it++) {
+        uint32_t shift, bits;
+        plan_digit(hi - lo, na + nb, shift, bits);
+        const uint64_t aligned = shift >= 64 ? 0 : (mm[0] & ~((1ull << shift) - 1));
+        if (aligned == lo) break;
+        lo = aligned;
+    }
+    return TJ_OK;
+}
+
 }  // namespace
 }  // namespace tj
 
@@ -1648,11 +1701,25 @@ static int sort_impl(int key_type, const void* keys_in, const int32_t* rids_in, 
         learned = rc == TJ_OK;
     }
     uint64_t lo = 0, hi = ~0ull;
-    if (!learned) TJ_RET(probe(x, keys_in, n, nullptr, 0, lo, hi));
+    bool spec = false;
+    if (!learned) {
+        // large unlimited calls take their first digit range from a sample (a
+        // sampled span of 0 could hide other keys: probe those exactly)
+        if (unlimited && n >= SAMPLED_PROBE_MIN_ROWS) {
+            TJ_RET(sampled_range(x, keys_in, n, nullptr, 0, lo, hi));
+            spec = hi > lo;
+        }
+        if (!spec) TJ_RET(probe(x, keys_in, n, nullptr, 0, lo, hi));
+    }
     if (unlimited) {
         x.stats.key_ranges = 1;
         x.auto_probe = want_learned && is_auto;
+        x.spec_range = spec;
         int rc = learned ? x.process_range(0, ~0ull, n, 0, false, 0) : x.process_range(lo, hi, n, 0, false, 0);
+        if (rc == TJ_RANGE_MISS) {
+            TJ_RET(probe(x, keys_in, n, nullptr, 0, lo, hi));
+            rc = x.process_range(lo, hi, n, 0, false, 0);
+        }
         if (rc == TJ_SWITCH_LEARNED) {
             const int tr = train();
             if (tr != TJ_OK && tr != TJ_E_WORKSPACE) return tr;
@@ -1776,12 +1843,24 @@ static int join_impl(int key_type, const void* r_keys, const int32_t* r_rids, ui
         learned = rc == TJ_OK;
     }
     uint64_t lo = 0, hi = ~0ull;
-    if (!learned) TJ_RET(probe(x, r_keys, n_r, s_keys, n_s, lo, hi));
+    bool spec = false;
+    if (!learned) {
+        if (unlimited && n_r + n_s >= SAMPLED_PROBE_MIN_ROWS) {  // as in tj_sort
+            TJ_RET(sampled_range(x, r_keys, n_r, s_keys, n_s, lo, hi));
+            spec = hi > lo;
+        }
+        if (!spec) TJ_RET(probe(x, r_keys, n_r, s_keys, n_s, lo, hi));
+    }
     uint64_t total = 0;
     if (unlimited) {
         x.stats.key_ranges = 1;
         x.auto_probe = want_learned && is_auto;
+        x.spec_range = spec;
         int rc = learned ? x.process_range(0, ~0ull, n_r, n_s, false, 0) : x.process_range(lo, hi, n_r, n_s, false, 0);
+        if (rc == TJ_RANGE_MISS) {
+            TJ_RET(probe(x, r_keys, n_r, s_keys, n_s, lo, hi));
+            rc = x.process_range(lo, hi, n_r, n_s, false, 0);
+        }
         if (rc == TJ_SWITCH_LEARNED) {
             const int tr = train();
             if (tr != TJ_OK && tr != TJ_E_WORKSPACE) return tr;
@@ -1977,7 +2056,7 @@ int tj_debug_partition_pass(const int64_t* keys, const int32_t* rids, uint64_t n
     TJ_CK(hipMemcpyAsync(x.d_cblocks, cbs.data(), cbs.size() * sizeof(CBlockDesc), hipMemcpyHostToDevice, st));
     TJ_CK(launch_fill_u64(x.d_gmin, 1u << bits, ~0ull, st));
     TJ_CK(launch_fill_u64(x.d_gmax, 1u << bits, 0ull, st));
-    TJ_CK(launch_hist(8, x.d_chunks, g.nchunks, x.d_groups, x.bufs, x.d_hist, x.d_gmin, x.d_gmax, st));
+    TJ_CK(launch_hist(8, x.d_chunks, g.nchunks, x.d_groups, x.bufs, x.d_hist, x.d_gmin, x.d_gmax, nullptr, st));
     TJ_CK(launch_scan(x.d_cblocks, g.ncblocks, x.d_groups, 1, x.d_hist, x.d_cbsum, x.d_ccount, x.d_cstart, st));
     TJ_CK(launch_scatter(8, 8, true, true, x.d_chunks, g.nchunks, x.d_groups, x.d_hist, x.d_cbsum, x.d_cstart, x.bufs, st));
     TJ_CK(hipMemcpyAsync(counts_out, x.d_ccount, (1u << bits) * 4ull, hipMemcpyDeviceToDevice, st));

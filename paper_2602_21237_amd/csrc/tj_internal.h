@@ -48,6 +48,9 @@ constexpr uint32_t GROUP_FORCE_REORDER = 1u;
 // GroupDesc::flags: in a launch that narrows keys to 4 bytes, this group keeps
 // its 8-byte keys (its children still span more than 2^32 ordinals).
 constexpr uint32_t GROUP_WIDE = 2u;
+// GroupDesc::flags: the group's digit range comes from a sampled probe; the
+// histogram flags any row outside [base, base + (nbins << shift)).
+constexpr uint32_t GROUP_CHECK_RANGE = 4u;
 
 struct GroupDesc {
     uint64_t start;      // first row scanned in the source array
@@ -156,9 +159,13 @@ constexpr int LEAF_CAP = 8192;
 hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t st);
 hipError_t launch_probe(int key_bytes, const void* a, uint64_t na, const void* b, uint64_t nb,
                         uint64_t* minmax, hipStream_t st);
+// Min and max ordinal of every step-th element of a and of b (step 1: all).
+hipError_t launch_probe_step(int key_bytes, const void* a, uint64_t na, const void* b, uint64_t nb,
+                             uint64_t step, uint64_t* minmax, hipStream_t st);
+// range_miss: set to nonzero when a GROUP_CHECK_RANGE group has a row outside its digit range.
 hipError_t launch_hist(int key_bytes, const ChunkDesc* chunks, uint32_t nchunks,
                        const GroupDesc* groups, BufSet bufs, uint32_t* hist,
-                       uint64_t* gmin, uint64_t* gmax, hipStream_t st);
+                       uint64_t* gmin, uint64_t* gmax, uint32_t* range_miss, hipStream_t st);
 // Histogram of the learned pass: the digit is the bucket of `model` (device
 // copy), and each row's bucket is also stored in bkt.b[side][row].
 hipError_t launch_learned_hist(int key_bytes, const ChunkDesc* chunks, uint32_t nchunks,

@@ -294,10 +294,11 @@ hipError_t launch_wave_scan_test(const uint32_t* in, uint32_t* out, uint64_t n, 
 // ---------------------------------------------------------------------------
 // range probe: minimum and maximum ordinal over one or two key columns
 // ---------------------------------------------------------------------------
+// step > 1: the minimum and maximum of every step-th element only (a sample).
 template <typename K>
 __global__ __launch_bounds__(256) void k_probe(const K* __restrict__ a, uint64_t na,
                                                const K* __restrict__ b, uint64_t nb,
-                                               uint64_t* __restrict__ minmax)
+                                               uint64_t* __restrict__ minmax, uint64_t step)
 {
     __shared__ uint64_t smin[4], smax[4];
     uint64_t mn = ~0ull, mx = 0;
@@ -306,10 +307,11 @@ __global__ __launch_bounds__(256) void k_probe(const K* __restrict__ a, uint64_t
     // U loads in flight per thread; a clamped index re-reads a real element,
     // which leaves the minimum and maximum unchanged.
     constexpr int U = 8;
-    for (uint64_t i0 = t0; i0 < na; i0 += stride * U) {
+    const uint64_t sa = (na + step - 1) / step, sb = (nb + step - 1) / step;  // sampled elements
+    for (uint64_t i0 = t0; i0 < sa; i0 += stride * U) {
         K v[U];
 #pragma unroll
-        for (int u = 0; u < U; u++) v[u] = ld_clamp(a, i0 + u * stride, na);
+        for (int u = 0; u < U; u++) v[u] = ld_clamp(a, (i0 + u * stride) * step, na);
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const uint64_t o = ord_of(v[u]);
@@ -317,10 +319,10 @@ __global__ __launch_bounds__(256) void k_probe(const K* __restrict__ a, uint64_t
             mx = o > mx ? o : mx;
         }
     }
-    for (uint64_t i0 = t0; i0 < nb; i0 += stride * U) {
+    for (uint64_t i0 = t0; i0 < sb; i0 += stride * U) {
         K v[U];
 #pragma unroll
-        for (int u = 0; u < U; u++) v[u] = ld_clamp(b, i0 + u * stride, nb);
+        for (int u = 0; u < U; u++) v[u] = ld_clamp(b, (i0 + u * stride) * step, nb);
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const uint64_t o = ord_of(v[u]);
@@ -345,24 +347,31 @@ __global__ __launch_bounds__(256) void k_probe(const K* __restrict__ a, uint64_t
     }
 }
 
-hipError_t launch_probe(int key_bytes, const void* a, uint64_t na, const void* b, uint64_t nb,
-                        uint64_t* minmax, hipStream_t st)
+hipError_t launch_probe_step(int key_bytes, const void* a, uint64_t na, const void* b, uint64_t nb,
+                             uint64_t step, uint64_t* minmax, hipStream_t st)
 {
     hipError_t e = launch_fill_u64(minmax, 1, ~0ull, st);
     if (e != hipSuccess) return e;
     e = launch_fill_u64(minmax + 1, 1, 0ull, st);
     if (e != hipSuccess) return e;
-    const uint64_t n = na > nb ? na : nb;
+    if (step < 1) step = 1;
+    const uint64_t n = ((na > nb ? na : nb) + step - 1) / step;
     uint64_t blocks = (n + 256 * 16 - 1) / (256 * 16);
     if (blocks < 1) blocks = 1;
     if (blocks > 8192) blocks = 8192;
     if (key_bytes == 4)
         hipLaunchKernelGGL(k_probe<int32_t>, dim3((uint32_t)blocks), dim3(256), 0, st,
-                           (const int32_t*)a, na, (const int32_t*)b, nb, minmax);
+                           (const int32_t*)a, na, (const int32_t*)b, nb, minmax, step);
     else
         hipLaunchKernelGGL(k_probe<int64_t>, dim3((uint32_t)blocks), dim3(256), 0, st,
-                           (const int64_t*)a, na, (const int64_t*)b, nb, minmax);
+                           (const int64_t*)a, na, (const int64_t*)b, nb, minmax, step);
     return hipGetLastError();
+}
+
+hipError_t launch_probe(int key_bytes, const void* a, uint64_t na, const void* b, uint64_t nb,
+                        uint64_t* minmax, hipStream_t st)
+{
+    return launch_probe_step(key_bytes, a, na, b, nb, 1, minmax, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -380,7 +389,8 @@ __global__ __launch_bounds__(NT) void k_hist(const ChunkDesc* __restrict__ chunk
                                                        BufSet bufs, uint32_t* __restrict__ hist,
                                                        uint64_t* __restrict__ gmin,
                                                        uint64_t* __restrict__ gmax,
-                                                       const tj_rmi_t* __restrict__ model, BktSet bkt)
+                                                       const tj_rmi_t* __restrict__ model, BktSet bkt,
+                                                       uint32_t* __restrict__ range_miss)
 {
     __shared__ uint32_t cnt[NB];
     __shared__ uint64_t mn[NB], mx[NB];
@@ -398,6 +408,11 @@ __global__ __launch_bounds__(NT) void k_hist(const ChunkDesc* __restrict__ chunk
     }
     if (LEARNED) rmi_to_lds<NT>((tj_rmi_t*)lm_raw, model);
     lds_barrier();
+    // GROUP_CHECK_RANGE: the digit range came from a sample; a row outside
+    // [base, base + nbins << shift) would take a wrong digit, so it is flagged
+    // (the planner then probes the exact range and repeats the pass).
+    const bool check = !LEARNED && (g.flags & GROUP_CHECK_RANGE) != 0;
+    bool miss = false;
     // Rows are counted with LDS atomics. When every valid row of a wave's round
     // falls in one bin (skewed inputs: buckets dominated by one key), the wave
     // reduces them first and one lane updates the bin.
@@ -431,6 +446,7 @@ __global__ __launch_bounds__(NT) void k_hist(const ChunkDesc* __restrict__ chunk
             uint32_t d;
             if (LEARNED) d = valid ? lb[LEARNED ? u : 0] : 0u;
             else d = valid ? (uint32_t)((o - g.base) >> g.shift) & (nbins - 1u) : 0u;
+            if (check) miss = miss || (valid && (o < g.base || ((o - g.base) >> g.shift) >= nbins));
             const uint64_t vm = ballot(valid);
             if (vm == 0) continue;
             const int first = __ffsll((unsigned long long)vm) - 1;
@@ -455,6 +471,7 @@ __global__ __launch_bounds__(NT) void k_hist(const ChunkDesc* __restrict__ chunk
             }
         }
     }
+    if (check && ballot(miss) && (threadIdx.x & 63) == 0) atomicOr(range_miss, 1u);
     lds_barrier();
     for (uint32_t d = threadIdx.x; d < nbins; d += NT) {
         hist[(uint64_t)blockIdx.x * NB + d] = cnt[d];
@@ -467,16 +484,16 @@ __global__ __launch_bounds__(NT) void k_hist(const ChunkDesc* __restrict__ chunk
 
 hipError_t launch_hist(int key_bytes, const ChunkDesc* chunks, uint32_t nchunks,
                        const GroupDesc* groups, BufSet bufs, uint32_t* hist, uint64_t* gmin,
-                       uint64_t* gmax, hipStream_t st)
+                       uint64_t* gmax, uint32_t* range_miss, hipStream_t st)
 {
     if (nchunks == 0) return hipSuccess;
     const BktSet none{};
     if (key_bytes == 4)
         hipLaunchKernelGGL((k_hist<int32_t, false>), dim3(nchunks), dim3(PART_THREADS), 0, st, chunks, groups,
-                           bufs, hist, gmin, gmax, nullptr, none);
+                           bufs, hist, gmin, gmax, nullptr, none, range_miss);
     else
         hipLaunchKernelGGL((k_hist<int64_t, false>), dim3(nchunks), dim3(PART_THREADS), 0, st, chunks, groups,
-                           bufs, hist, gmin, gmax, nullptr, none);
+                           bufs, hist, gmin, gmax, nullptr, none, range_miss);
     return hipGetLastError();
 }
 
@@ -490,11 +507,11 @@ hipError_t launch_learned_hist(int key_bytes, const ChunkDesc* chunks, uint32_t 
     if (key_bytes == 4)
         hipLaunchKernelGGL((k_hist<int32_t, true, LEARNED_HIST_THREADS>), dim3(nchunks), dim3(LEARNED_HIST_THREADS), 0, st,
                            chunks, groups,
-                           bufs, hist, gmin, gmax, model, bkt);
+                           bufs, hist, gmin, gmax, model, bkt, nullptr);
     else
         hipLaunchKernelGGL((k_hist<int64_t, true, LEARNED_HIST_THREADS>), dim3(nchunks), dim3(LEARNED_HIST_THREADS), 0, st,
                            chunks, groups,
-                           bufs, hist, gmin, gmax, model, bkt);
+                           bufs, hist, gmin, gmax, model, bkt, nullptr);
     return hipGetLastError();
 }
 

@@ -341,3 +341,28 @@ def test_forced_reranking_paths(tj):
         check_sort(tj, k, rng.permutation(k.size).astype(np.int32))
     finally:
         tj.tj.debug_set_flags(0)
+
+
+@pytest.mark.parametrize("where", ["high", "low", "both"])
+def test_sampled_range_miss(tj, where):
+    """Large calls take their first digit range from every 4096th key. An
+    outlier at an unsampled position falls outside it: the first histogram
+    flags it and the call probes the exact range; results stay exact."""
+    n = (1 << 22) + 3
+    rng = np.random.default_rng(17)
+    keys = rng.integers(0, 1 << 30, n).astype(np.int64)
+    if where in ("high", "both"):
+        keys[4097] = 1 << 50
+    if where in ("low", "both"):
+        keys[8191] = -(1 << 45)
+    rids = tjgen.perm_i32(n, 9)
+    check_sort(tj, keys, rids)
+    s_keys = rng.integers(0, 1 << 30, n // 2).astype(np.int64)
+    s_keys[1] = keys[4097]
+    s_keys[2] = keys[8191]
+    s_rids = tjgen.iota_i32(n // 2)
+    cnt = oracle.join_count(keys, s_keys)
+    assert tj.join_count(dev(keys), dev(s_keys)) == cnt
+    pr, ps = tj.join(dev(keys), dev(rids), dev(s_keys), dev(s_rids), capacity=cnt)
+    er, es, _ = oracle.join_pairs(keys, rids, s_keys, s_rids)
+    assert np.array_equal(host(pr), er) and np.array_equal(host(ps), es)

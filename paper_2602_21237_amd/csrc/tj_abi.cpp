@@ -1718,12 +1718,14 @@ static int sort_impl(int key_type, const void* keys_in, const int32_t* rids_in, 
         int rc = learned ? x.process_range(0, ~0ull, n, 0, false, 0) : x.process_range(lo, hi, n, 0, false, 0);
         if (rc == TJ_RANGE_MISS) {
             TJ_RET(probe(x, keys_in, n, nullptr, 0, lo, hi));
+            spec = false;
             rc = x.process_range(lo, hi, n, 0, false, 0);
         }
         if (rc == TJ_SWITCH_LEARNED) {
             const int tr = train();
             if (tr != TJ_OK && tr != TJ_E_WORKSPACE) return tr;
             x.auto_probe = false;
+            x.spec_range = spec;  // still checked if the range is the sampled one
             rc = tr == TJ_OK ? x.process_range(0, ~0ull, n, 0, false, 0) : x.process_range(lo, hi, n, 0, false, 0);
         }
         TJ_RET(rc);
@@ -1859,12 +1861,14 @@ static int join_impl(int key_type, const void* r_keys, const int32_t* r_rids, ui
         int rc = learned ? x.process_range(0, ~0ull, n_r, n_s, false, 0) : x.process_range(lo, hi, n_r, n_s, false, 0);
         if (rc == TJ_RANGE_MISS) {
             TJ_RET(probe(x, r_keys, n_r, s_keys, n_s, lo, hi));
+            spec = false;
             rc = x.process_range(lo, hi, n_r, n_s, false, 0);
         }
         if (rc == TJ_SWITCH_LEARNED) {
             const int tr = train();
             if (tr != TJ_OK && tr != TJ_E_WORKSPACE) return tr;
             x.auto_probe = false;
+            x.spec_range = spec;  // still checked if the range is the sampled one
             rc = tr == TJ_OK ? x.process_range(0, ~0ull, n_r, n_s, false, 0)
                              : x.process_range(lo, hi, n_r, n_s, false, 0);
         }

@@ -1317,17 +1317,31 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_leaf_sort(const LeafDesc* __restr
     __shared__ uint32_t tmp[NW];
     __shared__ uint64_t tmp64[NW];
 
+    // Wide leaves (one block per CU either way) also park their row ids in
+    // LDS, loaded together with the keys: one memory latency instead of two.
+    constexpr bool PARK = sizeof(KW) == 8;
+    __shared__ int32_t lds_rid_park[PARK ? C : 1];
+
     const LeafDesc L = leaves[blockIdx.x];
     if (L.rn == 0) return;
     const K* __restrict__ src_k = (const K*)bufs.key[L.buf][0] + L.kr0;
     const int32_t* __restrict__ src_r = bufs.rid[L.buf][0] + L.r0;
     const uint32_t w = threadIdx.x / 64, l = threadIdx.x & 63;
     KW key[KI];
+    int32_t prid[PARK ? KI : 1];
 #pragma unroll
     for (int r = 0; r < KI; r++) {
         const uint32_t q = (w * KI + r) * 64 + l;
         const K v = ld_clamp(src_k, q, L.rn);
+        if (PARK) prid[PARK ? r : 0] = ld_clamp(src_r, threadIdx.x + r * NT, L.rn);
         key[r] = q < L.rn ? (KW)(ord_of(v) - L.base) : (KW)~(KW)0;
+    }
+    if (PARK) {
+#pragma unroll
+        for (int r = 0; r < KI; r++) {
+            const uint32_t q = threadIdx.x + r * NT;
+            if (q < L.rn) lds_rid_park[q] = prid[PARK ? r : 0];
+        }
     }
     uint16_t idx[KI];
 #pragma unroll
@@ -1394,15 +1408,17 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_leaf_sort(const LeafDesc* __restr
         const uint32_t q = (w * KI + r) * 64 + l;
         if (q < L.rn) out_k[L.out + q] = key_of<K>(L.base + (uint64_t)lds_key[q]);
     }
-    lds_barrier();
-    int32_t* lds_rid = (int32_t*)lds_key_raw;
+    int32_t* lds_rid = PARK ? lds_rid_park : (int32_t*)lds_key_raw;
+    if (!PARK) {
+        lds_barrier();
 #pragma unroll
-    for (int r = 0; r < KI; r++) {
-        const uint32_t q = threadIdx.x + r * NT;
-        const int32_t v = ld_clamp(src_r, q, L.rn);
-        if (q < L.rn) lds_rid[q] = v;
+        for (int r = 0; r < KI; r++) {
+            const uint32_t q = threadIdx.x + r * NT;
+            const int32_t v = ld_clamp(src_r, q, L.rn);
+            if (q < L.rn) lds_rid[q] = v;
+        }
+        lds_barrier();
     }
-    lds_barrier();
 #pragma unroll
     for (int r = 0; r < KI; r++) {
         const uint32_t q = (w * KI + r) * 64 + l;

@@ -17,7 +17,7 @@ namespace tj {
 
 constexpr int MAX_DIGIT_BITS = 9;             // widest partition digit
 constexpr int NB = 1 << MAX_DIGIT_BITS;       // digit bins per group (table stride)
-constexpr int PART_THREADS = 256;             // histogram block
+constexpr int PART_THREADS = 1024;            // histogram block
 constexpr int PART_TILE = 8192;               // rows per scatter tile (chunks are multiples)
 constexpr int CBLOCK = 32;                    // chunks per first-level scan block
 

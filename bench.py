@@ -22,6 +22,10 @@ with the radix, the learned and the auto first pass (median of 5), outputs
 equal.
 composite_keys: sort and join on two key columns, 2^26 rows per relation,
 packed into one key (60 bits) or wide (128 bits: LSD groups / dense ranks).
+path_selection: the execution-time selector (HyperLogLog sketch of the join
+and sort keys) on the step's inputs, its indicators against the exact counts,
+and the join latency of the tensor path from 2^10 to 2^22 rows per side with
+the decision taken at each size.
 serving: Poisson arrivals at 50, 200, 800 and 3200 requests/s of sorts and joins
 (per-side rows log-uniform in [10^3, 10^7]) against the serving loop with a
 32 GiB workspace budget, 8 slots against one at a time: P50/P99/P99.9 latency
@@ -432,6 +436,65 @@ def composite_keys(tj, torch, n: int, repeats: int = 3):
     return out
 
 
+def path_selection(tj, torch, d_rk, d_sk_join, d_sort, join_count: int, repeats: int = 5):
+    """tj_select_path on the step's own inputs (the join's R and S, the sort
+    column): HIP-event time of the sketch pass against its algorithmic bytes
+    (every key read once), the indicators against the exact figures, and the
+    decision; then the tensor path's join latency over a size sweep with the
+    decision the default thresholds take at each size."""
+    out = {}
+    n_r, n_s = d_rk.numel(), d_sk_join.numel()
+    ws = torch.empty(tj.select_workspace_query(max(n_r, d_sort.numel()), n_s), dtype=torch.uint8, device="cuda")
+    for name, args, nbytes in (("join", (d_rk, d_sk_join), 8 * (n_r + n_s)), ("sort", (d_sort,), 8 * d_sort.numel())):
+        ms = []
+        for i in range(repeats + 1):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            sel = tj.select_path(*args, workspace=ws)
+            b.record()
+            b.synchronize()
+            if i:
+                ms.append(a.elapsed_time(b))
+        t = pct(ms, 0.5)
+        rec = {"ms": round(t, 4), "bytes": nbytes, "GBs": round(nbytes / (t * 1e-3) / 1e9, 1),
+               "hbm_frac": round(nbytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+               "path": "tensor" if sel["path"] else "linear", "reasons": sel["reasons"],
+               "distinct_r": round(sel["distinct_r"], 1)}
+        if name == "join":
+            rec.update({"distinct_s": round(sel["distinct_s"], 1), "distinct_common": round(sel["distinct_common"], 1),
+                        "est_output": round(sel["est_output"], 1), "exact_output": join_count,
+                        "exact_distinct_r": n_r})
+        out[name] = rec
+        log("path selection %s: %.3f ms, %s" % (name, t, rec["path"]))
+    del ws
+    sweep = []
+    rng = np.random.default_rng(17)
+    for lg in range(10, 23, 2):
+        n = 1 << lg
+        r = torch.from_numpy(rng.choice(1 << 40, n, replace=False)).to("cuda")  # distinct R keys
+        s = r[torch.from_numpy(rng.integers(0, n, n)).to("cuda")]
+        rid = torch.arange(n, dtype=torch.int32, device="cuda")
+        sel_ms, join_ms = [], []
+        for i in range(6):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sel = tj.select_path(r, s)
+            t1 = time.perf_counter()
+            pr, _ = tj.join(r, rid, s, rid)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            if i:
+                sel_ms.append((t1 - t0) * 1e3)
+                join_ms.append((t2 - t1) * 1e3)
+        sweep.append({"rows_per_side": n, "select_ms": round(pct(sel_ms, 0.5), 4),
+                      "join_ms": round(pct(join_ms, 0.5), 4), "pairs": int(pr.numel()),
+                      "est_output": round(sel["est_output"], 1),
+                      "path": "tensor" if sel["path"] else "linear", "reasons": sel["reasons"]})
+    out["sweep"] = sweep
+    out["thresholds"] = {"min_rows": 1 << 16, "min_output": 1 << 18}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -448,6 +511,7 @@ def main():
     ap.add_argument("--learned-repeats", type=int, default=5)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--no-multi", action="store_true", help="skip the composite-key measurement")
+    ap.add_argument("--no-select", action="store_true", help="skip the path-selection measurement")
     ap.add_argument("--multi-rows", type=int, default=1 << 26)
     ap.add_argument("--serve-requests", type=int, default=1000, help="arrivals per rate")
     ap.add_argument("--serve-rates", default="50,200,800,3200", help="arrival rates, requests/s")
@@ -567,6 +631,8 @@ def main():
         "roofline": roofline, "kernels": kernels,
         "plan": {"sort": sts, "join": stj},
     }
+    if not args.no_select:
+        line["path_selection"] = path_selection(tj, torch, d_rk, d_skj, d_sk, int(pr.numel()))
     del ko, ro, out_r, out_s, ws_sort, ws_join, d_sk, d_sr, d_rk, d_rr, d_skj, d_srj
     torch.cuda.empty_cache()
     if not args.no_learned:

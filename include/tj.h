@@ -358,6 +358,76 @@ int tj_server_memory(tj_server_t *server, uint64_t *in_use, uint64_t *peak);
 int tj_server_destroy(tj_server_t *server);
 
 /*
+ * Execution-time path selection (Sec. III.C; evaluated in Sec. V.D).
+ *
+ * The paper keeps the optimiser's plan and decides only at execution time
+ * whether a large join or sort runs on the tensor path or on the existing
+ * CPU (linear) path, from indicators that are cheap to observe then: the
+ * input scale, the cardinality of the join attribute and the expected size
+ * of the intermediate result. tj_select_path observes them on the device
+ * columns and returns the decision; it runs neither path. The linear path is
+ * the caller's own (a DBMS's hash join or sort), so this library contains no
+ * CPU execution path.
+ *
+ * Indicators:
+ *   scale:  n_r + n_s rows (sort: n_r).
+ *   distinct_r, distinct_s, distinct_union: HyperLogLog estimates (Flajolet
+ *     et al. 2007) of the distinct keys of R, of S and of R union S, from
+ *     2^14 registers per relation (standard error about 0.8%). The hash of a
+ *     key k (int32 keys sign-extended) is the first output of a SplitMix64
+ *     generator (Steele, Lea, Flood 2014) seeded with k; register h >> 50
+ *     keeps the largest rank (leading-one position, from 1) of the low 50
+ *     bits, 51 when they are zero. With C[r] registers of rank r, Z = sum
+ *     C[r] 2^(51 - r) as an exact integer, E = alpha_m m^2 2^51 / double(Z),
+ *     alpha_m = 0.7213 / (1 + 1.079 / m); when E <= 2.5 m and C[0] > 0 the
+ *     linear-counting estimate m ln(m / C[0]) replaces it.
+ *   distinct_common: max(0, min(distinct_r, distinct_s, distinct_r +
+ *     distinct_s - distinct_union)), the join keys present on both sides.
+ *   est_output: expected |R join S| when the rows of each relation are
+ *     spread evenly over its distinct keys: distinct_common * (n_r /
+ *     distinct_r) * (n_s / distinct_s) (0 for an empty side; sort: 0). It
+ *     underestimates skewed joins, whose heavy keys carry more than the
+ *     average rows.
+ * Decision: TJ_PATH_TENSOR when scale >= min_rows (reason TJ_SEL_SCALE) or,
+ * for a join, est_output >= min_output (TJ_SEL_OUTPUT); otherwise
+ * TJ_PATH_LINEAR. Options (may be NULL): a zero field takes its default,
+ * TJ_SELECT_DEFAULT_MIN_ROWS and TJ_SELECT_DEFAULT_MIN_OUTPUT; the paper
+ * leaves the thresholds open, so the defaults are starting points to be set
+ * from measured crossovers.
+ *
+ *   op: TJ_OP_SORT (s_keys ignored, n_s must be 0) or a join op;
+ *   r_keys[n_r], s_keys[n_s]: device key columns of key_type;
+ *   registers: NULL, or device memory of 3 * TJ_SELECT_REGISTERS bytes that
+ *     receives the R, S and union registers;
+ *   workspace: tj_select_workspace_query bytes, 256-byte aligned;
+ *   out (host): the indicators and the decision.
+ * Synchronous: returns after the result is on the host. Errors: TJ_E_ARG
+ * (NULL pointers, bad op or key type, sort with n_s != 0), TJ_E_TOO_LARGE,
+ * TJ_E_WORKSPACE, TJ_E_ALIAS (registers overlapping an input or the
+ * workspace), TJ_E_HIP.
+ */
+#define TJ_SELECT_REGISTERS 16384
+#define TJ_SELECT_DEFAULT_MIN_ROWS (1ull << 16)
+#define TJ_SELECT_DEFAULT_MIN_OUTPUT (1ull << 18)
+enum tj_path { TJ_PATH_LINEAR = 0, TJ_PATH_TENSOR = 1 };
+enum tj_select_reason { TJ_SEL_SCALE = 1, TJ_SEL_OUTPUT = 2 };
+typedef struct {
+    uint64_t min_rows;   /* scale at or above which the tensor path is taken */
+    uint64_t min_output; /* join: expected output at or above which it is taken */
+} tj_select_options_t;
+typedef struct {
+    uint64_t n_r, n_s;
+    double distinct_r, distinct_s, distinct_union, distinct_common;
+    double est_output;
+    int32_t path;     /* enum tj_path */
+    uint32_t reasons; /* TJ_SEL_* bits that chose the tensor path */
+} tj_selection_t;
+int tj_select_workspace_query(uint64_t n_r, uint64_t n_s, uint64_t *bytes);
+int tj_select_path(int op, int key_type, const void *r_keys, uint64_t n_r, const void *s_keys, uint64_t n_s,
+                   const tj_select_options_t *options, tj_selection_t *out, uint8_t *registers,
+                   void *workspace, uint64_t workspace_bytes, void *stream);
+
+/*
  * Per-kernel timing (profiling hook). tj_timing(1) clears the counters and
  * makes every later call record a HIP event pair around each kernel launch on
  * the call's stream; tj_timing(0) stops recording. tj_timing_read copies up to

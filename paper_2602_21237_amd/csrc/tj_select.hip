@@ -1,0 +1,137 @@
+// tj_select.hip - kernels of the execution-time path selection: a
+// HyperLogLog sketch of a key column (Flajolet, Fusy, Gandouet, Meunier 2007,
+// with a 64-bit hash as in Heule, Nunkesser, Hall 2013).
+//
+// A key k (int32 keys sign-extended to int64) is hashed by the output
+// function of SplitMix64 (Steele, Lea, Flood 2014) applied to the state
+// (k + gamma) mod 2^64, so the hash of k is the first output of a SplitMix64
+// generator seeded with k. With p = 14 index bits, register
+// idx = h >> 50 takes the rank of the remaining 50 bits: the position of
+// their leading one bit, counted from 1, or 51 when they are all zero.
+// Registers hold the maximum rank seen, 0 for none.
+//
+// One pass over the column: each block keeps the 16384 registers of its own
+// slice of rows in LDS (ds_max per row) and writes them to a per-block slab;
+// a merge kernel takes the maximum over the slabs (per relation, and of the
+// two relations for their union) and a one-block kernel histograms the
+// register values for the host-side estimate. No atomics reach HBM, so the
+// result does not depend on block scheduling.
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "tj_internal.h"
+#include "tj_select.h"
+
+namespace tj {
+namespace {
+
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+
+__device__ __forceinline__ uint32_t hll_code(uint64_t k)
+{
+    uint64_t z = k + kGamma;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const uint64_t w = z << HLL_P;  // the 50 rank bits, moved to the top
+    const uint32_t rank = w ? (uint32_t)__clzll((long long)w) + 1u : (uint32_t)(64 - HLL_P + 1);
+    return ((uint32_t)(z >> (64 - HLL_P)) << 8) | rank;  // index << 8 | rank
+}
+
+template <typename K>
+__device__ __forceinline__ uint64_t key_bits(K k)
+{
+    return (uint64_t)(int64_t)k;
+}
+
+// slab[blockIdx.x][j] = max rank of the rows [b0, b1) of this block at register j
+template <typename K>
+__global__ __launch_bounds__(HLL_THREADS) void k_hll_block(const K* __restrict__ keys, uint64_t n,
+                                                          uint64_t per_block, uint8_t* __restrict__ slab)
+{
+    __shared__ uint32_t reg[HLL_M];
+    for (uint32_t j = threadIdx.x; j < HLL_M; j += HLL_THREADS) reg[j] = 0;
+    __syncthreads();
+    const uint64_t b0 = (uint64_t)blockIdx.x * per_block;
+    const uint64_t b1 = b0 + per_block < n ? b0 + per_block : n;
+    constexpr int U = 8;
+    uint64_t i = b0 + threadIdx.x;
+    for (; i + (uint64_t)(U - 1) * HLL_THREADS < b1; i += (uint64_t)U * HLL_THREADS) {
+        K k[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) k[u] = keys[i + (uint64_t)u * HLL_THREADS];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const uint32_t c = hll_code(key_bits(k[u]));
+            atomicMax(&reg[c >> 8], c & 0xffu);
+        }
+    }
+    for (; i < b1; i += HLL_THREADS) {
+        const uint32_t c = hll_code(key_bits(keys[i]));
+        atomicMax(&reg[c >> 8], c & 0xffu);
+    }
+    __syncthreads();
+    uint8_t* out = slab + (uint64_t)blockIdx.x * HLL_M;
+    for (uint32_t j = threadIdx.x; j < HLL_M; j += HLL_THREADS) out[j] = (uint8_t)reg[j];
+}
+
+// regs[0][j] = max over R's slabs, regs[1][j] = over S's, regs[2][j] = both
+__global__ __launch_bounds__(256) void k_hll_merge(const uint8_t* __restrict__ slab_r, uint32_t nb_r,
+                                                   const uint8_t* __restrict__ slab_s, uint32_t nb_s,
+                                                   uint8_t* __restrict__ regs)
+{
+    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= HLL_M) return;
+    uint32_t mr = 0, ms = 0;
+    for (uint32_t b = 0; b < nb_r; b++) mr = max(mr, (uint32_t)slab_r[(uint64_t)b * HLL_M + j]);
+    for (uint32_t b = 0; b < nb_s; b++) ms = max(ms, (uint32_t)slab_s[(uint64_t)b * HLL_M + j]);
+    regs[j] = (uint8_t)mr;
+    regs[HLL_M + j] = (uint8_t)ms;
+    regs[2 * HLL_M + j] = (uint8_t)max(mr, ms);
+}
+
+// hist[a][r] = number of registers of array a (R, S, union) holding rank r
+__global__ __launch_bounds__(1024) void k_hll_hist(const uint8_t* __restrict__ regs, uint32_t* __restrict__ hist)
+{
+    __shared__ uint32_t h[3 * HLL_BINS];
+    for (uint32_t j = threadIdx.x; j < 3 * HLL_BINS; j += 1024) h[j] = 0;
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < 3 * HLL_M; j += 1024) atomicAdd(&h[(j / HLL_M) * HLL_BINS + regs[j]], 1u);
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < 3 * HLL_BINS; j += 1024) hist[j] = h[j];
+}
+
+}  // namespace
+
+uint32_t hll_blocks(uint64_t n)
+{
+    if (n == 0) return 0;
+    const uint64_t b = (n + HLL_MIN_ROWS_PER_BLOCK - 1) / HLL_MIN_ROWS_PER_BLOCK;
+    return (uint32_t)(b < HLL_MAX_BLOCKS ? b : HLL_MAX_BLOCKS);
+}
+
+hipError_t launch_hll_block(int kb, const void* keys, uint64_t n, uint8_t* slab, hipStream_t st)
+{
+    const uint32_t nb = hll_blocks(n);
+    if (nb == 0) return hipSuccess;
+    const uint64_t per = (n + nb - 1) / nb;
+    if (kb == 4)
+        hipLaunchKernelGGL(k_hll_block<int32_t>, dim3(nb), dim3(HLL_THREADS), 0, st, (const int32_t*)keys, n, per,
+                           slab);
+    else
+        hipLaunchKernelGGL(k_hll_block<int64_t>, dim3(nb), dim3(HLL_THREADS), 0, st, (const int64_t*)keys, n, per,
+                           slab);
+    return hipGetLastError();
+}
+
+hipError_t launch_hll_finish(const uint8_t* slab_r, uint32_t nb_r, const uint8_t* slab_s, uint32_t nb_s,
+                             uint8_t* regs, uint32_t* hist, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_hll_merge, dim3(HLL_M / 256), dim3(256), 0, st, slab_r, nb_r, slab_s, nb_s, regs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_hll_hist, dim3(1), dim3(1024), 0, st, (const uint8_t*)regs, hist);
+    return hipGetLastError();
+}
+
+}  // namespace tj

@@ -115,6 +115,8 @@ EXPORTS = {
     "tj_server_wait": (ctypes.c_int, [_P, _u64, _P]),
     "tj_server_memory": (ctypes.c_int, [_P, ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),
     "tj_server_destroy": (ctypes.c_int, [_P]),
+    "tj_select_workspace_query": (ctypes.c_int, [_u64, _u64, ctypes.POINTER(_u64)]),
+    "tj_select_path": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _P, _u64, _P, _u64, _P, _P, _P, _P, _u64, _P]),
     "tj_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "tj_version": (ctypes.c_int, []),
     "tj_timing": (ctypes.c_int, [ctypes.c_int]),
@@ -434,6 +436,62 @@ def rmi_buckets(keys, model: RmiModel, stream=None):
     _check(load().tj_rmi_buckets(kt, keys.data_ptr(), keys.numel(), ctypes.byref(model), out.data_ptr(),
                                  ws.data_ptr(), ws.numel(), _stream(stream)), "tj_rmi_buckets")
     return out[:keys.numel()].to(torch.int32) & 0xFFFF
+
+
+TJ_PATH_LINEAR, TJ_PATH_TENSOR = 0, 1
+TJ_SEL_SCALE, TJ_SEL_OUTPUT = 1, 2
+SELECT_REGISTERS = 16384
+
+
+class SelectOptions(ctypes.Structure):
+    _fields_ = [("min_rows", ctypes.c_uint64), ("min_output", ctypes.c_uint64)]
+
+
+class Selection(ctypes.Structure):
+    _fields_ = [("n_r", ctypes.c_uint64), ("n_s", ctypes.c_uint64), ("distinct_r", ctypes.c_double),
+                ("distinct_s", ctypes.c_double), ("distinct_union", ctypes.c_double),
+                ("distinct_common", ctypes.c_double), ("est_output", ctypes.c_double),
+                ("path", ctypes.c_int32), ("reasons", ctypes.c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def select_workspace_query(n_r: int, n_s: int = 0) -> int:
+    b = _u64()
+    _check(load().tj_select_workspace_query(n_r, n_s, ctypes.byref(b)), "tj_select_workspace_query")
+    return int(b.value)
+
+
+def select_path(r_keys, s_keys=None, min_rows: int = 0, min_output: int = 0, registers=None, workspace=None,
+                stream=None) -> dict:
+    """Execution-time choice between the linear and the tensor path for a sort
+    (s_keys None) or a join of the key columns (tj_select_path): the
+    indicators and the decision as a dict. `registers`, when given, is a
+    device uint8 tensor of 3 * 16384 bytes that receives the R, S and union
+    HyperLogLog registers."""
+    torch = _torch()
+    _dev(r_keys, "r_keys")
+    kt = _key_type(r_keys)
+    op, n_s, ps = TJ_OP_SORT, 0, None
+    if s_keys is not None:
+        _dev(s_keys, "s_keys")
+        if _key_type(s_keys) != kt:
+            raise TypeError("r_keys and s_keys must have the same dtype")
+        op, n_s, ps = TJ_OP_JOIN_COUNT, s_keys.numel(), s_keys.data_ptr()
+    need = select_workspace_query(r_keys.numel(), n_s)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=r_keys.device)
+    if registers is not None:
+        _dev(registers, "registers")
+        if registers.dtype != torch.uint8 or registers.numel() < 3 * SELECT_REGISTERS:
+            raise ValueError("registers must be a uint8 tensor of at least 3 * 16384 elements")
+    opt = SelectOptions(min_rows, min_output)
+    out = Selection()
+    _check(load().tj_select_path(op, kt, r_keys.data_ptr(), r_keys.numel(), ps, n_s, ctypes.byref(opt),
+                                 ctypes.byref(out), registers.data_ptr() if registers is not None else None,
+                                 workspace.data_ptr(), workspace.numel(), _stream(stream)), "tj_select_path")
+    return out.as_dict()
 
 
 def debug_wave_scan(x):

@@ -201,3 +201,31 @@ def test_multi_argument_errors():
     assert lib.tj_join_count_multi(2, two, cols, 10, cols, 10, None, W, 1 << 30, None, None) == tj.TJ_E_ARG
     assert lib.tj_join_count_multi(2, two, cols, 0, cols, 10, ctypes.byref(cnt), W, 1 << 30, None, None) == tj.TJ_OK
     assert cnt.value == 0
+
+
+def test_select_argument_errors():
+    lib = tj.load()
+    assert ctypes.sizeof(tj.Selection) == _c_sizeof("tj_selection_t")
+    assert ctypes.sizeof(tj.SelectOptions) == _c_sizeof("tj_select_options_t")
+    b = ctypes.c_uint64()
+    assert lib.tj_select_workspace_query(10, 10, None) == tj.TJ_E_ARG
+    assert lib.tj_select_workspace_query(1 << 31, 0, ctypes.byref(b)) == tj.TJ_E_TOO_LARGE
+    assert lib.tj_select_workspace_query(1 << 20, 1 << 20, ctypes.byref(b)) == tj.TJ_OK
+    need = b.value
+    assert need % 256 == 0 and need >= 2 * 64 * 16384 + 3 * 16384  # 64 blocks of 16384 rows per column
+    out = tj.Selection()
+    o = ctypes.byref(out)
+    sel = lib.tj_select_path
+    assert sel(tj.TJ_OP_JOIN_COUNT, 8, A, 100, B, 100, None, None, None, W, need, None) == tj.TJ_E_ARG
+    assert sel(tj.TJ_OP_JOIN_COUNT, 5, A, 100, B, 100, None, o, None, W, need, None) == tj.TJ_E_ARG
+    assert sel(7, 8, A, 100, B, 100, None, o, None, W, need, None) == tj.TJ_E_ARG
+    assert sel(tj.TJ_OP_SORT, 8, A, 100, B, 100, None, o, None, W, need, None) == tj.TJ_E_ARG  # sort with n_s
+    assert sel(tj.TJ_OP_JOIN_COUNT, 8, None, 100, B, 100, None, o, None, W, need, None) == tj.TJ_E_ARG
+    assert sel(tj.TJ_OP_JOIN_COUNT, 8, A, 100, None, 100, None, o, None, W, need, None) == tj.TJ_E_ARG
+    assert sel(tj.TJ_OP_JOIN_COUNT, 8, A, 1 << 31, B, 100, None, o, None, W, need, None) == tj.TJ_E_TOO_LARGE
+    assert sel(tj.TJ_OP_JOIN_COUNT, 8, A, 100, B, 100, None, o, None, W, 1000, None) == tj.TJ_E_WORKSPACE
+    assert sel(tj.TJ_OP_JOIN_COUNT, 8, A, 100, B, 100, None, o, None, W + 8, need, None) == tj.TJ_E_WORKSPACE
+    assert sel(tj.TJ_OP_JOIN_COUNT, 8, A, 100, B, 100, None, o, None, None, need, None) == tj.TJ_E_WORKSPACE
+    # registers overlapping an input or the workspace
+    assert sel(tj.TJ_OP_JOIN_COUNT, 8, A, 100, B, 100, None, o, A + 8, W, need, None) == tj.TJ_E_ALIAS
+    assert sel(tj.TJ_OP_JOIN_COUNT, 8, A, 100, B, 100, None, o, W + 256, W, need, None) == tj.TJ_E_ALIAS

@@ -12,10 +12,11 @@
 //
 // One pass over the column: each block keeps the 16384 registers of its own
 // slice of rows in LDS (ds_max per row) and writes them to a per-block slab;
-// a merge kernel takes the maximum over the slabs (per relation, and of the
-// two relations for their union) and a one-block kernel histograms the
-// register values for the host-side estimate. No atomics reach HBM, so the
-// result does not depend on block scheduling.
+// a fold kernel takes the maximum over groups of slabs (many blocks, four
+// registers per 4-byte load), a merge kernel over the groups (per relation,
+// and of the two relations for their union), and a one-block kernel
+// histograms the register values for the host-side estimate. No atomics
+// reach HBM, so the result does not depend on block scheduling.
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
@@ -44,8 +45,16 @@ __device__ __forceinline__ uint64_t key_bits(K k)
     return (uint64_t)(int64_t)k;
 }
 
-// slab[blockIdx.x][j] = max rank of the rows [b0, b1) of this block at register j
-template <typename K>
+__device__ __forceinline__ void hll_add(uint32_t* reg, uint64_t k)
+{
+    const uint32_t c = hll_code(k);
+    atomicMax(&reg[c >> 8], c & 0xffu);
+}
+
+// slab[blockIdx.x][j] = max rank of the rows [b0, b1) of this block at register j.
+// per_block is a multiple of HLL_ROW_ALIGN rows; with VEC the keys are 16-byte
+// aligned and read 16 bytes per lane.
+template <typename K, bool VEC>
 __global__ __launch_bounds__(HLL_THREADS) void k_hll_block(const K* __restrict__ keys, uint64_t n,
                                                           uint64_t per_block, uint8_t* __restrict__ slab)
 {
@@ -54,16 +63,51 @@ __global__ __launch_bounds__(HLL_THREADS) void k_hll_block(const K* __restrict__
     __syncthreads();
     const uint64_t b0 = (uint64_t)blockIdx.x * per_block;
     const uint64_t b1 = b0 + per_block < n ? b0 + per_block : n;
-    constexpr int U = 8;
     uint64_t i = b0 + threadIdx.x;
-    for (; i + (uint64_t)(U - 1) * HLL_THREADS < b1; i += (uint64_t)U * HLL_THREADS) {
-        K k[U];
+    if (VEC && b0 < b1) {
+        constexpr uint32_t E = 16 / sizeof(K);  // keys per 16-byte vector
+        constexpr int U = sizeof(K) == 8 ? 4 : 2;  // 8 keys per lane in flight
+        const uint4* __restrict__ vk = (const uint4*)(keys + b0);  // b0 is a multiple of E
+        const uint64_t nv = (b1 - b0) / E;
+        uint64_t v = threadIdx.x;
+        for (; v + (uint64_t)(U - 1) * HLL_THREADS < nv; v += (uint64_t)U * HLL_THREADS) {
+            uint4 x[U];
 #pragma unroll
-        for (int u = 0; u < U; u++) k[u] = keys[i + (uint64_t)u * HLL_THREADS];
+            for (int u = 0; u < U; u++) x[u] = vk[v + (uint64_t)u * HLL_THREADS];
 #pragma unroll
-        for (int u = 0; u < U; u++) {
-            const uint32_t c = hll_code(key_bits(k[u]));
-            atomicMax(&reg[c >> 8], c & 0xffu);
+            for (int u = 0; u < U; u++) {
+                if (sizeof(K) == 8) {
+                    hll_add(reg, ((uint64_t)x[u].y << 32) | x[u].x);
+                    hll_add(reg, ((uint64_t)x[u].w << 32) | x[u].z);
+                } else {
+                    hll_add(reg, key_bits((int32_t)x[u].x));
+                    hll_add(reg, key_bits((int32_t)x[u].y));
+                    hll_add(reg, key_bits((int32_t)x[u].z));
+                    hll_add(reg, key_bits((int32_t)x[u].w));
+                }
+            }
+        }
+        for (; v < nv; v += HLL_THREADS) {
+            const uint4 x = vk[v];
+            if (sizeof(K) == 8) {
+                hll_add(reg, ((uint64_t)x.y << 32) | x.x);
+                hll_add(reg, ((uint64_t)x.w << 32) | x.z);
+            } else {
+                hll_add(reg, key_bits((int32_t)x.x));
+                hll_add(reg, key_bits((int32_t)x.y));
+                hll_add(reg, key_bits((int32_t)x.z));
+                hll_add(reg, key_bits((int32_t)x.w));
+            }
+        }
+        i = b0 + nv * E + threadIdx.x;  // the last < E rows of the block
+    } else {
+        constexpr int U = 8;
+        for (; i + (uint64_t)(U - 1) * HLL_THREADS < b1; i += (uint64_t)U * HLL_THREADS) {
+            K k[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) k[u] = keys[i + (uint64_t)u * HLL_THREADS];
+#pragma unroll
+            for (int u = 0; u < U; u++) hll_add(reg, key_bits(k[u]));
         }
     }
     for (; i < b1; i += HLL_THREADS) {
@@ -75,16 +119,48 @@ __global__ __launch_bounds__(HLL_THREADS) void k_hll_block(const K* __restrict__
     for (uint32_t j = threadIdx.x; j < HLL_M; j += HLL_THREADS) out[j] = (uint8_t)reg[j];
 }
 
-// regs[0][j] = max over R's slabs, regs[1][j] = over S's, regs[2][j] = both
-__global__ __launch_bounds__(256) void k_hll_merge(const uint8_t* __restrict__ slab_r, uint32_t nb_r,
-                                                   const uint8_t* __restrict__ slab_s, uint32_t nb_s,
-                                                   uint8_t* __restrict__ regs)
+__device__ __forceinline__ uint32_t max_u8x4(uint32_t a, uint32_t b)
+{
+    uint32_t r = 0;
+#pragma unroll
+    for (int s = 0; s < 32; s += 8) r |= max((a >> s) & 0xffu, (b >> s) & 0xffu) << s;
+    return r;
+}
+
+// part[z][g][j] = max over the slabs b = g, g + HLL_GROUPS, ... < nb of
+// relation z (0: R, 1: S) at register j; grid (HLL_M / 1024, HLL_GROUPS, 2),
+// each thread four registers (one 4-byte word) of a 1024-register column.
+__global__ __launch_bounds__(256) void k_hll_fold(const uint8_t* __restrict__ slab_r, uint32_t nb_r,
+                                                  const uint8_t* __restrict__ slab_s, uint32_t nb_s,
+                                                  uint8_t* __restrict__ part)
+{
+    constexpr uint32_t W = HLL_M / 4;  // words per slab
+    const uint32_t col = blockIdx.x * 256 + threadIdx.x, g = blockIdx.y, z = blockIdx.z;
+    const uint32_t* __restrict__ sl = (const uint32_t*)(z ? slab_s : slab_r);
+    const uint32_t nb = z ? nb_s : nb_r;
+    uint32_t m = 0;
+    uint32_t b = g;
+    for (; b + 3 * HLL_GROUPS < nb; b += 4 * HLL_GROUPS) {
+        const uint32_t x0 = sl[(uint64_t)b * W + col], x1 = sl[(uint64_t)(b + HLL_GROUPS) * W + col];
+        const uint32_t x2 = sl[(uint64_t)(b + 2 * HLL_GROUPS) * W + col];
+        const uint32_t x3 = sl[(uint64_t)(b + 3 * HLL_GROUPS) * W + col];
+        m = max_u8x4(m, max_u8x4(max_u8x4(x0, x1), max_u8x4(x2, x3)));
+    }
+    for (; b < nb; b += HLL_GROUPS) m = max_u8x4(m, sl[(uint64_t)b * W + col]);
+    ((uint32_t*)part)[((uint64_t)z * HLL_GROUPS + g) * W + col] = m;
+}
+
+// regs[0][j] = max over R's groups, regs[1][j] = over S's, regs[2][j] = both
+__global__ __launch_bounds__(256) void k_hll_merge(const uint8_t* __restrict__ part, uint8_t* __restrict__ regs)
 {
     const uint32_t j = blockIdx.x * 256 + threadIdx.x;
     if (j >= HLL_M) return;
     uint32_t mr = 0, ms = 0;
-    for (uint32_t b = 0; b < nb_r; b++) mr = max(mr, (uint32_t)slab_r[(uint64_t)b * HLL_M + j]);
-    for (uint32_t b = 0; b < nb_s; b++) ms = max(ms, (uint32_t)slab_s[(uint64_t)b * HLL_M + j]);
+#pragma unroll
+    for (uint32_t g = 0; g < HLL_GROUPS; g++) {
+        mr = max(mr, (uint32_t)part[(uint64_t)g * HLL_M + j]);
+        ms = max(ms, (uint32_t)part[(uint64_t)(HLL_GROUPS + g) * HLL_M + j]);
+    }
     regs[j] = (uint8_t)mr;
     regs[HLL_M + j] = (uint8_t)ms;
     regs[2 * HLL_M + j] = (uint8_t)max(mr, ms);
@@ -103,32 +179,58 @@ __global__ __launch_bounds__(1024) void k_hll_hist(const uint8_t* __restrict__ r
 
 }  // namespace
 
+// Rows per block: n split evenly over the blocks, rounded up to whole
+// HLL_ROW_ALIGN rows, so every block but the last starts on a 16-byte
+// boundary of an aligned column; the block count then covers n exactly.
+uint64_t hll_rows_per_block(uint64_t n)
+{
+    if (n == 0) return HLL_ROW_ALIGN;
+    uint64_t b = (n + HLL_MIN_ROWS_PER_BLOCK - 1) / HLL_MIN_ROWS_PER_BLOCK;
+    if (b > HLL_MAX_BLOCKS) b = HLL_MAX_BLOCKS;
+    const uint64_t per = (n + b - 1) / b;
+    return (per + HLL_ROW_ALIGN - 1) / HLL_ROW_ALIGN * HLL_ROW_ALIGN;
+}
+
 uint32_t hll_blocks(uint64_t n)
 {
     if (n == 0) return 0;
-    const uint64_t b = (n + HLL_MIN_ROWS_PER_BLOCK - 1) / HLL_MIN_ROWS_PER_BLOCK;
-    return (uint32_t)(b < HLL_MAX_BLOCKS ? b : HLL_MAX_BLOCKS);
+    const uint64_t per = hll_rows_per_block(n);
+    return (uint32_t)((n + per - 1) / per);
 }
 
 hipError_t launch_hll_block(int kb, const void* keys, uint64_t n, uint8_t* slab, hipStream_t st)
 {
     const uint32_t nb = hll_blocks(n);
     if (nb == 0) return hipSuccess;
-    const uint64_t per = (n + nb - 1) / nb;
-    if (kb == 4)
-        hipLaunchKernelGGL(k_hll_block<int32_t>, dim3(nb), dim3(HLL_THREADS), 0, st, (const int32_t*)keys, n, per,
-                           slab);
-    else
-        hipLaunchKernelGGL(k_hll_block<int64_t>, dim3(nb), dim3(HLL_THREADS), 0, st, (const int64_t*)keys, n, per,
-                           slab);
+    const uint64_t per = hll_rows_per_block(n);
+    const bool vec = ((uintptr_t)keys % 16) == 0;
+    if (kb == 4) {
+        if (vec)
+            hipLaunchKernelGGL((k_hll_block<int32_t, true>), dim3(nb), dim3(HLL_THREADS), 0, st,
+                               (const int32_t*)keys, n, per, slab);
+        else
+            hipLaunchKernelGGL((k_hll_block<int32_t, false>), dim3(nb), dim3(HLL_THREADS), 0, st,
+                               (const int32_t*)keys, n, per, slab);
+    } else {
+        if (vec)
+            hipLaunchKernelGGL((k_hll_block<int64_t, true>), dim3(nb), dim3(HLL_THREADS), 0, st,
+                               (const int64_t*)keys, n, per, slab);
+        else
+            hipLaunchKernelGGL((k_hll_block<int64_t, false>), dim3(nb), dim3(HLL_THREADS), 0, st,
+                               (const int64_t*)keys, n, per, slab);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_hll_finish(const uint8_t* slab_r, uint32_t nb_r, const uint8_t* slab_s, uint32_t nb_s,
-                             uint8_t* regs, uint32_t* hist, hipStream_t st)
+                             uint8_t* part, uint8_t* regs, uint32_t* hist, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_hll_merge, dim3(HLL_M / 256), dim3(256), 0, st, slab_r, nb_r, slab_s, nb_s, regs);
+    hipLaunchKernelGGL(k_hll_fold, dim3(HLL_M / 1024, HLL_GROUPS, 2), dim3(256), 0, st, slab_r, nb_r, slab_s, nb_s,
+                       part);
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_hll_merge, dim3(HLL_M / 256), dim3(256), 0, st, (const uint8_t*)part, regs);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_hll_hist, dim3(1), dim3(1024), 0, st, (const uint8_t*)regs, hist);
     return hipGetLastError();

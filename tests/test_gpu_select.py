@@ -60,6 +60,23 @@ def test_join_selection(tj, dtype, n_r, n_s):
     _check(tj, r, s)
 
 
+@pytest.mark.parametrize("dtype,offset", [(np.int64, 1), (np.int64, 3), (np.int32, 1), (np.int32, 2), (np.int32, 3)])
+def test_unaligned_columns(tj, dtype, offset):
+    """Columns that do not start on a 16-byte boundary take the scalar-load
+    kernel; the registers must not change."""
+    rng = np.random.default_rng(offset)
+    info = np.iinfo(dtype)
+    full = rng.integers(info.min, info.max, size=300007 + offset, dtype=dtype)
+    sfull = rng.integers(-1000, 1000, size=70001 + offset).astype(dtype)
+    d, ds = dev(full)[offset:], dev(sfull)[offset:]
+    assert d.data_ptr() % 16 != 0
+    regs = torch.zeros(3 * S.M, dtype=torch.uint8, device="cuda")
+    got = tj.select_path(d, ds, registers=regs)
+    want = S.select(full[offset:], sfull[offset:])
+    assert np.array_equal(regs.cpu().numpy().reshape(3, S.M), want["registers"])
+    assert got["distinct_union"] == pytest.approx(want["distinct_union"], rel=1e-12)
+
+
 def test_extreme_keys_and_duplicates(tj):
     ext = np.array([np.iinfo(np.int64).min, np.iinfo(np.int64).max, 0, -1, 1], dtype=np.int64)
     r = np.repeat(ext, 40000)

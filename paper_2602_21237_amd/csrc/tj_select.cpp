@@ -28,7 +28,7 @@ bool overlap(const void* a, uint64_t an, const void* b, uint64_t bn)
 }
 
 struct Layout {
-    uint64_t slab_r, slab_s, part, regs, hist, total;
+    uint64_t slab_r, slab_s, part, regs, whist, hist, total;
 };
 
 Layout layout(uint64_t n_r, uint64_t n_s)
@@ -38,7 +38,8 @@ Layout layout(uint64_t n_r, uint64_t n_s)
     l.slab_s = l.slab_r + align_up((uint64_t)hll_blocks(n_r) * HLL_M);
     l.part = l.slab_s + align_up((uint64_t)hll_blocks(n_s) * HLL_M);
     l.regs = l.part + align_up(2ull * HLL_GROUPS * HLL_M);
-    l.hist = l.regs + align_up(3ull * HLL_M);
+    l.whist = l.regs + align_up(3ull * HLL_M);
+    l.hist = l.whist + align_up(HLL_WHIST_WORDS * sizeof(uint32_t));
     l.total = l.hist + align_up(3ull * HLL_BINS * sizeof(uint32_t));
     return l;
 }
@@ -102,11 +103,12 @@ int tj_select_path(int op, int key_type, const void* r_keys, uint64_t n_r, const
     uint8_t* slab_s = (uint8_t*)(w + l.slab_s);
     uint8_t* part = (uint8_t*)(w + l.part);
     uint8_t* regs = registers ? registers : (uint8_t*)(w + l.regs);
+    uint32_t* d_whist = (uint32_t*)(w + l.whist);
     uint32_t* d_hist = (uint32_t*)(w + l.hist);
     if (launch_hll_block(key_type, r_keys, n_r, slab_r, st) != hipSuccess) return TJ_E_HIP;
     if (join && launch_hll_block(key_type, s_keys, n_s, slab_s, st) != hipSuccess) return TJ_E_HIP;
-    if (launch_hll_finish(slab_r, hll_blocks(n_r), slab_s, join ? hll_blocks(n_s) : 0, part, regs, d_hist, st) !=
-        hipSuccess)
+    const uint32_t nb_s = join ? hll_blocks(n_s) : 0;
+    if (launch_hll_finish(slab_r, hll_blocks(n_r), slab_s, nb_s, part, regs, d_whist, d_hist, st) != hipSuccess)
         return TJ_E_HIP;
     uint32_t hist[3 * HLL_BINS];
     if (hipMemcpyAsync(hist, d_hist, sizeof(hist), hipMemcpyDeviceToHost, st) != hipSuccess) return TJ_E_HIP;

@@ -22,8 +22,10 @@ uint64_t hll_rows_per_block(uint64_t n);
 // slab[b][j] = max rank of register j over block b's rows of keys[n].
 hipError_t launch_hll_block(int key_bytes, const void* keys, uint64_t n, uint8_t* slab, hipStream_t st);
 // regs[3][HLL_M] = R, S and union registers; hist[3][HLL_BINS] = their value
-// counts; part: 2 * HLL_GROUPS * HLL_M bytes of scratch.
+// counts; scratch: part, 2 * HLL_GROUPS * HLL_M bytes, and whist,
+// HLL_WHIST_WORDS words.
+constexpr uint64_t HLL_WHIST_WORDS = (HLL_M / 64) * 3 * HLL_BINS;
 hipError_t launch_hll_finish(const uint8_t* slab_r, uint32_t nb_r, const uint8_t* slab_s, uint32_t nb_s,
-                             uint8_t* part, uint8_t* regs, uint32_t* hist, hipStream_t st);
+                             uint8_t* part, uint8_t* regs, uint32_t* whist, uint32_t* hist, hipStream_t st);
 
 }  // namespace tj

@@ -14,8 +14,9 @@
 // slice of rows in LDS (ds_max per row) and writes them to a per-block slab;
 // a fold kernel takes the maximum over groups of slabs (many blocks, four
 // registers per 4-byte load), a merge kernel over the groups (per relation,
-// and of the two relations for their union), and a one-block kernel
-// histograms the register values for the host-side estimate. No atomics
+// and of the two relations for their union) that also counts each wave's
+// register values by ballots, and a one-block kernel sums those counts into
+// the histogram the host turns into estimates. No atomics
 // reach HBM, so the result does not depend on block scheduling.
 #include <hip/hip_runtime.h>
 #include <cstdint>
@@ -150,11 +151,13 @@ __global__ __launch_bounds__(256) void k_hll_fold(const uint8_t* __restrict__ sl
     ((uint32_t*)part)[((uint64_t)z * HLL_GROUPS + g) * W + col] = m;
 }
 
-// regs[0][j] = max over R's groups, regs[1][j] = over S's, regs[2][j] = both
-__global__ __launch_bounds__(256) void k_hll_merge(const uint8_t* __restrict__ part, uint8_t* __restrict__ regs)
+// regs[0][j] = max over R's groups, regs[1][j] = over S's, regs[2][j] = both;
+// whist[wave][a][r] = registers of array a holding rank r among the wave's 64
+// (lane r counts rank r by one ballot per rank; grid HLL_M / 256 exactly).
+__global__ __launch_bounds__(256) void k_hll_merge(const uint8_t* __restrict__ part, uint8_t* __restrict__ regs,
+                                                   uint32_t* __restrict__ whist)
 {
     const uint32_t j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= HLL_M) return;
     uint32_t mr = 0, ms = 0;
 #pragma unroll
     for (uint32_t g = 0; g < HLL_GROUPS; g++) {
@@ -163,18 +166,34 @@ __global__ __launch_bounds__(256) void k_hll_merge(const uint8_t* __restrict__ p
     }
     regs[j] = (uint8_t)mr;
     regs[HLL_M + j] = (uint8_t)ms;
-    regs[2 * HLL_M + j] = (uint8_t)max(mr, ms);
+    const uint32_t mu = max(mr, ms);
+    regs[2 * HLL_M + j] = (uint8_t)mu;
+    const uint32_t lane = threadIdx.x & 63;
+    uint32_t cr = 0, cs = 0, cu = 0;
+    for (uint32_t r = 0; r <= (uint32_t)(64 - HLL_P + 1); r++) {
+        const uint32_t a = (uint32_t)__popcll(__ballot(mr == r));
+        const uint32_t b = (uint32_t)__popcll(__ballot(ms == r));
+        const uint32_t c = (uint32_t)__popcll(__ballot(mu == r));
+        if (lane == r) {
+            cr = a;
+            cs = b;
+            cu = c;
+        }
+    }
+    uint32_t* wh = whist + (uint64_t)(j / 64) * 3 * HLL_BINS;
+    wh[lane] = cr;
+    wh[HLL_BINS + lane] = cs;
+    wh[2 * HLL_BINS + lane] = cu;
 }
 
-// hist[a][r] = number of registers of array a (R, S, union) holding rank r
-__global__ __launch_bounds__(1024) void k_hll_hist(const uint8_t* __restrict__ regs, uint32_t* __restrict__ hist)
+// hist[a][r] = number of registers of array a (R, S, union) holding rank r:
+// the sum of the HLL_M / 64 per-wave counts; one thread per (a, r)
+__global__ __launch_bounds__(3 * HLL_BINS) void k_hll_hist(const uint32_t* __restrict__ whist,
+                                                           uint32_t* __restrict__ hist)
 {
-    __shared__ uint32_t h[3 * HLL_BINS];
-    for (uint32_t j = threadIdx.x; j < 3 * HLL_BINS; j += 1024) h[j] = 0;
-    __syncthreads();
-    for (uint32_t j = threadIdx.x; j < 3 * HLL_M; j += 1024) atomicAdd(&h[(j / HLL_M) * HLL_BINS + regs[j]], 1u);
-    __syncthreads();
-    for (uint32_t j = threadIdx.x; j < 3 * HLL_BINS; j += 1024) hist[j] = h[j];
+    uint32_t t = 0;
+    for (uint32_t w = 0; w < HLL_M / 64; w++) t += whist[(uint64_t)w * 3 * HLL_BINS + threadIdx.x];
+    hist[threadIdx.x] = t;
 }
 
 }  // namespace
@@ -223,16 +242,16 @@ hipError_t launch_hll_block(int kb, const void* keys, uint64_t n, uint8_t* slab,
 }
 
 hipError_t launch_hll_finish(const uint8_t* slab_r, uint32_t nb_r, const uint8_t* slab_s, uint32_t nb_s,
-                             uint8_t* part, uint8_t* regs, uint32_t* hist, hipStream_t st)
+                             uint8_t* part, uint8_t* regs, uint32_t* whist, uint32_t* hist, hipStream_t st)
 {
     hipLaunchKernelGGL(k_hll_fold, dim3(HLL_M / 1024, HLL_GROUPS, 2), dim3(256), 0, st, slab_r, nb_r, slab_s, nb_s,
                        part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_hll_merge, dim3(HLL_M / 256), dim3(256), 0, st, (const uint8_t*)part, regs);
+    hipLaunchKernelGGL(k_hll_merge, dim3(HLL_M / 256), dim3(256), 0, st, (const uint8_t*)part, regs, whist);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_hll_hist, dim3(1), dim3(1024), 0, st, (const uint8_t*)regs, hist);
+    hipLaunchKernelGGL(k_hll_hist, dim3(1), dim3(3 * HLL_BINS), 0, st, (const uint32_t*)whist, hist);
     return hipGetLastError();
 }
 

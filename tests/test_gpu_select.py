@@ -112,3 +112,30 @@ def test_full_size_join(tj):
     sigma = 1.04 / np.sqrt(S.M)
     assert abs(got["distinct_r"] - r.size) <= 3 * sigma * r.size  # R's keys are distinct
     assert got["path"] == 1 and got["reasons"] & 1
+
+
+def test_side_stream_and_join_ops(tj):
+    """The selection runs on the caller's stream, and both join ops give the
+    same selection."""
+    import ctypes
+    from paper_2602_21237_amd import tj as tjm
+    rng = np.random.default_rng(9)
+    r = rng.integers(0, 1 << 30, size=200003, dtype=np.int64)
+    s = rng.integers(0, 1 << 30, size=100001, dtype=np.int64)
+    dr, ds = dev(r), dev(s)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        got = tj.select_path(dr, ds, stream=side)
+    want = S.select(r, s)
+    assert got["path"] == want["path"] and got["distinct_union"] == pytest.approx(want["distinct_union"], rel=1e-12)
+    lib = tjm.load()
+    need = tj.select_workspace_query(r.size, s.size)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    outs = []
+    for op in (tj.TJ_OP_JOIN_COUNT, tj.TJ_OP_JOIN_MATERIALIZE):
+        o = tjm.Selection()
+        assert lib.tj_select_path(op, 8, dr.data_ptr(), r.size, ds.data_ptr(), s.size, None, ctypes.byref(o), None,
+                                  ws.data_ptr(), need, None) == 0
+        outs.append(o.as_dict())
+    assert outs[0] == outs[1] == got

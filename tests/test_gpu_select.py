@@ -103,7 +103,7 @@ def test_thresholds(tj):
 
 
 def test_full_size_join(tj):
-    """The benchmark's join inputs (2^27 R rows with distinct keys, 2^28 S
+    """The benchmark's join inputs (2^27 R rows with distinct keys, 2^29 S
     rows): registers against the oracle's, estimates against the known
     distinct counts."""
     w = tjgen.hbm_scale(0.0)

@@ -43,7 +43,7 @@ def _check(tj, r, s=None, **kw):
 
 
 @pytest.mark.parametrize("dtype", [np.int32, np.int64])
-@pytest.mark.parametrize("n", [0, 1, 1000, 3 * 16384 + 17, (1 << 20) + 13])
+@pytest.mark.parametrize("n", [0, 1, 1000, 4096, 3 * 16384 + 17, (1 << 20) + 13, 512 * 16384, 512 * 16384 + 1])
 def test_sort_selection(tj, dtype, n):
     rng = np.random.default_rng(n + 1)
     info = np.iinfo(dtype)

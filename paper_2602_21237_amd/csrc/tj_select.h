@@ -14,7 +14,7 @@ constexpr uint32_t HLL_BINS = 64;              // register values 0 .. 64 - HLL_
 constexpr uint32_t HLL_THREADS = 1024;
 constexpr uint32_t HLL_MAX_BLOCKS = 512;       // two 64 KiB-LDS blocks per CU
 constexpr uint64_t HLL_MIN_ROWS_PER_BLOCK = 16384;
-constexpr uint64_t HLL_ROW_ALIGN = 4096;       // rows per block are a multiple of this
+constexpr uint64_t HLL_ROW_ALIGN = 64;         // rows per block are a multiple of this
 constexpr uint32_t HLL_GROUPS = 16;            // slab groups of the first merge step
 // Blocks (slabs of HLL_M bytes) one column of n rows uses; 0 for n = 0.
 uint32_t hll_blocks(uint64_t n);

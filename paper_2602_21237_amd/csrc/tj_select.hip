@@ -199,8 +199,8 @@ __global__ __launch_bounds__(3 * HLL_BINS) void k_hll_hist(const uint32_t* __res
 }  // namespace
 
 // Rows per block: n split evenly over the blocks, rounded up to whole
-// HLL_ROW_ALIGN rows, so every block but the last starts on a 16-byte
-// boundary of an aligned column; the block count then covers n exactly.
+// HLL_ROW_ALIGN rows, so every block starts on a 16-byte boundary of an
+// aligned column; the block count then covers n exactly.
 uint64_t hll_rows_per_block(uint64_t n)
 {
     if (n == 0) return HLL_ROW_ALIGN;

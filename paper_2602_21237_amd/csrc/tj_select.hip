@@ -29,6 +29,16 @@ namespace {
 
 constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// A 16-byte streaming load: the keys are read once, so they are not kept in
+// the caches.
+__device__ __forceinline__ uint4 ld_stream(const uint4* p)
+{
+    const u32x4 v = __builtin_nontemporal_load((const u32x4*)p);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
 __device__ __forceinline__ uint32_t hll_code(uint64_t k)
 {
     uint64_t z = k + kGamma;
@@ -74,7 +84,7 @@ __global__ __launch_bounds__(HLL_THREADS) void k_hll_block(const K* __restrict__
         for (; v + (uint64_t)(U - 1) * HLL_THREADS < nv; v += (uint64_t)U * HLL_THREADS) {
             uint4 x[U];
 #pragma unroll
-            for (int u = 0; u < U; u++) x[u] = vk[v + (uint64_t)u * HLL_THREADS];
+            for (int u = 0; u < U; u++) x[u] = ld_stream(vk + v + (uint64_t)u * HLL_THREADS);
 #pragma unroll
             for (int u = 0; u < U; u++) {
                 if (sizeof(K) == 8) {
@@ -89,7 +99,7 @@ __global__ __launch_bounds__(HLL_THREADS) void k_hll_block(const K* __restrict__
             }
         }
         for (; v < nv; v += HLL_THREADS) {
-            const uint4 x = vk[v];
+            const uint4 x = ld_stream(vk + v);
             if (sizeof(K) == 8) {
                 hll_add(reg, ((uint64_t)x.y << 32) | x.x);
                 hll_add(reg, ((uint64_t)x.w << 32) | x.z);

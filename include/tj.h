@@ -2,10 +2,11 @@
  * tj.h - tensor-path equi-join and sort on one MI355X (gfx950).
  *
  * The paper's tensor-based execution path (Sec. III-IV) keeps relations as
- * columns ("a relation is a sparse set of coordinates, one axis per attribute",
- * Sec. III.B) and delays linearisation and materialisation to the last step
- * (Sec. III.A). Here a relation is two device columns, keys[n] and rids[n],
- * and the only materialised join output is the final (rid_R, rid_S) pairs.
+ * columns: a relation is treated as a sparse set of points with one coordinate
+ * axis per attribute (Sec. III.B), and linearisation and materialisation are
+ * delayed to the last step (Sec. III.A). Here a relation is two device
+ * columns, keys[n] and rids[n], and the only materialised join output is the
+ * final (rid_R, rid_S) pairs.
  *
  * Every call takes a caller-owned device workspace of `workspace_bytes`; it
  * plays the role of the paper's work_mem budget M (Sec. VI, Eq. 1). Results
@@ -17,8 +18,9 @@
  *   - key_type: TJ_KEY_I32 (int32_t keys) or TJ_KEY_I64 (int64_t keys). Keys
  *     are compared as signed integers.
  *   - All array pointers are device pointers into caller-owned memory. Inputs
- *     are read-only; outputs must not overlap inputs or the workspace
- *     (TJ_E_ALIAS). The library allocates no device memory.
+ *     are read-only; outputs must not overlap inputs or the workspace, and the
+ *     workspace must not overlap an input (TJ_E_ALIAS). The library allocates
+ *     no device memory.
  *   - workspace: device memory of workspace_bytes bytes, 256-byte aligned.
  *     Its contents are undefined after a call.
  *   - stream: a hipStream_t (NULL = the null stream). Work is ordered on it.
@@ -49,9 +51,9 @@ enum tj_status {
     TJ_E_WORKSPACE = -2,  /* workspace_bytes below the minimum, or misaligned */
     TJ_E_CAPACITY = -3,   /* join result larger than `capacity` (count still set) */
     TJ_E_TOO_LARGE = -4,  /* a row count >= 2^31 */
-    TJ_E_ALIAS = -5,      /* an output overlaps an input or the workspace */
+    TJ_E_ALIAS = -5,      /* an output overlaps an input or the workspace, or the workspace an input */
     TJ_E_HIP = -6,        /* a HIP runtime call or kernel launch failed */
-    TJ_E_INTERNAL = -7    /* a planner invariant failed (a library bug) */
+    TJ_E_INTERNAL = -7    /* a planner invariant failed (a library bug), or host memory ran out */
 };
 
 /* Plan bookkeeping of one call. Byte counts are the algorithmic HBM bytes of
@@ -404,7 +406,7 @@ int tj_server_destroy(tj_server_t *server);
  * Synchronous: returns after the result is on the host. Errors: TJ_E_ARG
  * (NULL pointers, bad op or key type, sort with n_s != 0), TJ_E_TOO_LARGE,
  * TJ_E_WORKSPACE, TJ_E_ALIAS (registers overlapping an input or the
- * workspace), TJ_E_HIP.
+ * workspace, or the workspace overlapping an input), TJ_E_HIP.
  */
 #define TJ_SELECT_REGISTERS 16384
 #define TJ_SELECT_DEFAULT_MIN_ROWS (1ull << 16)
@@ -472,11 +474,16 @@ int tj_version(void);
  *   result must not change). Other bits give TJ_E_ARG.
  */
 #define TJ_DEBUG_FORCE_REORDER 1u
+#define TJ_DEBUG_FAIL_HOST_ALLOC 2u
 /*
  * tj_debug_set_flags: process-wide self-test switch for every later call.
  *   TJ_DEBUG_FORCE_REORDER: each partition tile and each join block also runs
  *   the ballot-ranked path that replaces an atomic-ranked order found out of
  *   input order; results must not change, only time. 0 turns it off.
+ *   TJ_DEBUG_FAIL_HOST_ALLOC: every later sort or join call (plain, _ex,
+ *   and the learned-model training) fails its first host-side allocation,
+ *   before any device work; the call returns TJ_E_INTERNAL. It tests that no
+ *   C++ exception crosses the C ABI.
  *   Returns TJ_OK, or TJ_E_ARG for unknown bits.
  */
 int tj_debug_set_flags(uint32_t flags);

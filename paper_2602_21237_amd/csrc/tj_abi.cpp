@@ -29,6 +29,7 @@
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <new>
 #include <vector>
 
 namespace tj {
@@ -318,6 +319,8 @@ thread_local HostVecs* t_host_vecs = nullptr;  // never freed, like the pinned s
 // private set owned through `owned`.
 HostVecs& borrow_host_vecs(HostVecs*& owned)
 {
+    // self-test: a host allocation failure at the start of a call, before any device work
+    if (g_debug_flags.load() & TJ_DEBUG_FAIL_HOST_ALLOC) throw std::bad_alloc();
     if (!t_host_vecs) t_host_vecs = new HostVecs();
     if (!t_host_vecs->busy) {
         t_host_vecs->busy = true;
@@ -1639,7 +1642,7 @@ int learned_wanted(const tj_options_t* opt, uint64_t rows, bool& want, bool& is_
 }  // namespace
 }  // namespace tj
 
-static int sort_impl(int key_type, const void* keys_in, const int32_t* rids_in, uint64_t n, void* keys_out,
+static int sort_body(int key_type, const void* keys_in, const int32_t* rids_in, uint64_t n, void* keys_out,
                      int32_t* rids_out, void* workspace, uint64_t workspace_bytes, void* stream,
                      const tj_options_t* opt, tj_stats_t* stats)
 {
@@ -1660,6 +1663,8 @@ static int sort_impl(int key_type, const void* keys_in, const int32_t* rids_in, 
             overlap(outs[i], osz[i], workspace, workspace_bytes))
             return TJ_E_ALIAS;
     if (overlap(keys_out, kbytes, rids_out, rbytes)) return TJ_E_ALIAS;
+    if (overlap(workspace, workspace_bytes, keys_in, kbytes) || overlap(workspace, workspace_bytes, rids_in, rbytes))
+        return TJ_E_ALIAS;
 
     Exec x;
     x.timed_on = timing_enabled() && !t_nested;
@@ -1775,7 +1780,7 @@ static int sort_impl(int key_type, const void* keys_in, const int32_t* rids_in, 
     return TJ_OK;
 }
 
-static int join_impl(int key_type, const void* r_keys, const int32_t* r_rids, uint64_t n_r,
+static int join_body(int key_type, const void* r_keys, const int32_t* r_rids, uint64_t n_r,
                      const void* s_keys, const int32_t* s_rids, uint64_t n_s, int32_t* out_r,
                      int32_t* out_s, uint64_t capacity, uint64_t* count, void* workspace,
                      uint64_t workspace_bytes, void* stream, tj_stats_t* stats, bool mat,
@@ -1794,6 +1799,10 @@ static int join_impl(int key_type, const void* r_keys, const int32_t* r_rids, ui
     if (mat && (!r_rids || !s_rids || (capacity > 0 && (!out_r || !out_s)))) return TJ_E_ARG;
     if ((uintptr_t)workspace % ALIGN) return TJ_E_WORKSPACE;
     const uint64_t kb = (uint64_t)key_type;
+    if (overlap(workspace, workspace_bytes, r_keys, n_r * kb) || overlap(workspace, workspace_bytes, s_keys, n_s * kb) ||
+        (mat && (overlap(workspace, workspace_bytes, r_rids, n_r * 4) ||
+                 overlap(workspace, workspace_bytes, s_rids, n_s * 4))))
+        return TJ_E_ALIAS;
     if (mat && capacity > 0) {
         const void* ins[4] = {r_keys, s_keys, r_rids, s_rids};
         const uint64_t isz[4] = {n_r * kb, n_s * kb, n_r * 4, n_s * 4};
@@ -1903,6 +1912,34 @@ static int join_impl(int key_type, const void* r_keys, const int32_t* r_rids, ui
     return TJ_OK;
 }
 
+// Host-side containers of the planner may throw (std::bad_alloc); nothing
+// crosses the C ABI: an exception becomes TJ_E_INTERNAL.
+static int sort_impl(int key_type, const void* keys_in, const int32_t* rids_in, uint64_t n, void* keys_out,
+                     int32_t* rids_out, void* workspace, uint64_t workspace_bytes, void* stream,
+                     const tj_options_t* opt, tj_stats_t* stats)
+{
+    try {
+        return sort_body(key_type, keys_in, rids_in, n, keys_out, rids_out, workspace, workspace_bytes, stream, opt,
+                         stats);
+    } catch (...) {
+        return TJ_E_INTERNAL;
+    }
+}
+
+static int join_impl(int key_type, const void* r_keys, const int32_t* r_rids, uint64_t n_r,
+                     const void* s_keys, const int32_t* s_rids, uint64_t n_s, int32_t* out_r,
+                     int32_t* out_s, uint64_t capacity, uint64_t* count, void* workspace,
+                     uint64_t workspace_bytes, void* stream, tj_stats_t* stats, bool mat,
+                     const tj_options_t* opt)
+{
+    try {
+        return join_body(key_type, r_keys, r_rids, n_r, s_keys, s_rids, n_s, out_r, out_s, capacity, count,
+                         workspace, workspace_bytes, stream, stats, mat, opt);
+    } catch (...) {
+        return TJ_E_INTERNAL;
+    }
+}
+
 extern "C" {
 
 int tj_sort(int key_type, const void* keys_in, const int32_t* rids_in, uint64_t n, void* keys_out,
@@ -1965,7 +2002,9 @@ int tj_rmi_workspace_query(int key_type, uint64_t n_a, uint64_t n_b, uint32_t pe
     return TJ_OK;
 }
 
-int tj_rmi_train(int key_type, const void* keys_a, uint64_t n_a, const void* keys_b, uint64_t n_b,
+}  // extern "C"
+
+static int rmi_train_body(int key_type, const void* keys_a, uint64_t n_a, const void* keys_b, uint64_t n_b,
                  uint32_t permille, tj_rmi_t* model, void* workspace, uint64_t workspace_bytes, void* stream)
 {
     if (validate_common(key_type) != TJ_OK || !keys_a || n_a == 0 || !model || !workspace) return TJ_E_ARG;
@@ -1985,6 +2024,19 @@ int tj_rmi_train(int key_type, const void* keys_a, uint64_t n_a, const void* key
     TJ_CK(hipMemcpyAsync(model, x.d_model, sizeof(tj_rmi_t), hipMemcpyDeviceToHost, x.st));
     TJ_CK(hipStreamSynchronize(x.st));
     return TJ_OK;
+}
+
+extern "C" {
+
+int tj_rmi_train(int key_type, const void* keys_a, uint64_t n_a, const void* keys_b, uint64_t n_b,
+                 uint32_t permille, tj_rmi_t* model, void* workspace, uint64_t workspace_bytes, void* stream)
+{
+    try {
+        return rmi_train_body(key_type, keys_a, n_a, keys_b, n_b, permille, model, workspace, workspace_bytes,
+                              stream);
+    } catch (...) {
+        return TJ_E_INTERNAL;
+    }
 }
 
 int tj_rmi_buckets(int key_type, const void* keys, uint64_t n, const tj_rmi_t* model, uint16_t* buckets,
@@ -2011,7 +2063,9 @@ int tj_rmi_buckets(int key_type, const void* keys, uint64_t n, const tj_rmi_t* m
     return TJ_OK;
 }
 
-int tj_debug_partition_pass(const int64_t* keys, const int32_t* rids, uint64_t n, uint64_t base,
+}  // extern "C"
+
+static int partition_pass_body(const int64_t* keys, const int32_t* rids, uint64_t n, uint64_t base,
                             uint32_t shift, uint32_t bits, uint32_t flags, int64_t* keys_out,
                             int32_t* rids_out, uint32_t* counts_out, void* workspace,
                             uint64_t workspace_bytes, void* stream)
@@ -2068,9 +2122,24 @@ int tj_debug_partition_pass(const int64_t* keys, const int32_t* rids, uint64_t n
     return TJ_OK;
 }
 
+extern "C" {
+
+int tj_debug_partition_pass(const int64_t* keys, const int32_t* rids, uint64_t n, uint64_t base,
+                            uint32_t shift, uint32_t bits, uint32_t flags, int64_t* keys_out,
+                            int32_t* rids_out, uint32_t* counts_out, void* workspace,
+                            uint64_t workspace_bytes, void* stream)
+{
+    try {
+        return partition_pass_body(keys, rids, n, base, shift, bits, flags, keys_out, rids_out, counts_out,
+                                   workspace, workspace_bytes, stream);
+    } catch (...) {
+        return TJ_E_INTERNAL;
+    }
+}
+
 int tj_debug_set_flags(uint32_t flags)
 {
-    if (flags & ~(uint32_t)TJ_DEBUG_FORCE_REORDER) return TJ_E_ARG;
+    if (flags & ~(uint32_t)(TJ_DEBUG_FORCE_REORDER | TJ_DEBUG_FAIL_HOST_ALLOC)) return TJ_E_ARG;
     g_debug_flags.store(flags);
     return TJ_OK;
 }

@@ -192,6 +192,12 @@ int join_impl(int ncols, const int* types, const void* const* r_keys, const int3
         if (!r_keys[c] || !s_keys[c]) return TJ_E_ARG;
     if (mat && (!r_rids || !s_rids || (capacity && (!out_r || !out_s)))) return TJ_E_ARG;
     if ((uintptr_t)workspace % kAlign) return TJ_E_WORKSPACE;
+    for (int c = 0; c < ncols; c++)
+        if (overlap(workspace, ws_bytes, r_keys[c], n_r * types[c]) ||
+            overlap(workspace, ws_bytes, s_keys[c], n_s * types[c]))
+            return TJ_E_ALIAS;
+    if (mat && (overlap(workspace, ws_bytes, r_rids, n_r * 4) || overlap(workspace, ws_bytes, s_rids, n_s * 4)))
+        return TJ_E_ALIAS;
     if (mat && capacity) {
         for (int c = 0; c < ncols; c++)
             for (int32_t* o : {out_r, out_s})
@@ -316,6 +322,8 @@ static int sort_multi_body(int ncols, const int* key_types, const void* const* k
         for (size_t q = o + 1; q < outs.size(); q++)
             if (overlap(outs[o].first, outs[o].second, outs[q].first, outs[q].second)) return TJ_E_ALIAS;
     }
+    for (size_t i = 0; i + 1 < ins.size(); i++)  // the workspace (last) against every input
+        if (overlap(workspace, workspace_bytes, ins[i].first, ins[i].second)) return TJ_E_ALIAS;
     hipStream_t st = (hipStream_t)stream;
     tj_stats_t acc{};
     Carve cv{(char*)workspace, (char*)workspace + workspace_bytes};

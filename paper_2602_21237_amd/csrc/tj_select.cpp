@@ -90,6 +90,8 @@ int tj_select_path(int op, int key_type, const void* r_keys, uint64_t n_r, const
     if (overlap(registers, reg_bytes, r_keys, n_r * kb) || overlap(registers, reg_bytes, s_keys, n_s * kb) ||
         overlap(registers, reg_bytes, workspace, workspace_bytes))
         return TJ_E_ALIAS;
+    if (overlap(workspace, workspace_bytes, r_keys, n_r * kb) || overlap(workspace, workspace_bytes, s_keys, n_s * kb))
+        return TJ_E_ALIAS;
 
     uint64_t min_rows = TJ_SELECT_DEFAULT_MIN_ROWS, min_output = TJ_SELECT_DEFAULT_MIN_OUTPUT;
     if (options) {

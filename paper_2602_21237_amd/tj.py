@@ -503,10 +503,12 @@ def debug_wave_scan(x):
 
 
 TJ_DEBUG_FORCE_REORDER = 1
+TJ_DEBUG_FAIL_HOST_ALLOC = 2
 
 
 def debug_set_flags(flags: int) -> None:
-    """Process-wide self-test flags for later calls (TJ_DEBUG_FORCE_REORDER or 0)."""
+    """Process-wide self-test flags for later calls (TJ_DEBUG_FORCE_REORDER,
+    TJ_DEBUG_FAIL_HOST_ALLOC, or 0)."""
     _check(load().tj_debug_set_flags(flags), "tj_debug_set_flags")
 
 

@@ -91,6 +91,61 @@ def test_join_argument_errors():
                                    1 << 30, None, None) == tj.TJ_E_ALIAS
 
 
+def test_workspace_overlapping_an_input():
+    lib = tj.load()
+    n = 1000
+    cnt = ctypes.c_uint64(0)
+    # the workspace over the sort's keys or rids
+    assert lib.tj_sort(8, A, B, n, C, D, A + 256, 1 << 20, None, None) == tj.TJ_E_ALIAS
+    assert lib.tj_sort(8, A, B, n, C, D, B - 256, 1 << 20, None, None) == tj.TJ_E_ALIAS
+    # the workspace over a join's key or rid columns
+    assert lib.tj_join_count(8, A, n, B, n, ctypes.byref(cnt), B - 256, 1 << 20, None, None) == tj.TJ_E_ALIAS
+    assert lib.tj_join_materialize(8, A, B, n, C, D, n, 0x60000000, 0x61000000, 10, ctypes.byref(cnt),
+                                   D + 256, 1 << 20, None, None) == tj.TJ_E_ALIAS
+    # the path selector's workspace over a key column
+    need = ctypes.c_uint64()
+    assert lib.tj_select_workspace_query(n, n, ctypes.byref(need)) == tj.TJ_OK
+    out = tj.Selection()
+    assert lib.tj_select_path(tj.TJ_OP_JOIN_COUNT, 8, A, n, B, n, None, ctypes.byref(out), None, A,
+                              need.value, None) == tj.TJ_E_ALIAS
+    # composite keys: the workspace over a key column or the rids
+    two = (ctypes.c_int * 2)(8, 4)
+    cols = (ctypes.c_void_p * 2)(A, B)
+    outs = (ctypes.c_void_p * 2)(C, C + 8000)
+    assert lib.tj_sort_multi(2, two, cols, D, n, outs, W, B, 1 << 20, None, None) == tj.TJ_E_ALIAS
+    assert lib.tj_join_count_multi(2, two, cols, n, cols, n, ctypes.byref(cnt), A + 4096, 1 << 20, None,
+                                   None) == tj.TJ_E_ALIAS
+
+
+def test_host_allocation_failure_returns_internal():
+    """A host allocation that throws inside the planner comes back as
+    TJ_E_INTERNAL (no C++ exception crosses the C ABI). The self-test flag
+    makes the first host allocation of every sort and join call fail before
+    any device work, so fake device addresses are never touched."""
+    lib = tj.load()
+    n = 1000
+    cnt = ctypes.c_uint64(0)
+    opt = tj.Options(tj.TJ_PART_LEARNED, 0, 0)
+    m = tj.RmiModel()
+    tj.debug_set_flags(tj.TJ_DEBUG_FAIL_HOST_ALLOC)
+    try:
+        assert lib.tj_sort(8, A, B, n, C, D, W, 1 << 30, None, None) == tj.TJ_E_INTERNAL
+        assert lib.tj_sort_ex(4, A, B, n, C, D, W, 1 << 30, None, ctypes.byref(opt), None) == tj.TJ_E_INTERNAL
+        assert lib.tj_join_count(8, A, n, B, n, ctypes.byref(cnt), W, 1 << 30, None, None) == tj.TJ_E_INTERNAL
+        assert lib.tj_join_count_ex(8, A, n, B, n, ctypes.byref(cnt), W, 1 << 30, None, ctypes.byref(opt),
+                                    None) == tj.TJ_E_INTERNAL
+        assert lib.tj_join_materialize(8, A, B, n, C, D, n, 0x60000000, 0x61000000, 10, ctypes.byref(cnt),
+                                       W, 1 << 26, None, None) == tj.TJ_E_INTERNAL
+        assert lib.tj_rmi_train(8, A, n, None, 0, 0, ctypes.byref(m), W, 1 << 30, None) == tj.TJ_E_INTERNAL
+        assert lib.tj_debug_partition_pass(A, B, n, 0, 0, 8, 0, C, D, 0x60000000, W, 1 << 30,
+                                           None) == tj.TJ_E_INTERNAL
+        # argument errors are still found first
+        assert lib.tj_sort(8, None, B, n, C, D, W, 1 << 30, None, None) == tj.TJ_E_ARG
+    finally:
+        tj.debug_set_flags(0)
+    assert lib.tj_debug_set_flags(8) == tj.TJ_E_ARG
+
+
 def _c_sizeof(type_name: str) -> int:
     import subprocess
     import tempfile

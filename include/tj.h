@@ -19,8 +19,9 @@
  *     are compared as signed integers.
  *   - All array pointers are device pointers into caller-owned memory. Inputs
  *     are read-only; outputs must not overlap inputs or the workspace, and the
- *     workspace must not overlap an input (TJ_E_ALIAS). The library allocates
- *     no device memory.
+ *     workspace must not overlap an input (TJ_E_ALIAS). No call allocates
+ *     device memory (tj_sort_static works in a fixed array that the library's
+ *     code object brings with it).
  *   - workspace: device memory of workspace_bytes bytes, 256-byte aligned.
  *     Its contents are undefined after a call.
  *   - stream: a hipStream_t (NULL = the null stream). Work is ordered on it.
@@ -96,6 +97,30 @@ int tj_workspace_query(int op, int key_type, uint64_t n_r, uint64_t n_s,
 int tj_sort(int key_type, const void *keys_in, const int32_t *rids_in, uint64_t n,
             void *keys_out, int32_t *rids_out,
             void *workspace, uint64_t workspace_bytes, void *stream, tj_stats_t *stats);
+
+/*
+ * tj_sort for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, semantics, results and errors as tj_sort, without the
+ * workspace: the call uses a device array of TJ_STATIC_SCRATCH_BYTES (256 MiB)
+ * that the library holds on every GPU it runs on, from the library's load
+ * until the process ends, as its workspace budget. Inputs of up to 22,322,688
+ * int64 rows (33,484,032 int32 rows) run the unlimited plan; larger ones run
+ * the budget-bound plan (key ranges) inside the same array, so results never
+ * change, only time.
+ * The call makes no device or pinned-host allocation (its read-backs go to
+ * grow-only pageable host memory) and records no timing events.
+ * The array is shared by every call on one GPU: the library serialises those
+ * calls (each returns after its work is complete on `stream`), so two calls
+ * on one GPU never overlap; nothing is carried from one call to the next.
+ * `stream` must belong to the current device.
+ * Errors: as tj_sort; TJ_E_WORKSPACE if the shape's minimum workspace exceeds
+ * the array (no row count below 2^31 does); TJ_E_HIP if the array's device
+ * address cannot be obtained.
+ */
+#define TJ_STATIC_SCRATCH_BYTES (256ull << 20)
+int tj_sort_static(int key_type, const void *keys_in, const int32_t *rids_in, uint64_t n,
+                   void *keys_out, int32_t *rids_out, void *stream, tj_stats_t *stats);
 
 /*
  * Tensor-based hash join, count only (Sec. IV.A): the inner equi-join size

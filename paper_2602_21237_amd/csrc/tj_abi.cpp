@@ -121,8 +121,19 @@ struct PinnedBuf {
 thread_local PinnedBuf* t_down = nullptr;
 thread_local PinnedBuf* t_up = nullptr;
 
+// Set while a call runs without allocating (tj_sort_static): read-backs then
+// land in grow-only pageable host memory instead of pinned staging, and the
+// call records no timing events.
+thread_local bool t_noalloc = false;
+thread_local std::vector<char>* t_pageable = nullptr;  // never freed, like the pinned staging
+
 void* pinned_down(size_t n)
 {
+    if (t_noalloc) {
+        if (!t_pageable) t_pageable = new std::vector<char>();
+        if (t_pageable->size() < n) t_pageable->resize(std::max<size_t>(n, 1 << 16));
+        return t_pageable->data();
+    }
     if (!t_down) t_down = new PinnedBuf();
     return t_down->get(n);
 }
@@ -1667,7 +1678,7 @@ static int sort_body(int key_type, const void* keys_in, const int32_t* rids_in, 
         return TJ_E_ALIAS;
 
     Exec x;
-    x.timed_on = timing_enabled() && !t_nested;
+    x.timed_on = timing_enabled() && !t_nested && !t_noalloc;
     x.sh = Shape{TJ_OP_SORT, key_type, false, false, true, n, 0};
     x.st = (hipStream_t)stream;
     int tier;
@@ -1816,7 +1827,7 @@ static int join_body(int key_type, const void* r_keys, const int32_t* r_rids, ui
     }
 
     Exec x;
-    x.timed_on = timing_enabled() && !t_nested;
+    x.timed_on = timing_enabled() && !t_nested && !t_noalloc;
     x.sh = Shape{mat ? TJ_OP_JOIN_MATERIALIZE : TJ_OP_JOIN_COUNT, key_type, true, mat, mat, n_r, n_s};
     x.st = (hipStream_t)stream;
     int tier;
@@ -1940,6 +1951,23 @@ static int join_impl(int key_type, const void* r_keys, const int32_t* r_rids, ui
     }
 }
 
+namespace tj {
+// The sort of tj_sort with the workspace given by the caller of this
+// function (the static scratch of tj_sort_static); no pinned staging and no
+// timing events.
+int sort_noalloc(int key_type, const void* keys_in, const int32_t* rids_in, uint64_t n, void* keys_out,
+                 int32_t* rids_out, void* workspace, uint64_t workspace_bytes, void* stream, tj_stats_t* stats)
+{
+    struct Flag {
+        bool saved = t_noalloc;
+        Flag() { t_noalloc = true; }
+        ~Flag() { t_noalloc = saved; }
+    } flag;
+    return sort_impl(key_type, keys_in, rids_in, n, keys_out, rids_out, workspace, workspace_bytes, stream,
+                     nullptr, stats);
+}
+}  // namespace tj
+
 extern "C" {
 
 int tj_sort(int key_type, const void* keys_in, const int32_t* rids_in, uint64_t n, void* keys_out,
@@ -2014,7 +2042,7 @@ static int rmi_train_body(int key_type, const void* keys_a, uint64_t n_a, const 
     if ((uintptr_t)workspace % ALIGN || workspace_bytes < need) return TJ_E_WORKSPACE;
     if (!permille) permille = DEFAULT_PERMILLE;
     Exec x;
-    x.timed_on = timing_enabled() && !t_nested;
+    x.timed_on = timing_enabled() && !t_nested && !t_noalloc;
     x.sh = Shape{TJ_OP_SORT, key_type, false, false, true, n_a, n_b};
     x.st = (hipStream_t)stream;
     char* p = (char*)workspace;

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "lib", "libtj.so")
 
 TJ_KEY_I32, TJ_KEY_I64 = 4, 8
 TJ_OP_SORT, TJ_OP_JOIN_COUNT, TJ_OP_JOIN_MATERIALIZE = 0, 1, 2
+TJ_STATIC_SCRATCH_BYTES = 256 << 20  # the device scratch of tj_sort_static
 TJ_OK, TJ_E_ARG, TJ_E_WORKSPACE, TJ_E_CAPACITY = 0, -1, -2, -3
 TJ_E_TOO_LARGE, TJ_E_ALIAS, TJ_E_HIP, TJ_E_INTERNAL = -4, -5, -6, -7
 
@@ -96,6 +97,7 @@ EXPORTS = {
     "tj_join_materialize": (ctypes.c_int, [ctypes.c_int, _P, _P, _u64, _P, _P, _u64, _P, _P, _u64,
                                            ctypes.POINTER(_u64), _P, _u64, _P, _P]),
     "tj_sort_ex": (ctypes.c_int, [ctypes.c_int, _P, _P, _u64, _P, _P, _P, _u64, _P, _P, _P]),
+    "tj_sort_static": (ctypes.c_int, [ctypes.c_int, _P, _P, _u64, _P, _P, _P, _P]),
     "tj_join_count_ex": (ctypes.c_int, [ctypes.c_int, _P, _u64, _P, _u64, ctypes.POINTER(_u64),
                                         _P, _u64, _P, _P, _P]),
     "tj_join_materialize_ex": (ctypes.c_int, [ctypes.c_int, _P, _P, _u64, _P, _P, _u64, _P, _P, _u64,
@@ -255,6 +257,26 @@ def sort(keys, rids, keys_out=None, rids_out=None, workspace=None, workspace_byt
                                  rids_out.data_ptr(), ws.data_ptr(), wsb, _stream(stream), ctypes.byref(opt),
                                  ctypes.byref(st)), "tj_sort_ex")
     return (keys_out, rids_out, st.as_dict()) if stats else (keys_out, rids_out)
+
+
+def sort_static(keys, rids, keys_out, rids_out, stream=None, stats: bool = False):
+    """tj_sort_static: the sort of tj_sort on the library's own device scratch.
+    Outputs are the caller's (allocated beforehand); the call allocates nothing."""
+    torch = _torch()
+    _dev(keys, "keys")
+    _dev(rids, "rids")
+    _dev(keys_out, "keys_out")
+    _dev(rids_out, "rids_out")
+    if rids.dtype != torch.int32 or rids.shape != keys.shape:
+        raise TypeError("rids must be int32 with the shape of keys")
+    if keys_out.dtype != keys.dtype or keys_out.shape != keys.shape or rids_out.dtype != torch.int32 \
+            or rids_out.shape != keys.shape:
+        raise TypeError("outputs must match the inputs' shapes and types")
+    st = Stats()
+    _check(load().tj_sort_static(_key_type(keys), keys.data_ptr(), rids.data_ptr(), keys.numel(),
+                                 keys_out.data_ptr(), rids_out.data_ptr(), _stream(stream), ctypes.byref(st)),
+           "tj_sort_static")
+    return st.as_dict() if stats else None
 
 
 def join_count(r_keys, s_keys, workspace=None, workspace_bytes=None, stream=None,

@@ -328,13 +328,26 @@ int tj_join_materialize_multi(int ncols, const int *key_types, const void *const
  * paper), which the server sub-allocates; it allocates no device memory
  * itself. Inputs and outputs are the caller's, as in the plain calls. A
  * request is admitted with the workspace it needs to finish; a join
- * materialisation is counted first (phase 1), then re-admitted ahead of newer
- * requests to write its pairs (phase 2; TJ_E_CAPACITY with the count when they
+ * materialisation is one call (TJ_E_CAPACITY with the count when its pairs
  * exceed `capacity`). Admitted work never waits for memory and releases its
  * workspace when it ends, so the queue always drains. Each request takes the
  * full workspace of its shape when that fits the arena, else the smallest one
  * (key ranges); a request whose smallest workspace exceeds the arena
  * completes at once with TJ_E_WORKSPACE.
+ *
+ * Fusion (continuous batching of small requests): when the head of the queue
+ * is a small sort or join materialisation (rows, both sides of a join, at most
+ * the server's fuse_max_rows; radix partitioner), the worker that admits it
+ * also takes the queued requests of the same op and key type that are small
+ * (up to fuse_max_requests and 16 * fuse_max_rows rows together, from the
+ * next 256 queued) and serves them with ONE composite-key call whose leading
+ * key column is the request's index in the batch. Each request's rows stay
+ * together in its own stable order, and its pairs form one contiguous stretch
+ * in its own canonical order, so every result equals the request run alone;
+ * one set of kernel launches replaces one per request. The fused call takes
+ * one arena block (combined columns, outputs and workspace); a join batch in
+ * which some request's pairs exceed its own capacity is served one request at
+ * a time in that block. result->fused reports the batch size.
  *
  * All functions are thread-safe. Inputs must stay valid and unchanged, and
  * outputs untouched, until the request completes.
@@ -359,11 +372,13 @@ typedef struct {
     int status;                  /* TJ_OK or the call's error */
     int op;
     uint64_t count;              /* sort: rows; joins: |R join S| (also on TJ_E_CAPACITY) */
-    double queue_ms;             /* submission to admission (phase 2 waits included) */
+    double queue_ms;             /* submission to admission */
     double run_ms;               /* time on a slot */
     double total_ms;             /* submission to completion */
     uint32_t learned;            /* the call used the learned first pass */
     uint32_t key_ranges;         /* 1 unless the budget forced key ranges */
+    uint32_t fused;              /* requests served by the same call (1: alone) */
+    uint32_t pad;
 } tj_result_t;
 /* Starts `slots` (1..64) worker threads with one HIP stream each (default
  * priority) on the current device. Errors: TJ_E_ARG, TJ_E_WORKSPACE
@@ -378,6 +393,11 @@ int tj_server_submit(tj_server_t *server, const tj_request_t *req, uint64_t *tic
  * ticket. Returns TJ_OK (the request's own status is result->status) or
  * TJ_E_ARG (unknown ticket, or a ticket another thread is already waiting for). */
 int tj_server_wait(tj_server_t *server, uint64_t ticket, tj_result_t *result);
+/* Fusion settings: requests of at most fuse_max_rows rows are fused, at most
+ * fuse_max_requests (2 .. 256) per call; fuse_max_rows = 0 or
+ * fuse_max_requests < 2 turns fusion off. Defaults: 65536 rows, 32 requests.
+ * Applies to requests admitted after the call. Errors: TJ_E_ARG. */
+int tj_server_configure(tj_server_t *server, uint64_t fuse_max_rows, uint32_t fuse_max_requests);
 /* Arena bytes reserved now and at most so far (workspaces of running requests). */
 int tj_server_memory(tj_server_t *server, uint64_t *in_use, uint64_t *peak);
 /* Finishes every queued request, stops the workers and frees the server

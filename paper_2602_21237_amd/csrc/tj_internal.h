@@ -249,4 +249,29 @@ hipError_t launch_rmi_fit(int key_bytes, const void* sorted, uint32_t M, uint32_
 hipError_t launch_rmi_eval(int key_bytes, const void* keys, uint64_t n, const tj_rmi_t* model,
                            uint16_t* out, hipStream_t st);
 
+
+// One request of a fused serving call (tj_fuse.hip): its inputs and outputs,
+// rows per side, and where its rows sit in the combined columns.
+struct FuseDesc {
+    const void* r_keys;
+    const int32_t* r_rids;
+    const void* s_keys;
+    const int32_t* s_rids;
+    void* out0;            // sort: keys_out; join: out_r
+    int32_t* out1;         // sort: rids_out; join: out_s
+    uint64_t n_r, n_s;
+    uint64_t off_r, off_s; // first row in the combined columns
+    uint64_t capacity;     // join: pairs out0/out1 hold
+};
+// gather: rows of every request into the combined columns (item index, keys,
+// and the request's row ids, or with positions != 0 the combined position)
+hipError_t launch_fuse_gather(int key_bytes, const FuseDesc* desc, uint32_t nreq, uint64_t max_rows, int side,
+                              int positions, int32_t* item, void* keys, int32_t* rids, hipStream_t st);
+hipError_t launch_fuse_scatter_sort(int key_bytes, const FuseDesc* desc, uint32_t nreq, uint64_t max_rows,
+                                    const void* keys, const int32_t* rids, hipStream_t st);
+hipError_t launch_fuse_bounds(const int32_t* pr, const int32_t* item_r, uint64_t count, uint32_t nreq,
+                              uint64_t* bounds, hipStream_t st);
+hipError_t launch_fuse_scatter_pairs(const FuseDesc* desc, uint32_t nreq, const uint64_t* bounds, const int32_t* pr,
+                                     const int32_t* ps, uint64_t count, hipStream_t st);
+
 }  // namespace tj

@@ -1,11 +1,12 @@
 // tj_serve.cpp - the serving loop (tj_server_*): requests admitted against a
 // device arena and run concurrently on per-slot HIP streams.
 //
-// Admission is first-come first-served over two queues: re-admissions (phase 2
-// of a join materialisation, after its count) go ahead of new requests. A
-// request is admitted when a slot is idle and the arena has room for its
-// workspace; the arena holds nothing else, so every admitted request finishes
-// and frees what it took, and the queue always drains.
+// Admission is first-come first-served. A request is admitted when a slot is
+// idle and the arena has room for its workspace; the arena holds nothing else,
+// so every admitted request finishes and frees what it took, and the queue
+// always drains. A join materialisation is one call: it writes its pairs when
+// they fit the caller's capacity and otherwise reports TJ_E_CAPACITY with the
+// count, so no separate count pass is needed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,12 +21,16 @@
 #include <thread>
 #include <vector>
 
-#include "tj.h"
+#include "tj_internal.h"
 
 namespace {
 
 constexpr uint64_t kAlign = 256;
 constexpr uint64_t kMaxRows = (1ull << 31) - 1;
+constexpr uint64_t kFuseDefaultRows = 1ull << 16;  // rows of a request the server fuses by default
+constexpr uint32_t kFuseDefaultRequests = 32;      // requests per fused call by default
+constexpr uint32_t kFuseMaxRequests = 256;
+constexpr size_t kFuseLookahead = 256;             // queue positions searched for partners
 
 inline uint64_t align_up(uint64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -102,8 +107,8 @@ private:
 struct Job {
     uint64_t ticket = 0;
     tj_request_t req{};
-    int phase = 0;                 // materialise: 1 count, 2 write pairs
-    uint64_t count = 0;            // known after phase 1
+    uint64_t count = 0;
+    uint32_t fused = 1;            // requests of the call that served this one
     char* ws = nullptr;            // arena block held while running
     uint64_t ws_bytes = 0;
     Clock::time_point submitted, admitted;
@@ -123,10 +128,45 @@ struct tj_server {
     int slots = 0;
     bool stopping = false;
     uint64_t next_ticket = 1;
-    std::deque<Job*> fresh, again;      // new requests; phase-2 re-admissions
+    std::deque<Job*> fresh;             // requests in arrival order
     std::map<uint64_t, Job*> jobs;      // every ticket not yet waited for
     std::vector<std::thread> workers;
     std::vector<hipStream_t> streams;
+    uint64_t fuse_rows = kFuseDefaultRows;       // 0: no fusion
+    uint32_t fuse_requests = kFuseDefaultRequests;
+
+    // Rows a request brings (both sides of a join).
+    static uint64_t rows_of(const tj_request_t& r) { return r.n_r + (r.op == TJ_OP_SORT ? 0 : r.n_s); }
+
+    bool fusable(const Job* j) const
+    {
+        const tj_request_t& r = j->req;
+        return fuse_rows && fuse_requests > 1 && j->res.status == TJ_OK && r.partitioner == TJ_PART_RADIX &&
+               (r.op == TJ_OP_SORT || r.op == TJ_OP_JOIN_MATERIALIZE) && rows_of(r) <= fuse_rows;
+    }
+
+    // Arena bytes of a fused call over `b`: the combined columns, the
+    // composite call's outputs and its full workspace, the descriptors and
+    // the pair boundaries.
+    uint64_t fused_bytes(const std::vector<Job*>& b)
+    {
+        const tj_request_t& r0 = b[0]->req;
+        const uint64_t kb = (uint64_t)r0.key_type;
+        uint64_t nr = 0, ns = 0, cap = 0;
+        for (const Job* j : b) {
+            nr += j->req.n_r;
+            ns += j->req.op == TJ_OP_SORT ? 0 : j->req.n_s;
+            cap += j->req.op == TJ_OP_SORT ? 0 : j->req.capacity;
+        }
+        const int types[2] = {TJ_KEY_I32, r0.key_type};
+        uint64_t mws = 0;
+        if (tj_multi_workspace_query(r0.op, 2, types, nr, ns, &mws) != TJ_OK) return ~0ull;
+        uint64_t bytes = mws + align_up(b.size() * sizeof(tj::FuseDesc)) + align_up((b.size() + 1) * 8);
+        if (r0.op == TJ_OP_SORT) bytes += 2 * (2 * align_up(nr * 4) + align_up(nr * kb));
+        else bytes += 2 * align_up(nr * 4) + align_up(nr * kb) + 2 * align_up(ns * 4) + align_up(ns * kb) +
+                      2 * align_up(cap * 4);
+        return bytes;
+    }
 
     // Workspace for a call of this shape: the full plan if it fits the arena,
     // else the minimum; 0 if even that does not fit.
@@ -144,8 +184,7 @@ struct tj_server {
     bool reserve(Job* j)
     {
         const tj_request_t& r = j->req;
-        const int op = r.op == TJ_OP_JOIN_MATERIALIZE && j->phase == 1 ? TJ_OP_JOIN_COUNT : r.op;
-        const uint64_t ws = ws_for(op, r.key_type, r.n_r, r.op == TJ_OP_SORT ? 0 : r.n_s);
+        const uint64_t ws = ws_for(r.op, r.key_type, r.n_r, r.op == TJ_OP_SORT ? 0 : r.n_s);
         if (ws == 0) {
             j->res.status = TJ_E_WORKSPACE;
             return true;  // completes without running
@@ -157,17 +196,163 @@ struct tj_server {
         return true;
     }
 
-    // Next job a worker may start (lock held): phase-2 jobs first, each queue in order.
-    Job* admit()
+    // Next work a worker may start (lock held), in arrival order: the head of
+    // the queue, with the queued requests it can be fused with (same op and
+    // key type, small) when the arena holds the fused call; the first job of
+    // a fused batch holds the batch's arena block.
+    bool admit(std::vector<Job*>& batch)
     {
-        for (std::deque<Job*>* q : {&again, &fresh}) {
-            if (q->empty()) continue;
-            Job* j = q->front();
-            if (!reserve(j)) return nullptr;  // the head waits for memory; nothing overtakes it
-            q->pop_front();
-            return j;
+        batch.clear();
+        if (fresh.empty()) return false;
+        Job* j = fresh.front();
+        if (fusable(j)) {
+            batch.push_back(j);
+            uint64_t rows = rows_of(j->req);
+            const uint64_t max_rows = fuse_rows * 16;
+            for (size_t i = 1; i < fresh.size() && i < kFuseLookahead && batch.size() < fuse_requests; i++) {
+                Job* k = fresh[i];
+                if (!fusable(k) || k->req.op != j->req.op || k->req.key_type != j->req.key_type) continue;
+                if (rows + rows_of(k->req) > max_rows) continue;
+                batch.push_back(k);
+                rows += rows_of(k->req);
+            }
+            while (batch.size() > 1) {
+                const uint64_t need = fused_bytes(batch);
+                char* a = need <= arena.bytes() ? arena.take(need) : nullptr;
+                if (a) {
+                    j->ws = a;
+                    j->ws_bytes = need;
+                    for (Job* k : batch) fresh.erase(std::find(fresh.begin(), fresh.end(), k));
+                    return true;
+                }
+                batch.pop_back();  // fewer partners: a smaller fused call
+            }
+            batch.clear();
         }
-        return nullptr;
+        if (!reserve(j)) return false;  // the head waits for memory; nothing overtakes it
+        fresh.pop_front();
+        batch.push_back(j);
+        return true;
+    }
+
+    // One fused call over `b` (b.size() >= 2) in the arena block of b[0];
+    // every job's status and count are set. A join batch whose pairs exceed
+    // the summed capacities (some request's own capacity is too small) runs
+    // its requests one by one in the same block instead.
+    void run_fused(std::vector<Job*>& b, hipStream_t st)
+    {
+        const tj_request_t& r0 = b[0]->req;
+        const int kt = r0.key_type;
+        const uint64_t kb = (uint64_t)kt;
+        const bool sort = r0.op == TJ_OP_SORT;
+        const uint32_t nreq = (uint32_t)b.size();
+        std::vector<tj::FuseDesc> desc(nreq);
+        uint64_t nr = 0, ns = 0, cap = 0, maxr = 0, maxs = 0;
+        for (uint32_t i = 0; i < nreq; i++) {
+            const tj_request_t& r = b[i]->req;
+            tj::FuseDesc& d = desc[i];
+            d.r_keys = r.r_keys;
+            d.r_rids = r.r_rids;
+            d.s_keys = sort ? nullptr : r.s_keys;
+            d.s_rids = sort ? nullptr : r.s_rids;
+            d.out0 = r.out0;
+            d.out1 = r.out1;
+            d.n_r = r.n_r;
+            d.n_s = sort ? 0 : r.n_s;
+            d.off_r = nr;
+            d.off_s = ns;
+            d.capacity = sort ? 0 : r.capacity;
+            nr += d.n_r;
+            ns += d.n_s;
+            cap += d.capacity;
+            maxr = std::max(maxr, d.n_r);
+            maxs = std::max(maxs, d.n_s);
+        }
+        char* p = b[0]->ws;
+        auto take = [&](uint64_t bytes) {
+            char* q = p;
+            p += align_up(bytes);
+            return q;
+        };
+        tj::FuseDesc* d_desc = (tj::FuseDesc*)take(nreq * sizeof(tj::FuseDesc));
+        uint64_t* d_bounds = (uint64_t*)take((nreq + 1) * 8);
+        const int types[2] = {TJ_KEY_I32, kt};
+        tj_stats_t stats{};
+        int rc = TJ_OK;
+        auto ck = [&](hipError_t e) {
+            if (e != hipSuccess && rc == TJ_OK) rc = TJ_E_HIP;
+        };
+        ck(hipMemcpyAsync(d_desc, desc.data(), nreq * sizeof(tj::FuseDesc), hipMemcpyHostToDevice, st));
+        if (sort) {
+            int32_t* item = (int32_t*)take(nr * 4);
+            void* keys = take(nr * kb);
+            int32_t* rids = (int32_t*)take(nr * 4);
+            int32_t* oitem = (int32_t*)take(nr * 4);
+            void* okeys = take(nr * kb);
+            int32_t* orids = (int32_t*)take(nr * 4);
+            char* mws = p;
+            const uint64_t mws_bytes = (uint64_t)(b[0]->ws + b[0]->ws_bytes - p);
+            if (rc == TJ_OK) ck(tj::launch_fuse_gather(kt, d_desc, nreq, maxr, 0, 0, item, keys, rids, st));
+            if (rc == TJ_OK) {
+                const void* kin[2] = {item, keys};
+                void* kout[2] = {oitem, okeys};
+                rc = tj_sort_multi(2, types, kin, rids, nr, kout, orids, mws, mws_bytes, st, &stats);
+            }
+            if (rc == TJ_OK) ck(tj::launch_fuse_scatter_sort(kt, d_desc, nreq, maxr, okeys, orids, st));
+            if (rc == TJ_OK) ck(hipStreamSynchronize(st));
+            for (Job* j : b) {
+                j->res.status = rc;
+                j->count = j->req.n_r;
+            }
+        } else {
+            int32_t* item_r = (int32_t*)take(nr * 4);
+            void* keys_r = take(nr * kb);
+            int32_t* pos_r = (int32_t*)take(nr * 4);
+            int32_t* item_s = (int32_t*)take(ns * 4);
+            void* keys_s = take(ns * kb);
+            int32_t* pos_s = (int32_t*)take(ns * 4);
+            int32_t* pr = (int32_t*)take(cap * 4);
+            int32_t* ps = (int32_t*)take(cap * 4);
+            char* mws = p;
+            const uint64_t mws_bytes = (uint64_t)(b[0]->ws + b[0]->ws_bytes - p);
+            if (rc == TJ_OK) ck(tj::launch_fuse_gather(kt, d_desc, nreq, maxr, 0, 1, item_r, keys_r, pos_r, st));
+            if (rc == TJ_OK) ck(tj::launch_fuse_gather(kt, d_desc, nreq, maxs, 1, 1, item_s, keys_s, pos_s, st));
+            uint64_t cnt = 0;
+            if (rc == TJ_OK) {
+                const void* rk[2] = {item_r, keys_r};
+                const void* sk[2] = {item_s, keys_s};
+                rc = tj_join_materialize_multi(2, types, rk, pos_r, nr, sk, pos_s, ns, cap ? pr : nullptr,
+                                               cap ? ps : nullptr, cap, &cnt, mws, mws_bytes, st, &stats);
+            }
+            if (rc == TJ_E_CAPACITY) {
+                // some request's pairs exceed its capacity: serve them one by one
+                for (Job* j : b) {
+                    const tj_request_t& r = j->req;
+                    tj_options_t opt{};
+                    uint64_t c = 0;
+                    j->res.status = tj_join_materialize_ex(r.key_type, r.r_keys, r.r_rids, r.n_r, r.s_keys, r.s_rids,
+                                                           r.n_s, (int32_t*)r.out0, r.out1, r.capacity, &c, b[0]->ws,
+                                                           b[0]->ws_bytes, st, &opt, &stats);
+                    j->count = c;
+                    j->fused = 1;
+                }
+                return;
+            }
+            std::vector<uint64_t> bounds(nreq + 1, 0);
+            if (rc == TJ_OK) ck(tj::launch_fuse_bounds(pr, item_r, cnt, nreq, d_bounds, st));
+            if (rc == TJ_OK) ck(tj::launch_fuse_scatter_pairs(d_desc, nreq, d_bounds, pr, ps, cnt, st));
+            if (rc == TJ_OK) ck(hipMemcpyAsync(bounds.data(), d_bounds, (nreq + 1) * 8, hipMemcpyDeviceToHost, st));
+            if (rc == TJ_OK) ck(hipStreamSynchronize(st));
+            for (uint32_t i = 0; i < nreq; i++) {
+                Job* j = b[i];
+                j->count = rc == TJ_OK ? bounds[i + 1] - bounds[i] : 0;
+                j->res.status = rc != TJ_OK ? rc : (j->count > j->req.capacity ? TJ_E_CAPACITY : TJ_OK);
+            }
+        }
+        for (Job* j : b) {
+            j->res.learned = 0;
+            j->res.key_ranges = stats.key_ranges;
+        }
     }
 
     void run(Job* j, hipStream_t st)
@@ -182,7 +367,7 @@ struct tj_server {
                 rc = tj_sort_ex(r.key_type, r.r_keys, r.r_rids, r.n_r, r.out0, r.out1, j->ws, j->ws_bytes, st, &opt,
                                 &stats);
                 j->count = r.n_r;
-            } else if (r.op == TJ_OP_JOIN_COUNT || j->phase == 1) {
+            } else if (r.op == TJ_OP_JOIN_COUNT) {
                 uint64_t cnt = 0;
                 rc = tj_join_count_ex(r.key_type, r.r_keys, r.n_r, r.s_keys, r.n_s, &cnt, j->ws, j->ws_bytes, st, &opt,
                                       &stats);
@@ -192,7 +377,7 @@ struct tj_server {
                 rc = tj_join_materialize_ex(r.key_type, r.r_keys, r.r_rids, r.n_r, r.s_keys, r.s_rids, r.n_s,
                                             (int32_t*)r.out0, r.out1, r.capacity, &cnt, j->ws, j->ws_bytes, st, &opt,
                                             &stats);
-                if ((rc == TJ_OK || rc == TJ_E_CAPACITY) && cnt != j->count) rc = TJ_E_INTERNAL;
+                j->count = cnt;
             }
         }
         j->res.status = rc;
@@ -205,36 +390,42 @@ struct tj_server {
         (void)hipSetDevice(device);
         hipStream_t st = streams[slot];
         std::unique_lock<std::mutex> lk(mu);
+        std::vector<Job*> batch;
         for (;;) {
-            Job* j = nullptr;
-            cv_work.wait(lk, [&] { return (j = admit()) != nullptr || (stopping && fresh.empty() && again.empty()); });
-            if (!j) return;
-            j->admitted = Clock::now();
+            bool got = false;
+            cv_work.wait(lk, [&] { return (got = admit(batch)) || (stopping && fresh.empty()); });
+            if (!got) return;
+            const auto start = Clock::now();
+            for (Job* j : batch) {
+                j->admitted = start;
+                j->fused = (uint32_t)batch.size();
+            }
             lk.unlock();
-            run(j, st);
+            if (batch.size() > 1) {
+                try {
+                    run_fused(batch, st);
+                } catch (...) {  // host memory ran out: nothing crosses the C ABI
+                    for (Job* j : batch) j->res.status = TJ_E_INTERNAL;
+                }
+            } else {
+                run(batch[0], st);
+            }
             const auto end = Clock::now();
             lk.lock();
-            j->run_ms += ms_between(j->admitted, end);
-            arena.give(j->ws);
-            j->ws = nullptr;
-            bool phase1 = j->req.op == TJ_OP_JOIN_MATERIALIZE && j->phase == 1 && j->res.status == TJ_OK;
-            if (phase1 && j->count > j->req.capacity) {
-                j->res.status = TJ_E_CAPACITY;  // nothing to write: the pairs would not fit
-                phase1 = false;
-            }
-            if (phase1) {
-                j->phase = 2;
-                again.push_back(j);
-            } else {
+            arena.give(batch[0]->ws);
+            batch[0]->ws = nullptr;
+            for (Job* j : batch) {
+                j->run_ms += ms_between(j->admitted, end);
                 const int st_ = j->res.status;
                 j->res.op = j->req.op;
                 j->res.count = st_ == TJ_OK || st_ == TJ_E_CAPACITY ? j->count : 0;
                 j->res.run_ms = j->run_ms;
                 j->res.total_ms = ms_between(j->submitted, end);
                 j->res.queue_ms = j->res.total_ms - j->run_ms;
+                j->res.fused = j->fused;
                 j->done = true;
-                cv_done.notify_all();
             }
+            cv_done.notify_all();
             cv_work.notify_all();  // memory was freed: the queue head may fit now
         }
     }
@@ -326,7 +517,6 @@ int tj_server_submit(tj_server_t* s, const tj_request_t* req, uint64_t* ticket)
     Job* j = new (std::nothrow) Job();
     if (!j) return TJ_E_INTERNAL;
     j->req = r;
-    j->phase = r.op == TJ_OP_JOIN_MATERIALIZE ? 1 : 0;
     j->submitted = Clock::now();
     {
         std::lock_guard<std::mutex> lk(s->mu);
@@ -356,6 +546,15 @@ int tj_server_wait(tj_server_t* s, uint64_t ticket, tj_result_t* result)
     *result = j->res;
     s->jobs.erase(ticket);
     delete j;
+    return TJ_OK;
+}
+
+int tj_server_configure(tj_server_t* s, uint64_t fuse_max_rows, uint32_t fuse_max_requests)
+{
+    if (!s || fuse_max_requests > kFuseMaxRequests || fuse_max_rows > kMaxRows) return TJ_E_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->fuse_rows = fuse_max_rows;
+    s->fuse_requests = fuse_max_requests;
     return TJ_OK;
 }
 

@@ -116,6 +116,7 @@ EXPORTS = {
     "tj_server_submit": (ctypes.c_int, [_P, _P, ctypes.POINTER(_u64)]),
     "tj_server_wait": (ctypes.c_int, [_P, _u64, _P]),
     "tj_server_memory": (ctypes.c_int, [_P, ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),
+    "tj_server_configure": (ctypes.c_int, [_P, _u64, ctypes.c_uint32]),
     "tj_server_destroy": (ctypes.c_int, [_P]),
     "tj_select_workspace_query": (ctypes.c_int, [_u64, _u64, ctypes.POINTER(_u64)]),
     "tj_select_path": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _P, _u64, _P, _u64, _P, _P, _P, _P, _u64, _P]),
@@ -561,7 +562,8 @@ class Request(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("op", ctypes.c_int), ("count", _u64),
                 ("queue_ms", ctypes.c_double), ("run_ms", ctypes.c_double),
-                ("total_ms", ctypes.c_double), ("learned", ctypes.c_uint32), ("key_ranges", ctypes.c_uint32)]
+                ("total_ms", ctypes.c_double), ("learned", ctypes.c_uint32), ("key_ranges", ctypes.c_uint32),
+                ("fused", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
 
 
 class Server:
@@ -613,12 +615,18 @@ class Server:
         _check(load().tj_server_wait(self._h, ticket, ctypes.byref(r)), "tj_server_wait")
         op, _, out0, out1 = self._keep.pop(ticket)
         out = {"status": r.status, "op": r.op, "count": int(r.count), "queue_ms": r.queue_ms, "run_ms": r.run_ms,
-               "total_ms": r.total_ms, "learned": int(r.learned), "key_ranges": int(r.key_ranges)}
+               "total_ms": r.total_ms, "learned": int(r.learned), "key_ranges": int(r.key_ranges),
+               "fused": int(r.fused)}
         if r.status == TJ_OK and op == TJ_OP_SORT:
             out["keys"], out["rids"] = out0, out1
         elif r.status == TJ_OK and op == TJ_OP_JOIN_MATERIALIZE:
             out["out_r"], out["out_s"] = out0[:r.count], out1[:r.count]
         return out
+
+    def configure(self, fuse_max_rows: int, fuse_max_requests: int = 32) -> None:
+        """tj_server_configure: fuse requests of at most fuse_max_rows rows,
+        at most fuse_max_requests per call (fuse_max_rows = 0: no fusion)."""
+        _check(load().tj_server_configure(self._h, fuse_max_rows, fuse_max_requests), "tj_server_configure")
 
     def memory(self):
         """(arena bytes reserved now, peak so far)."""

@@ -152,3 +152,95 @@ def test_many_small_requests_overlap(tj):
     span = max(r["total_ms"] for r in res)
     busy = sum(r["run_ms"] for r in res)
     assert busy > span, (busy, span)
+
+
+def _small_requests(count, seed):
+    """Small sorts and joins (0 .. 30,000 rows per side), int32 and int64 keys,
+    uniform or Zipf(0.8), permuted row ids: all below the fusion threshold."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(rng.integers(0, 30_000)) if i % 7 else int(rng.integers(0, 3))
+        op = "sort" if i % 2 else "join"
+        if i % 3 == 0:
+            w = tjgen.small_uniform(seed=seed * 1000 + i, n=n, bits=int(rng.integers(8, 24)), rid_perm=True)
+        else:
+            w = tjgen.paper_shaped(0.8 if i % 4 else 0.0, seed=seed * 1000 + i, n=n, rid_perm=True)
+        out.append((op, w))
+    return out
+
+
+@pytest.mark.parametrize("slots", [1, 3])
+def test_fused_small_requests_match_alone(tj, slots):
+    """Small requests that queue up behind a large one are served by fused
+    calls (one composite-key call per batch): every result equals the request
+    run alone and the oracle, and batches of more than one request formed."""
+    reqs = _small_requests(96, seed=5 + slots)
+    devs = [{k: dev(v) for k, v in w.items()} for _, w in reqs]
+    alone = [_alone(tj, op, d, "radix") for (op, _), d in zip(reqs, devs)]
+    big = tjgen.sort_uniform64(1 << 24)["keys"]
+    d_big = dev(big)
+    d_big_r = torch.arange(big.size, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    with tj.tj.Server(2 << 30, slots=slots) as srv:
+        blockers = [srv.sort(d_big, d_big_r) for _ in range(slots)]  # keep every slot busy meanwhile
+        tickets = [_submit(srv, op, d, "radix", _cap(op, w)) for (op, w), d in zip(reqs, devs)]
+        for t in blockers:
+            assert srv.wait(t)["status"] == 0
+        fused = []
+        for (op, w), t, a in zip(reqs, tickets, alone):
+            res = srv.wait(t)
+            assert res["status"] == 0, res
+            fused.append(res["fused"])
+            if op == "sort":
+                assert torch.equal(res["keys"], a[0]) and torch.equal(res["rids"], a[1])
+            else:
+                assert torch.equal(res["out_r"], a[0]) and torch.equal(res["out_s"], a[1])
+            _check_oracle(op, w, res)
+        assert srv.memory()[0] == 0
+    assert max(fused) > 1, fused
+
+
+def test_fused_batch_with_a_short_capacity(tj):
+    """One join of a fused batch has capacity for one pair less than it
+    needs: it reports TJ_E_CAPACITY with its count and writes nothing at or
+    beyond its capacity; the other requests of the batch are unaffected."""
+    reqs = _small_requests(12, seed=11)
+    reqs = [(op, w) for op, w in reqs if op == "join" and len(w["r_keys"]) > 100]
+    devs = [{k: dev(v) for k, v in w.items()} for _, w in reqs]
+    caps = [oracle.join_count(w["r_keys"], w["s_keys"]) for _, w in reqs]
+    assert caps[0] > 0
+    guard = 1 << 16
+    outs = []
+    with tj.tj.Server(1 << 30, slots=1) as srv:
+        tickets = []
+        for i, ((op, w), d) in enumerate(zip(reqs, devs)):
+            cap = caps[i] - 1 if i == 0 else caps[i]
+            o_r = torch.full((cap + guard,), -7, dtype=torch.int32, device="cuda")
+            o_s = torch.full((cap + guard,), -7, dtype=torch.int32, device="cuda")
+            outs.append((o_r, o_s, cap))
+            tickets.append(srv.join(d["r_keys"], d["r_rids"], d["s_keys"], d["s_rids"], capacity=cap,
+                                    out_r=o_r, out_s=o_s))
+        for i, ((op, w), t) in enumerate(zip(reqs, tickets)):
+            res = srv.wait(t)
+            o_r, o_s, cap = outs[i]
+            assert bool((o_r[cap:] == -7).all().item()) and bool((o_s[cap:] == -7).all().item())
+            if i == 0:
+                assert res["status"] == tj.tj.TJ_E_CAPACITY and res["count"] == caps[0]
+            else:
+                assert res["status"] == 0
+                _check_oracle(op, w, res)
+
+
+def test_fusion_can_be_turned_off(tj):
+    reqs = _small_requests(24, seed=13)
+    devs = [{k: dev(v) for k, v in w.items()} for _, w in reqs]
+    with tj.tj.Server(1 << 30, slots=2) as srv:
+        srv.configure(0)
+        tickets = [_submit(srv, op, d, "radix", _cap(op, w)) for (op, w), d in zip(reqs, devs)]
+        for (op, w), t in zip(reqs, tickets):
+            res = srv.wait(t)
+            assert res["status"] == 0 and res["fused"] == 1
+            _check_oracle(op, w, res)
+        with pytest.raises(tj.TjError):
+            srv.configure(1 << 16, 1000)  # more requests per call than allowed

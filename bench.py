@@ -13,7 +13,11 @@ seeds and are resident in HBM before timing starts.
 value = (sort rows + |R| + |S|) / step time  [tuples/s], whole job.
 roofline: the kernel family with the most time; algorithmic bytes per launch
 over its HIP-event-measured average duration, against the 8 TB/s HBM peak.
-cpu_baseline: the CPU oracle (single thread) on a 1/32 sample of the workload.
+cpu_baseline: the CPU oracle (single thread) on a 1/32 sample of the workload;
+beside it the oracle built -O3 -march=native on this host and pinned to one
+core: P50/P99 of C1 and of the paper-shaped workload, and the sort and join
+times of the path-selection sweep (2^8 ... 2^22 rows per side), from which the
+size where the tensor path overtakes it is read.
 paper_shaped: P50/P99 latency of the |R| = |S| = 10^6 workload at workspace
 budgets of 1 MiB, 64 MiB and unlimited, theta in {0, 0.99}.
 learned_vs_radix: |R| = |S| = 2^28 int64 keys from a lognormal, an interval
@@ -26,6 +30,14 @@ path_selection: the execution-time selector (HyperLogLog sketch of the join
 and sort keys) on the step's inputs, its indicators against the exact counts,
 and the join latency of the tensor path from 2^10 to 2^22 rows per side with
 the decision taken at each size.
+stream_copy: a hand-written 16-byte streaming copy of 4 GiB, the bandwidth a
+read-once write-once kernel reaches (the practical ceiling beside the peak).
+c1_small: |R| = |S| = 10^5 int32 keys uniform in [0, 2^20): GPU P50/P99 of the
+sort and the join over 100 calls.
+hbm_zipf: the HBM-scale join with Zipf(0.99) matches (hot keys with
+multiplicity 4, 1.37e9 pairs) and a sort of its 2^29 skewed S keys, timed
+like the step, with its kernel families and roofline; plus the standalone sort
+of 2^29 keys uniform over [0, 2^40).
 serving: Poisson arrivals at 50, 200, 800 and 3200 requests/s of sorts and joins
 (per-side rows log-uniform in [10^3, 10^7]) against the serving loop with a
 32 GiB workspace budget, 8 slots against one at a time: P50/P99/P99.9 latency
@@ -260,16 +272,21 @@ def learned_vs_radix(tj, torch, n: int, repeats: int):
     return {"n_per_relation": n, "repeats": repeats, "dists": out}
 
 
-def serving(tj, torch, rates, nreq: int, pool: int = 48, arena_gib: int = 32, slots: int = 8):
+def serving(tj, torch, rates, nreq: int, pool: int = 64, arena_gib: int = 32, slots: int = 8,
+            saturate: bool = True):
     """Poisson stream of sort and join requests against the serving loop.
 
     Pool: `pool` requests resident on the GPU, per-side rows log-uniform in
     [10^3, 10^7], int64 keys (R keys unique over [0, 2^40), S foreign keys with
     Zipf(0) or Zipf(0.8) over R's keys, half each), op sort (of S) or join
     (materialised pairs), half each. Each rate runs `nreq` arrivals (seeded
-    exponential gaps) twice: on `slots` concurrent slots, and one request at a
-    time (one slot); latency runs from the scheduled arrival to completion.
-    Every result is compared with the same request run alone."""
+    exponential gaps; pool entries drawn uniformly) in three modes: `slots`
+    concurrent slots with fusion of small requests (the default), the same
+    without fusion (rates of 800/s and more), and one request at a time (one
+    slot, no fusion). Latency runs from the scheduled arrival to completion. With
+    `saturate`, all `nreq` arrive at once as well: requests per second over the
+    makespan is the highest rate each mode sustains on this mix. Every result is
+    compared with the same request run alone."""
     import threading
     import tjgen
     rng = np.random.default_rng(2602)
@@ -293,89 +310,112 @@ def serving(tj, torch, rates, nreq: int, pool: int = 48, arena_gib: int = 32, sl
                         torch.empty(max(e["count"], 1), dtype=torch.int32, device="cuda"))
         reqs.append(e)
     torch.cuda.synchronize()
-    out = {"pool": pool, "requests_per_rate": nreq, "arena_GiB": arena_gib, "slots": slots, "rates": {}}
-    for rate in rates:
-        gaps = np.random.default_rng(int(rate)).exponential(1.0 / rate, nreq)
-        sched = np.cumsum(gaps) - gaps[0]
-        order = np.random.default_rng(int(rate) + 1).integers(0, pool, nreq)
-        res_rate = {}
-        for mode, nslots in (("served", slots), ("one_at_a_time", 1)):
-            srv = tj.tj.Server(arena_gib << 30, slots=nslots)
-            # warm-up: every slot's first call sets up its host-side staging
-            warm = [srv.sort(reqs[i % pool]["d"]["s_keys"], reqs[i % pool]["d"]["s_rids"])
-                    for i in range(1, 4 * nslots, 4)]
-            for t in warm:
-                srv.wait(t)
-            busy = set()
-            lock = threading.Lock()
-            done = []
-            tickets = []  # (ticket, entry, scheduled time, submit delay)
-            cv = threading.Condition()
+    rows = [e["tuples"] for e in reqs]
+    out = {"pool": pool, "requests_per_rate": nreq, "arena_GiB": arena_gib, "slots": slots,
+           "pool_mean_rows": round(float(np.mean(rows)), 1), "rates": {}}
 
-            def waiter():
-                k = 0
-                while k < nreq:
-                    with cv:
-                        while len(tickets) <= k:
-                            cv.wait()
-                        t, ei, ts, delay = tickets[k]
-                    r = srv.wait(t)
-                    e = reqs[ei]
-                    ok = r["status"] == 0
-                    if ok and e["op"] == "sort":
-                        ok = torch.equal(r["keys"], e["ref"][0]) and torch.equal(r["rids"], e["ref"][1])
-                    elif ok:
-                        ok = torch.equal(r["out_r"], e["ref"][0]) and torch.equal(r["out_s"], e["ref"][1])
-                    with lock:
-                        busy.discard(ei)
-                    done.append((delay + r["total_ms"], r["queue_ms"], r["run_ms"], ok, e["tuples"],
-                                 ts * 1e3 + delay + r["total_ms"]))
-                    k += 1
+    def run(sched, order, nslots, fuse):
+        srv = tj.tj.Server(arena_gib << 30, slots=nslots)
+        if not fuse:
+            srv.configure(0)
+        # warm-up: every slot's first call sets up its host-side staging
+        warm = [srv.sort(reqs[i % pool]["d"]["s_keys"], reqs[i % pool]["d"]["s_rids"])
+                for i in range(1, 4 * nslots, 4)]
+        for t in warm:
+            srv.wait(t)
+        busy = set()
+        lock = threading.Lock()
+        done = []
+        tickets = []  # (ticket, entry, scheduled time, submit delay)
+        cv = threading.Condition()
 
-            th = threading.Thread(target=waiter)
-            th.start()
-            t0 = time.perf_counter()
-            for i in range(nreq):
-                ei = int(order[i])
-                while True:  # an entry's output buffers serve one request at a time
-                    with lock:
-                        free = [x for x in range(pool) if (ei + x) % pool not in busy]
-                        if free:
-                            ei = (ei + free[0]) % pool
-                            busy.add(ei)
-                            break
-                    time.sleep(0.0005)  # every entry in flight: the arrival waits (counted in its latency)
-                now = time.perf_counter() - t0
-                if sched[i] > now:
-                    time.sleep(sched[i] - now)
-                delay = (time.perf_counter() - t0 - sched[i]) * 1e3
-                e = reqs[ei]
-                d = e["d"]
-                if e["op"] == "sort":
-                    t = srv.sort(d["s_keys"], d["s_rids"], keys_out=e["out"][0], rids_out=e["out"][1])
-                else:
-                    t = srv.join(d["r_keys"], d["r_rids"], d["s_keys"], d["s_rids"], capacity=e["count"],
-                                 out_r=e["out"][0], out_s=e["out"][1])
+        def waiter():
+            k = 0
+            while k < nreq:
                 with cv:
-                    tickets.append((t, ei, sched[i], delay))
-                    cv.notify()
-            th.join()
-            peak = srv.memory()[1]
-            srv.close()
-            lat = [x[0] for x in done]
-            makespan_ms = max(x[5] for x in done)
-            tuples = sum(x[4] for x in done)
-            assert all(x[3] for x in done), "a served result differs from the same request run alone"
-            res_rate[mode] = {"p50_ms": round(pct(lat, 0.5), 3), "p99_ms": round(pct(lat, 0.99), 3),
-                              "p999_ms": round(pct(lat, 0.999), 3), "mean_ms": round(float(np.mean(lat)), 3),
-                              "tuples_per_s": round(tuples / (makespan_ms * 1e-3), 1),
-                              "mean_queue_ms": round(float(np.mean([x[1] for x in done])), 3),
-                              "mean_run_ms": round(float(np.mean([x[2] for x in done])), 3),
-                              "peak_arena_GB": round(peak / 1e9, 3), "results_identical": True}
-            log("serving %g req/s %s: P50 %.2f P99 %.2f P99.9 %.2f ms, %.3g tuples/s" %
-                (rate, mode, res_rate[mode]["p50_ms"], res_rate[mode]["p99_ms"], res_rate[mode]["p999_ms"],
-                 res_rate[mode]["tuples_per_s"]))
-        out["rates"]["%g" % rate] = res_rate
+                    while len(tickets) <= k:
+                        cv.wait()
+                    t, ei, ts, delay = tickets[k]
+                r = srv.wait(t)
+                e = reqs[ei]
+                ok = r["status"] == 0
+                if ok and e["op"] == "sort":
+                    ok = torch.equal(r["keys"], e["ref"][0]) and torch.equal(r["rids"], e["ref"][1])
+                elif ok:
+                    ok = torch.equal(r["out_r"], e["ref"][0]) and torch.equal(r["out_s"], e["ref"][1])
+                with lock:
+                    busy.discard(ei)
+                done.append((delay + r["total_ms"], r["queue_ms"], r["run_ms"], ok, e["tuples"],
+                             ts * 1e3 + delay + r["total_ms"], r["fused"]))
+                k += 1
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        t0 = time.perf_counter()
+        for i in range(nreq):
+            ei = int(order[i])
+            while True:  # an entry's output buffers serve one request at a time
+                with lock:
+                    free = [x for x in range(pool) if (ei + x) % pool not in busy]
+                    if free:
+                        ei = (ei + free[0]) % pool
+                        busy.add(ei)
+                        break
+                time.sleep(0.0005)  # every entry in flight: the arrival waits (counted in its latency)
+            now = time.perf_counter() - t0
+            if sched[i] > now:
+                time.sleep(sched[i] - now)
+            delay = (time.perf_counter() - t0 - sched[i]) * 1e3
+            e = reqs[ei]
+            d = e["d"]
+            if e["op"] == "sort":
+                t = srv.sort(d["s_keys"], d["s_rids"], keys_out=e["out"][0], rids_out=e["out"][1])
+            else:
+                t = srv.join(d["r_keys"], d["r_rids"], d["s_keys"], d["s_rids"], capacity=e["count"],
+                             out_r=e["out"][0], out_s=e["out"][1])
+            with cv:
+                tickets.append((t, ei, sched[i], delay))
+                cv.notify()
+        th.join()
+        peak = srv.memory()[1]
+        srv.close()
+        lat = [x[0] for x in done]
+        makespan_ms = max(x[5] for x in done)
+        tuples = sum(x[4] for x in done)
+        fused = [x[6] for x in done]
+        assert all(x[3] for x in done), "a served result differs from the same request run alone"
+        return {"p50_ms": round(pct(lat, 0.5), 3), "p99_ms": round(pct(lat, 0.99), 3),
+                "p999_ms": round(pct(lat, 0.999), 3), "mean_ms": round(float(np.mean(lat)), 3),
+                "tuples_per_s": round(tuples / (makespan_ms * 1e-3), 1),
+                "requests_per_s": round(nreq / (makespan_ms * 1e-3), 1),
+                "mean_queue_ms": round(float(np.mean([x[1] for x in done])), 3),
+                "mean_run_ms": round(float(np.mean([x[2] for x in done])), 3),
+                "fused_requests_frac": round(float(np.mean([f > 1 for f in fused])), 4),
+                "max_fused_batch": int(max(fused)),
+                "peak_arena_GB": round(peak / 1e9, 3), "results_identical": True}
+
+    cases = [(r, "%g" % r) for r in rates] + ([(float("inf"), "saturated")] if saturate else [])
+    for rate, name in cases:
+        if np.isinf(rate):
+            sched = np.zeros(nreq)
+        else:
+            gaps = np.random.default_rng(int(rate)).exponential(1.0 / rate, nreq)
+            sched = np.cumsum(gaps) - gaps[0]
+        order = np.random.default_rng(7 if np.isinf(rate) else int(rate) + 1).integers(0, pool, nreq)
+        modes = [("served", slots, True)]
+        if rate >= 800:
+            modes.append(("served_no_fusion", slots, False))
+        modes.append(("one_at_a_time", 1, False))
+        res_rate = {}
+        for mode, nslots, fuse in modes:
+            res_rate[mode] = r = run(sched, order, nslots, fuse)
+            log("serving %s %s: P50 %.2f P99 %.2f P99.9 %.2f ms, %.1f req/s, %.3g tuples/s, %.1f%% fused" %
+                (name, mode, r["p50_ms"], r["p99_ms"], r["p999_ms"], r["requests_per_s"], r["tuples_per_s"],
+                 100 * r["fused_requests_frac"]))
+        out["rates"][name] = res_rate
+    if saturate:
+        out["max_sustainable_requests_per_s"] = {m: v["requests_per_s"]
+                                                 for m, v in out["rates"]["saturated"].items()}
     del reqs
     torch.cuda.empty_cache()
     return out
@@ -468,31 +508,283 @@ def path_selection(tj, torch, d_rk, d_sk_join, d_sort, join_count: int, repeats:
         log("path selection %s: %.3f ms, %s" % (name, t, rec["path"]))
     del ws
     sweep = []
-    rng = np.random.default_rng(17)
-    for lg in range(10, 23, 2):
-        n = 1 << lg
-        r = torch.from_numpy(rng.choice(1 << 40, n, replace=False)).to("cuda")  # distinct R keys
-        s = r[torch.from_numpy(rng.integers(0, n, n)).to("cuda")]
-        rid = torch.arange(n, dtype=torch.int32, device="cuda")
-        sel_ms, join_ms = [], []
-        for i in range(6):
+    import tjgen
+    for lg in CROSSOVER_LOGS:
+        w = tjgen.crossover(lg)
+        r, s = torch.from_numpy(w["r_keys"]).to("cuda"), torch.from_numpy(w["s_keys"]).to("cuda")
+        rr, sr = torch.from_numpy(w["r_rids"]).to("cuda"), torch.from_numpy(w["s_rids"]).to("cuda")
+        sel_ms, join_ms, sort_ms = [], [], []
+        for i in range(11):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             sel = tj.select_path(r, s)
             t1 = time.perf_counter()
-            pr, _ = tj.join(r, rid, s, rid)
+            pr, _ = tj.join(r, rr, s, sr)
             torch.cuda.synchronize()
             t2 = time.perf_counter()
+            tj.sort(s, sr)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
             if i:
                 sel_ms.append((t1 - t0) * 1e3)
                 join_ms.append((t2 - t1) * 1e3)
-        sweep.append({"rows_per_side": n, "select_ms": round(pct(sel_ms, 0.5), 4),
-                      "join_ms": round(pct(join_ms, 0.5), 4), "pairs": int(pr.numel()),
-                      "est_output": round(sel["est_output"], 1),
+                sort_ms.append((t3 - t2) * 1e3)
+        assert pr.numel() == w.expected_count
+        sweep.append({"rows_per_side": 1 << lg, "select_ms": round(pct(sel_ms, 0.5), 4),
+                      "join_ms": round(pct(join_ms, 0.5), 4), "sort_ms": round(pct(sort_ms, 0.5), 4),
+                      "pairs": int(pr.numel()), "est_output": round(sel["est_output"], 1),
                       "path": "tensor" if sel["path"] else "linear", "reasons": sel["reasons"]})
     out["sweep"] = sweep
-    out["thresholds"] = {"min_rows": 1 << 16, "min_output": 1 << 18}
+    out["thresholds"] = {"min_rows": tj.TJ_SELECT_DEFAULT_MIN_ROWS, "min_output": tj.TJ_SELECT_DEFAULT_MIN_OUTPUT}
     return out
+
+
+CROSSOVER_LOGS = tuple(range(8, 23, 2))
+
+
+def stream_copy(tj, torch, mib: int = 4096, repeats: int = 10):
+    """Bandwidth of the hand-written streaming copy and of torch's copy_ on the
+    same buffers (HIP events on the current stream, median of `repeats`)."""
+    nb = mib << 20
+    src = torch.ones(nb // 8, dtype=torch.int64, device="cuda")
+    dst = torch.empty_like(src)
+    out = {"bytes_copied": nb}
+    for name, f in (("hand_written", lambda: tj.debug_stream_copy(src, dst)), ("torch_copy", lambda: dst.copy_(src))):
+        ms = []
+        for i in range(repeats + 2):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            f()
+            b.record()
+            b.synchronize()
+            if i >= 2:
+                ms.append(a.elapsed_time(b))
+        t = pct(ms, 0.5)
+        gbs = 2 * nb / (t * 1e-3) / 1e9
+        out[name] = {"ms": round(t, 4), "GBs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
+    assert torch.equal(src[:1 << 20], dst[:1 << 20]), "copy wrong"
+    out["achievable_GBs"] = max(out["hand_written"]["GBs"], out["torch_copy"]["GBs"])
+    log("stream copy: %.1f GB/s hand-written, %.1f GB/s torch" % (out["hand_written"]["GBs"],
+                                                                  out["torch_copy"]["GBs"]))
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
+def c1_small(tj, torch, repeats: int = 100, warmup: int = 10):
+    """GPU P50/P99 (wall clock, synchronised) of the sort of R and the join of
+    R and S at |R| = |S| = 10^5 int32 keys uniform in [0, 2^20)."""
+    import tjgen
+    w = tjgen.small_uniform()
+    d = {k: torch.from_numpy(v).to("cuda") for k, v in w.items()}
+    count = tj.join_count(d["r_keys"], d["s_keys"])
+    out_r = torch.empty(max(count, 1), dtype=torch.int32, device="cuda")
+    out_s = torch.empty_like(out_r)
+    ko, ro = torch.empty_like(d["r_keys"]), torch.empty_like(d["r_rids"])
+    ws_s = torch.empty(tj.workspace_query(tj.TJ_OP_SORT, tj.TJ_KEY_I32, 10 ** 5)[1], dtype=torch.uint8,
+                       device="cuda")
+    ws_j = torch.empty(tj.workspace_query(tj.TJ_OP_JOIN_MATERIALIZE, tj.TJ_KEY_I32, 10 ** 5, 10 ** 5)[1],
+                       dtype=torch.uint8, device="cuda")
+    ops = {"sort": lambda: tj.sort(d["r_keys"], d["r_rids"], keys_out=ko, rids_out=ro, workspace=ws_s),
+           "join": lambda: tj.join(d["r_keys"], d["r_rids"], d["s_keys"], d["s_rids"], capacity=count,
+                                   out_r=out_r, out_s=out_s, workspace=ws_j)}
+    res = {"rows_per_side": 10 ** 5, "join_count": count, "repeats": repeats}
+    for op, f in ops.items():
+        times = []
+        for i in range(warmup + repeats):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            f()
+            torch.cuda.synchronize()
+            if i >= warmup:
+                times.append((time.perf_counter() - t0) * 1e3)
+        res[op] = {"p50_ms": round(pct(times, 0.5), 4), "p99_ms": round(pct(times, 0.99), 4)}
+    log("C1: sort P50 %.3f ms, join P50 %.3f ms" % (res["sort"]["p50_ms"], res["join"]["p50_ms"]))
+    del d, out_r, out_s, ko, ro, ws_s, ws_j
+    return res
+
+
+def hbm_variants(tj, torch, steps: int):
+    """The Zipf(0.99) HBM-scale join (R: 2^27 rows, the 2^20 hottest keys 4
+    times; S: 2^29 rows, 80% matched by Zipf(0.99)) with a sort of its S keys,
+    timed like the step; then the standalone sort of 2^29 keys uniform over
+    [0, 2^40)."""
+    import tjgen
+    log("hbm zipf: generating")
+    w = tjgen.hbm_scale(0.99)
+    n_r, n_s = w["r_keys"].size, w["s_keys"].size
+    d_rk = torch.from_numpy(w["r_keys"]).to("cuda")
+    d_rr = torch.from_numpy(w["r_rids"]).to("cuda")
+    d_sk = torch.from_numpy(w["s_keys"]).to("cuda")
+    d_sr = torch.from_numpy(w["s_rids"]).to("cuda")
+    expected = w.expected_count
+    del w
+    cap = 4 * n_s
+    out_r = torch.empty(cap, dtype=torch.int32, device="cuda")
+    out_s = torch.empty(cap, dtype=torch.int32, device="cuda")
+    ko, ro = torch.empty_like(d_sk), torch.empty_like(d_sr)
+    ws_sort = torch.empty(tj.workspace_query(tj.TJ_OP_SORT, tj.TJ_KEY_I64, n_s)[1], dtype=torch.uint8, device="cuda")
+    ws_join = torch.empty(tj.workspace_query(tj.TJ_OP_JOIN_MATERIALIZE, tj.TJ_KEY_I64, n_r, n_s)[1],
+                          dtype=torch.uint8, device="cuda")
+
+    def sort():
+        return tj.sort(d_sk, d_sr, keys_out=ko, rids_out=ro, workspace=ws_sort, stats=True)[2]
+
+    def join():
+        pr, _, st = tj.join(d_rk, d_rr, d_sk, d_sr, capacity=cap, out_r=out_r, out_s=out_s, workspace=ws_join,
+                            stats=True)
+        return pr.numel(), st
+
+    sort()
+    join()
+    torch.cuda.synchronize()
+    tj.timing(True)
+    t_sort, t_join = [], []
+    for i in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sts = sort()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        cnt, stj = join()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        t_sort.append(t1 - t0)
+        t_join.append(t2 - t1)
+        log("hbm zipf step %d: sort %.2f ms, join %.2f ms" % (i, (t1 - t0) * 1e3, (t2 - t1) * 1e3))
+    tj.timing(False)
+    fams = tj.timing_read()
+    assert cnt == expected, "zipf join count %d != closed form %d" % (cnt, expected)
+    assert bool((ko[1:] >= ko[:-1]).all().item()), "zipf sort output not ordered"
+    step_s = (sum(t_sort) + sum(t_join)) / steps
+    dom = max((f for f in fams if not f.startswith("host_")), key=lambda f: fams[f]["ms"])
+    fd = fams[dom]
+    avg_ms = fd["ms"] / max(fd["launches"], 1)
+    bpl = fd["bytes"] / max(fd["launches"], 1)
+    ach = bpl / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    planned = sts["bytes_read"] + sts["bytes_written"] + stj["bytes_read"] + stj["bytes_written"]
+    zipf = {"workload": "hbm_scale theta=0.99: join |R|=2^27 x |S|=2^29 int64 keys (2^20 hottest R keys x4, "
+                        "S 80%% matched by Zipf(0.99)) + sort of the 2^29 S keys; int32 row ids",
+            "steps": steps, "join_count": cnt, "pair_capacity": cap,
+            "tuples_per_s": round((2 * n_s + n_r) / step_s, 1),
+            "sort_ms_p50": round(pct(t_sort, 0.5) * 1e3, 3), "sort_ms_max": round(max(t_sort) * 1e3, 3),
+            "join_ms_p50": round(pct(t_join, 0.5) * 1e3, 3), "join_ms_max": round(max(t_join) * 1e3, 3),
+            "pairs_per_s": round(cnt / pct(t_join, 0.5), 1),
+            "planned_hbm_frac": round(planned / step_s / (HBM_PEAK_GBS * 1e9), 4),
+            "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_launch": int(bpl),
+                         "avg_launch_ms": round(avg_ms, 4), "launches_per_step": fd["launches"] / steps},
+            "kernels": {f: {"launches_per_step": v["launches"] / steps, "ms_per_step": round(v["ms"] / steps, 3),
+                            "GBs": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None}
+                        for f, v in fams.items() if v["launches"]},
+            "plan": {"sort": sts, "join": stj}}
+    log("hbm zipf: sort %.2f ms, join %.2f ms (%d pairs), %s %.1f GB/s" %
+        (zipf["sort_ms_p50"], zipf["join_ms_p50"], cnt, dom, ach))
+    del d_rk, d_rr, d_sk, d_sr, out_r, out_s, ko, ro, ws_sort, ws_join
+    torch.cuda.empty_cache()
+    # standalone sort, keys uniform over [0, 2^40)
+    keys = torch.from_numpy(tjgen.sort_uniform64(1 << 29, bits=40)["keys"]).to("cuda")
+    rids = torch.arange(keys.numel(), dtype=torch.int32, device="cuda")
+    ko, ro = torch.empty_like(keys), torch.empty_like(rids)
+    ws = torch.empty(tj.workspace_query(tj.TJ_OP_SORT, tj.TJ_KEY_I64, keys.numel())[1], dtype=torch.uint8,
+                     device="cuda")
+    times = []
+    for i in range(steps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, st = tj.sort(keys, rids, keys_out=ko, rids_out=ro, workspace=ws, stats=True)
+        torch.cuda.synchronize()
+        if i:
+            times.append(time.perf_counter() - t0)
+    assert bool((ko[1:] >= ko[:-1]).all().item()), "40-bit sort output not ordered"
+    s40 = {"workload": "sort of 2^29 int64 keys uniform over [0, 2^40), int32 row ids",
+           "ms_p50": round(pct(times, 0.5) * 1e3, 3), "ms_max": round(max(times) * 1e3, 3),
+           "keys_per_s": round(keys.numel() / pct(times, 0.5), 1), "passes": st["passes"]}
+    log("sort 40-bit: %.2f ms" % s40["ms_p50"])
+    del keys, rids, ko, ro, ws
+    torch.cuda.empty_cache()
+    return {"zipf_0.99": zipf, "sort_40bit": s40}
+
+
+def _host_cpu():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0))}
+
+
+def cpu_latencies(c2_repeats: int = 10):
+    """The oracle built -O3 -march=native on this host, pinned to one core:
+    C1 and paper-shaped P50/P99, and the size sweep's sort and join times."""
+    import tempfile
+    import oracle
+    import tjgen
+    tmp = tempfile.mkdtemp(prefix="tj_oracle_")
+    orc = oracle.Oracle(oracle.build_native(tmp))
+    before = os.sched_getaffinity(0)
+    core = min(before)
+    os.sched_setaffinity(0, {core})
+    try:
+        out = {"build": "g++ -O3 -march=native", "pinned_core": core, "threads": 1, "host": _host_cpu()}
+
+        def lat(f, repeats, warm=1):
+            ts = []
+            for i in range(warm + repeats):
+                t0 = time.perf_counter()
+                f()
+                if i >= warm:
+                    ts.append((time.perf_counter() - t0) * 1e3)
+            return {"p50_ms": round(pct(ts, 0.5), 4), "p99_ms": round(pct(ts, 0.99), 4), "repeats": repeats}
+
+        w = tjgen.small_uniform()
+        out["c1_small"] = {"sort": lat(lambda: orc.sort(w["r_keys"], w["r_rids"]), 100, 10),
+                           "join": lat(lambda: orc.join_pairs(w["r_keys"], w["r_rids"], w["s_keys"], w["s_rids"]),
+                                       100, 10)}
+        log("cpu C1 done")
+        for theta in (0.0, 0.99):
+            w = tjgen.paper_shaped(theta)
+            out["paper_shaped_theta%g" % theta] = {
+                "sort": lat(lambda: orc.sort(w["s_keys"], w["s_rids"]), c2_repeats),
+                "join": lat(lambda: orc.join_pairs(w["r_keys"], w["r_rids"], w["s_keys"], w["s_rids"]), c2_repeats)}
+            log("cpu paper-shaped theta %g done" % theta)
+        sweep = []
+        for lg in CROSSOVER_LOGS:
+            w = tjgen.crossover(lg)
+            reps = 20 if lg <= 16 else (3 if lg <= 18 else 1)
+            sweep.append({"rows_per_side": 1 << lg,
+                          "sort_ms": lat(lambda: orc.sort(w["s_keys"], w["s_rids"]), reps)["p50_ms"],
+                          "join_ms": lat(lambda: orc.join_pairs(w["r_keys"], w["r_rids"], w["s_keys"],
+                                                                w["s_rids"]), reps)["p50_ms"]})
+        out["sweep"] = sweep
+        log("cpu sweep done")
+    finally:
+        os.sched_setaffinity(0, before)
+    return out
+
+
+def crossover(gpu_sweep, cpu_sweep, key):
+    """Smallest size (rows per side, interpolated on log2 size between the two
+    measured sizes around it) from which the tensor path's time stays below the
+    oracle's; None when it never does."""
+    pts = [(np.log2(g["rows_per_side"]), g[key] - c[key]) for g, c in zip(gpu_sweep, cpu_sweep)]
+    last = None
+    for i in range(len(pts)):
+        if all(d < 0 for _, d in pts[i:]):
+            last = i
+            break
+    if last is None:
+        return None
+    if last == 0:
+        return {"rows_per_side": int(2 ** pts[0][0]), "below_sweep": True}
+    (x0, d0), (x1, d1) = pts[last - 1], pts[last]
+    x = x0 + (x1 - x0) * d0 / (d0 - d1)
+    return {"rows_per_side": int(round(2 ** x)), "below_sweep": False}
 
 
 def main():
@@ -515,6 +807,14 @@ def main():
     ap.add_argument("--multi-rows", type=int, default=1 << 26)
     ap.add_argument("--serve-requests", type=int, default=1000, help="arrivals per rate")
     ap.add_argument("--serve-rates", default="50,200,800,3200", help="arrival rates, requests/s")
+    ap.add_argument("--serve-pool", type=int, default=64, help="requests resident on the device")
+    ap.add_argument("--only-serving", action="store_true",
+                    help="run the serving measurement alone (no step, no other section) and print its JSON")
+    ap.add_argument("--no-copy", action="store_true", help="skip the streaming-copy bandwidth line")
+    ap.add_argument("--no-c1", action="store_true", help="skip the small (10^5-row) latency line")
+    ap.add_argument("--no-zipf", action="store_true", help="skip the Zipf(0.99) HBM-scale section")
+    ap.add_argument("--zipf-steps", type=int, default=5)
+    ap.add_argument("--c2-repeats", type=int, default=10, help="oracle repeats of the paper-shaped workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="before timing, copy MIB MiB device-to-device three times (a plain copy "
                          "of known size that scales the FETCH_SIZE / WRITE_SIZE counters)")
@@ -531,6 +831,11 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     tj.load()
+    if args.only_serving:
+        res = serving(tj, torch, [float(r) for r in args.serve_rates.split(",")], args.serve_requests,
+                      pool=args.serve_pool)
+        print(json.dumps({"serving": res}), flush=True)
+        return
     log("generating workload %s" % args.workload)
     w, sort_keys, desc = make_workload(args.workload, args.theta)
     kt = tj.TJ_KEY_I64 if sort_keys.dtype == np.int64 else tj.TJ_KEY_I32
@@ -635,18 +940,34 @@ def main():
         line["path_selection"] = path_selection(tj, torch, d_rk, d_skj, d_sk, int(pr.numel()))
     del ko, ro, out_r, out_s, ws_sort, ws_join, d_sk, d_sr, d_rk, d_rr, d_skj, d_srj
     torch.cuda.empty_cache()
+    if not args.no_copy:
+        line["stream_copy"] = stream_copy(tj, torch)
+        line["roofline"]["achievable_GBs"] = line["stream_copy"]["achievable_GBs"]
+        line["roofline"]["frac_of_achievable"] = round(achieved / line["stream_copy"]["achievable_GBs"], 4)
+    if not args.no_c1:
+        line["c1_small"] = c1_small(tj, torch)
+    if not args.no_zipf and args.workload == "hbm":
+        line["hbm_zipf"] = hbm_variants(tj, torch, args.zipf_steps)
     if not args.no_learned:
         line["learned_vs_radix"] = learned_vs_radix(tj, torch, args.learned_rows, args.learned_repeats)
     if not args.no_multi:
         line["composite_keys"] = composite_keys(tj, torch, args.multi_rows)
     if not args.no_serving:
-        line["serving"] = serving(tj, torch, [float(r) for r in args.serve_rates.split(",")], args.serve_requests)
+        line["serving"] = serving(tj, torch, [float(r) for r in args.serve_rates.split(",")], args.serve_requests,
+                                  pool=args.serve_pool)
     if not args.no_sweep:
         log("paper-shaped budget sweep")
         line["paper_shaped"] = paper_shaped_sweep(tj, torch, args.sweep_repeats)
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(args.workload, args.theta)
+        lat = cpu_latencies(args.c2_repeats)
+        line["cpu_baseline"]["native_pinned"] = lat
+        if "path_selection" in line:
+            ps = line["path_selection"]
+            ps["oracle_sweep"] = lat["sweep"]
+            ps["crossover"] = {"join": crossover(ps["sweep"], lat["sweep"], "join_ms"),
+                               "sort": crossover(ps["sweep"], lat["sweep"], "sort_ms")}
     print(json.dumps(line), flush=True)
 
 

@@ -204,11 +204,12 @@ typedef struct {
 /*
  * TJ_PART_AUTO decides at execution time from the data: the call starts the
  * radix path, and once the first pass's histogram is known (before anything
- * is moved) it counts the rows in buckets holding more than 8 times the mean
- * bucket size. If they are more than half of all rows, the radix digit would
- * leave them for further passes: the call trains the learned model and
- * partitions with it instead. Otherwise it continues with radix, at the cost
- * of one read-back of the bucket counts.
+ * is moved) it reads back the bucket counts. If one bucket holds more than
+ * half of all rows, the digit has not separated the bulk of the keys from a
+ * long tail (each radix level narrows the digit to its bucket's key range,
+ * which splits a few dense intervals at the next level but not a heavy
+ * tail): the call trains the learned model and partitions with it instead.
+ * Otherwise it continues with radix, at the cost of that one read-back.
  */
 enum tj_partitioner { TJ_PART_RADIX = 0, TJ_PART_LEARNED = 1, TJ_PART_AUTO = 2 };
 typedef struct {
@@ -517,6 +518,13 @@ int tj_version(void);
  *   flags: 0, or TJ_DEBUG_FORCE_REORDER to make every scatter tile take the
  *   path that re-ranks it when its first ranking is not in input order (the
  *   result must not change). Other bits give TJ_E_ARG.
+ * tj_debug_stream_copy: copies `bytes` (a multiple of 16) from src to dst,
+ *   both device pointers aligned to 16 bytes and not overlapping, with a plain
+ *   16-byte-per-lane streaming kernel, asynchronously on `stream`. It gives
+ *   the bandwidth a kernel that reads and writes each byte once reaches on
+ *   the device, the practical ceiling the partition and leaf kernels are
+ *   compared with. TJ_E_ARG for a size or alignment it does not take,
+ *   TJ_E_ALIAS for overlapping buffers, TJ_E_HIP for a failed launch.
  */
 #define TJ_DEBUG_FORCE_REORDER 1u
 #define TJ_DEBUG_FAIL_HOST_ALLOC 2u
@@ -533,6 +541,7 @@ int tj_version(void);
  */
 int tj_debug_set_flags(uint32_t flags);
 int tj_debug_wave_scan(const uint32_t *in, uint32_t *out, uint64_t n, void *stream);
+int tj_debug_stream_copy(const void *src, void *dst, uint64_t bytes, void *stream);
 int tj_debug_partition_pass(const int64_t *keys, const int32_t *rids, uint64_t n,
                             uint64_t base, uint32_t shift, uint32_t bits, uint32_t flags,
                             int64_t *keys_out, int32_t *rids_out, uint32_t *counts_out,

@@ -34,6 +34,14 @@ def build(force: bool = False) -> str:
     return _LIB
 
 
+def build_native(out_dir: str) -> str:
+    """Compile the same source with -O3 -march=native into out_dir, for timing
+    on the machine that runs it (the benchmark's CPU leg)."""
+    path = os.path.join(out_dir, "liboracle_native.so")
+    subprocess.check_call(["g++", "-O3", "-march=native", "-std=c++17", "-shared", "-fPIC", "-o", path, _SRC])
+    return path
+
+
 def _bind(lib):
     for t in ("i32", "i64"):
         getattr(lib, "tjo_sort_" + t).argtypes = [_P, _P, _u64, _P, _P]

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libtj.so")
-SOURCES = ["tj_kernels.hip", "tj_rmi.hip", "tj_multi.hip", "tj_abi.cpp", "tj_serve.cpp", "tj_multi.cpp", "tj_static.hip", "tj_fuse.hip",
+SOURCES = ["tj_kernels.hip", "tj_rmi.hip", "tj_multi.hip", "tj_abi.cpp", "tj_serve.cpp", "tj_multi.cpp", "tj_static.hip", "tj_fuse.hip", "tj_bandwidth.hip",
            "tj_select.hip", "tj_select.cpp"]
 HEADERS = ["tj_internal.h", "tj_rmi.h", "tj_select.h"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

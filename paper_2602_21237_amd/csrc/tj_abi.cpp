@@ -48,7 +48,7 @@ constexpr size_t DEVICE_BATCH_MIN_SEGS = 16;  // segments of a pass before leave
 constexpr uint32_t LEARNED_BUCKETS = 512;        // buckets of the learned pass: one full-width digit
 constexpr uint32_t DEFAULT_PERMILLE = 10;        // 1% sample per relation
 constexpr uint64_t DEFAULT_LEARNED_MIN_ROWS = 1ull << 22;
-constexpr uint64_t AUTO_HEAVY = 8;               // a radix bucket over 8x the mean counts as heavy
+constexpr uint64_t AUTO_BULK_DEN = 2;            // auto: learned when one bucket holds over 1/2 of the rows
 constexpr int TJ_SWITCH_LEARNED = 100;           // internal: the auto partitioner hands over
 constexpr int TJ_RANGE_MISS = 101;               // internal: a row fell outside the sampled range
 constexpr uint64_t SAMPLED_PROBE_MIN_ROWS = 1ull << 22;  // rows from which the range is sampled
@@ -690,24 +690,27 @@ struct Exec {
                 return launch_scan(d_cblocks, ncb, d_groups, ng, d_hist, d_cbsum, d_ccount, d_cstart, st);
             }));
             if (auto_probe) {
-                // The radix digit's bucket sizes decide: when most rows sit in
-                // buckets over AUTO_HEAVY times the mean, the digit leaves them
-                // for further passes and the learned partitioner takes over
-                // (nothing has been scattered yet).
+                // The radix digit's bucket sizes decide. Every next pass
+                // narrows the digit to its bucket's own key range, so a few
+                // dense key intervals split at the next level; but when one
+                // bucket holds most of the rows, the digit has not separated
+                // the bulk of the keys from a long tail, and narrowing leaves
+                // it crowded again level after level: then the learned
+                // partitioner takes over (nothing has been scattered yet).
                 auto_probe = false;
                 std::vector<uint32_t> cnt(child);
                 TJ_CK(hipMemcpyAsync(cnt.data(), d_ccount, (size_t)child * 4, hipMemcpyDeviceToHost, st));
                 TJ_CK(hipStreamSynchronize(st));
-                uint64_t rows = 0, heavy = 0;
+                uint64_t rows = 0, largest = 0;
                 std::vector<uint64_t> per(child / nside, 0);
                 for (uint32_t gi = 0; gi < ng; gi++)
                     for (uint32_t d = 0; d < (1u << groups[gi].bits); d++)
                         per[groups[gi - gi % nside].child0 / nside + d] += cnt[groups[gi].child0 + d];
-                for (uint64_t c : per) rows += c;
-                const uint64_t nb = per.empty() ? 1 : per.size();
-                for (uint64_t c : per)
-                    if (c * nb > AUTO_HEAVY * rows) heavy += c;
-                if (2 * heavy > rows) {
+                for (uint64_t c : per) {
+                    rows += c;
+                    largest = std::max(largest, c);
+                }
+                if (AUTO_BULK_DEN * largest > rows) {
                     stats.passes--;  // histogram only
                     return TJ_SWITCH_LEARNED;
                 }
@@ -2170,6 +2173,13 @@ int tj_debug_set_flags(uint32_t flags)
     if (flags & ~(uint32_t)(TJ_DEBUG_FORCE_REORDER | TJ_DEBUG_FAIL_HOST_ALLOC)) return TJ_E_ARG;
     g_debug_flags.store(flags);
     return TJ_OK;
+}
+
+int tj_debug_stream_copy(const void* src, void* dst, uint64_t bytes, void* stream)
+{
+    if (!src || !dst || bytes % 16 || (uintptr_t)src % 16 || (uintptr_t)dst % 16) return TJ_E_ARG;
+    if (overlap(src, bytes, dst, bytes)) return TJ_E_ALIAS;
+    return launch_stream_copy(src, dst, bytes, (hipStream_t)stream) == hipSuccess ? TJ_OK : TJ_E_HIP;
 }
 
 int tj_debug_wave_scan(const uint32_t* in, uint32_t* out, uint64_t n, void* stream)

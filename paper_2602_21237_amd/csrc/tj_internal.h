@@ -250,6 +250,9 @@ hipError_t launch_rmi_eval(int key_bytes, const void* keys, uint64_t n, const tj
                            uint16_t* out, hipStream_t st);
 
 
+// plain streaming copy of `bytes` (a multiple of 16, both pointers 16-byte aligned)
+hipError_t launch_stream_copy(const void* src, void* dst, uint64_t bytes, hipStream_t st);
+
 // One request of a fused serving call (tj_fuse.hip): its inputs and outputs,
 // rows per side, and where its rows sit in the combined columns.
 struct FuseDesc {

@@ -126,6 +126,7 @@ EXPORTS = {
     "tj_timing_read": (ctypes.c_int, [_P, ctypes.c_int]),
     "tj_debug_wave_scan": (ctypes.c_int, [_P, _P, _u64, _P]),
     "tj_debug_set_flags": (ctypes.c_int, [ctypes.c_uint32]),
+    "tj_debug_stream_copy": (ctypes.c_int, [_P, _P, _u64, _P]),
     "tj_debug_partition_pass": (ctypes.c_int, [_P, _P, _u64, _u64, ctypes.c_uint32, ctypes.c_uint32,
                                                ctypes.c_uint32, _P, _P, _P, _P, _u64, _P]),
 }
@@ -464,6 +465,8 @@ def rmi_buckets(keys, model: RmiModel, stream=None):
 TJ_PATH_LINEAR, TJ_PATH_TENSOR = 0, 1
 TJ_SEL_SCALE, TJ_SEL_OUTPUT = 1, 2
 SELECT_REGISTERS = 16384
+TJ_SELECT_DEFAULT_MIN_ROWS = 1 << 16
+TJ_SELECT_DEFAULT_MIN_OUTPUT = 1 << 18
 
 
 class SelectOptions(ctypes.Structure):
@@ -527,6 +530,16 @@ def debug_wave_scan(x):
 
 TJ_DEBUG_FORCE_REORDER = 1
 TJ_DEBUG_FAIL_HOST_ALLOC = 2
+
+
+def debug_stream_copy(src, dst, stream=None) -> None:
+    """Plain streaming copy of src into dst (device tensors of equal byte size,
+    a multiple of 16 bytes), on `stream` (default: torch's current stream)."""
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb:
+        raise ValueError("src and dst differ in size")
+    _check(load().tj_debug_stream_copy(src.data_ptr(), dst.data_ptr(), nb, _stream(stream)),
+           "tj_debug_stream_copy")
 
 
 def debug_set_flags(flags: int) -> None:

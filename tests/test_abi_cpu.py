@@ -284,3 +284,23 @@ def test_select_argument_errors():
     # registers overlapping an input or the workspace
     assert sel(tj.TJ_OP_JOIN_COUNT, 8, A, 100, B, 100, None, o, A + 8, W, need, None) == tj.TJ_E_ALIAS
     assert sel(tj.TJ_OP_JOIN_COUNT, 8, A, 100, B, 100, None, o, W + 256, W, need, None) == tj.TJ_E_ALIAS
+
+
+def test_stream_copy_argument_errors():
+    lib = tj.load()
+    cp = lib.tj_debug_stream_copy
+    assert cp(None, B, 64, None) == tj.TJ_E_ARG
+    assert cp(A, None, 64, None) == tj.TJ_E_ARG
+    assert cp(A, B, 60, None) == tj.TJ_E_ARG  # not a multiple of 16 bytes
+    assert cp(A + 8, B, 64, None) == tj.TJ_E_ARG  # misaligned
+    assert cp(A, A + 32, 64, None) == tj.TJ_E_ALIAS
+
+
+def _header_define(name):
+    m = re.search(r"#define\s+%s\s+\(1ull << (\d+)\)" % name, open(HEADER).read())
+    return 1 << int(m.group(1))
+
+
+def test_select_defaults_match_header():
+    assert tj.TJ_SELECT_DEFAULT_MIN_ROWS == _header_define("TJ_SELECT_DEFAULT_MIN_ROWS")
+    assert tj.TJ_SELECT_DEFAULT_MIN_OUTPUT == _header_define("TJ_SELECT_DEFAULT_MIN_OUTPUT")

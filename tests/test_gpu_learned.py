@@ -171,11 +171,14 @@ def test_learned_equals_radix_large(tj, name):
     assert c1 == c2 and st["learned"] == 1
 
 
-@pytest.mark.parametrize("name,expect", [("lognormal", 1), ("seqgap", 0)])
+@pytest.mark.parametrize("name,expect", [("lognormal", 1), ("mixture", 0), ("seqgap", 0)])
 def test_auto_partitioner_decides_from_the_histogram(tj, name, expect):
-    """Auto: lognormal keys crowd the radix digit's buckets, so the call hands
-    over to the learned pass; gapped sequential keys spread evenly, so it stays
-    radix. Results equal the radix path's either way."""
+    """Auto: lognormal keys put nearly all rows in one bucket of the radix
+    digit (a heavy tail), so the call hands over to the learned pass; the
+    interval mixture fills a few buckets, none with half the rows (its
+    intervals split once the next level narrows the range), and gapped
+    sequential keys spread evenly, so both stay radix. Results equal the radix
+    path's either way."""
     w = tjgen.learned(name, 1 << 24)
     rk, sk, rid = dev(w["r_keys"]), dev(w["s_keys"]), dev(w["r_rids"])
     k1, r1 = tj.sort(rk, rid)

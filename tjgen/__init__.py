@@ -198,6 +198,13 @@ def hbm_scale(theta: float = 0.0, seed: int = BASE_SEED, n_r: int = 1 << 27,
     return _fk_pair(40 + int(round(theta * 100)), n_r, n_s, theta, hot=hot, mult=mult, seed=seed)
 
 
+def crossover(lg: int, seed: int = BASE_SEED) -> Workload:
+    """|R| = |S| = 2^lg, the paper-shaped structure (unique 40-bit R keys, 80%
+    uniform FK matches): the inputs of the path-selection size sweep."""
+    n = 1 << lg
+    return _fk_pair(300 + lg, n, n, 0.0, seed=seed)
+
+
 def sort_uniform64(n: int = 1 << 29, seed: int = BASE_SEED, bits: int = 64) -> Workload:
     """n int64 keys uniform over [0, 2^bits) (bits = 64: the whole signed range)."""
     w = Workload(keys=uniform_i64(n, stream(60 + bits, seed), bits), rids=iota_i32(n))

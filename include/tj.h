@@ -439,9 +439,14 @@ int tj_server_destroy(tj_server_t *server);
  * Decision: TJ_PATH_TENSOR when scale >= min_rows (reason TJ_SEL_SCALE) or,
  * for a join, est_output >= min_output (TJ_SEL_OUTPUT); otherwise
  * TJ_PATH_LINEAR. Options (may be NULL): a zero field takes its default,
- * TJ_SELECT_DEFAULT_MIN_ROWS and TJ_SELECT_DEFAULT_MIN_OUTPUT; the paper
- * leaves the thresholds open, so the defaults are starting points to be set
- * from measured crossovers.
+ * TJ_SELECT_DEFAULT_MIN_ROWS and TJ_SELECT_DEFAULT_MIN_OUTPUT. The paper
+ * leaves the thresholds open; the defaults come from a measured crossover on
+ * one MI355X against a single-core CPU hash join and std::sort (built -O3
+ * -march=native, inputs in host memory): over FK joins of 2^8 ... 2^22 rows per
+ * side, the tensor path's join (device inputs, wall time of the call) is
+ * faster from about 1,300 rows per side (scale 2,600, about 1,050 output
+ * pairs) and its sort from about 1,760 rows, below which its fixed cost of
+ * roughly 0.06-0.25 ms per call dominates.
  *
  *   op: TJ_OP_SORT (s_keys ignored, n_s must be 0) or a join op;
  *   r_keys[n_r], s_keys[n_s]: device key columns of key_type;
@@ -455,8 +460,8 @@ int tj_server_destroy(tj_server_t *server);
  * workspace, or the workspace overlapping an input), TJ_E_HIP.
  */
 #define TJ_SELECT_REGISTERS 16384
-#define TJ_SELECT_DEFAULT_MIN_ROWS (1ull << 16)
-#define TJ_SELECT_DEFAULT_MIN_OUTPUT (1ull << 18)
+#define TJ_SELECT_DEFAULT_MIN_ROWS (1ull << 11)
+#define TJ_SELECT_DEFAULT_MIN_OUTPUT (1ull << 10)
 enum tj_path { TJ_PATH_LINEAR = 0, TJ_PATH_TENSOR = 1 };
 enum tj_select_reason { TJ_SEL_SCALE = 1, TJ_SEL_OUTPUT = 2 };
 typedef struct {

@@ -38,8 +38,8 @@ M_BITS = 14
 M = 1 << M_BITS
 MAX_RANK = 64 - M_BITS + 1
 GAMMA = 0x9E3779B97F4A7C15
-DEFAULT_MIN_ROWS = 1 << 16
-DEFAULT_MIN_OUTPUT = 1 << 18
+DEFAULT_MIN_ROWS = 1 << 11
+DEFAULT_MIN_OUTPUT = 1 << 10
 _MASK = (1 << 64) - 1
 
 

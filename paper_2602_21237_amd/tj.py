@@ -465,8 +465,8 @@ def rmi_buckets(keys, model: RmiModel, stream=None):
 TJ_PATH_LINEAR, TJ_PATH_TENSOR = 0, 1
 TJ_SEL_SCALE, TJ_SEL_OUTPUT = 1, 2
 SELECT_REGISTERS = 16384
-TJ_SELECT_DEFAULT_MIN_ROWS = 1 << 16
-TJ_SELECT_DEFAULT_MIN_OUTPUT = 1 << 18
+TJ_SELECT_DEFAULT_MIN_ROWS = 1 << 11
+TJ_SELECT_DEFAULT_MIN_OUTPUT = 1 << 10
 
 
 class SelectOptions(ctypes.Structure):

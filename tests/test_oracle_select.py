@@ -156,5 +156,5 @@ def test_decision_rule():
     sel = S.select(many, many, min_rows=10**9, min_output=10**6)
     assert (sel["path"], sel["reasons"]) == (0, 0)
     # defaults
-    assert S.select(np.arange(1 << 16, dtype=np.int64))["reasons"] == 1
-    assert S.select(np.arange((1 << 16) - 1, dtype=np.int64))["reasons"] == 0
+    assert S.select(np.arange(1 << 11, dtype=np.int64))["reasons"] == 1
+    assert S.select(np.arange((1 << 11) - 1, dtype=np.int64))["reasons"] == 0

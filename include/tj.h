@@ -67,9 +67,12 @@ typedef struct {
     uint32_t passes;          /* partition passes (histogram + scan + scatter) */
     uint32_t leaves;          /* per-bucket LDS sort / join blocks */
     uint32_t single_key;      /* buckets holding a single key value */
-    uint32_t key_ranges;      /* key ranges processed one at a time (1 = budget not binding) */
+    uint32_t key_ranges;      /* key ranges processed one at a time, each read from the
+                                 inputs (1 = the inputs are read once) */
     uint32_t learned;         /* 1 when the first pass used the learned bucket function */
     uint32_t learned_overflow;/* buckets of that pass holding more than twice the mean */
+    uint32_t windows;         /* sort under a binding budget: runs of buckets taken through
+                                 the workspace window (0 when the budget does not bind) */
     uint64_t sample_rows;     /* keys the learned model was fitted to */
 } tj_stats_t;
 
@@ -93,6 +96,14 @@ int tj_workspace_query(int op, int key_type, uint64_t n_r, uint64_t n_s,
  *   keys_in [n] (int32 or int64 per key_type), rids_in [n] int32: inputs.
  *   keys_out[n], rids_out[n]: outputs (device, caller-owned, no overlap).
  * n = 0 is allowed and does nothing.
+ * Under a binding budget (workspace_bytes below tj_workspace_query's
+ * full_bytes) the first partition pass still reads the input once and writes
+ * every row into keys_out/rids_out, where leaf buckets are then sorted in
+ * place. Buckets that need more passes take them through the workspace, as
+ * many adjacent buckets at a time as it holds (tj_stats_t.windows counts those
+ * runs). A bucket larger than the workspace that holds more than one key value
+ * is sorted the same way into its own rows of the output, from the input read
+ * again and filtered to the bucket's key range (key_ranges - 1 such reads).
  */
 int tj_sort(int key_type, const void *keys_in, const int32_t *rids_in, uint64_t n,
             void *keys_out, int32_t *rids_out,
@@ -106,8 +117,8 @@ int tj_sort(int key_type, const void *keys_in, const int32_t *rids_in, uint64_t 
  * that the library holds on every GPU it runs on, from the library's load
  * until the process ends, as its workspace budget. Inputs of up to 22,322,688
  * int64 rows (33,484,032 int32 rows) run the unlimited plan; larger ones run
- * the budget-bound plan (key ranges) inside the same array, so results never
- * change, only time.
+ * the budget-bound plan (the array as the window of tj_sort under a binding
+ * budget), so results never change, only time.
  * The call makes no device or pinned-host allocation (its read-backs go to
  * grow-only pageable host memory) and records no timing events.
  * The array is shared by every call on one GPU: the library serialises those
@@ -377,9 +388,9 @@ typedef struct {
     double run_ms;               /* time on a slot */
     double total_ms;             /* submission to completion */
     uint32_t learned;            /* the call used the learned first pass */
-    uint32_t key_ranges;         /* 1 unless the budget forced key ranges */
+    uint32_t key_ranges;         /* tj_stats_t.key_ranges of the call */
     uint32_t fused;              /* requests served by the same call (1: alone) */
-    uint32_t pad;
+    uint32_t windows;            /* tj_stats_t.windows of the call */
 } tj_result_t;
 /* Starts `slots` (1..64) worker threads with one HIP stream each (default
  * priority) on the current device. Errors: TJ_E_ARG, TJ_E_WORKSPACE

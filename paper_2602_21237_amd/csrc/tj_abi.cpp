@@ -36,7 +36,7 @@ namespace tj {
 namespace {
 
 constexpr uint64_t ALIGN = 256;
-constexpr int TABLE_TIERS = 8;
+constexpr int TABLE_TIERS = 9;
 constexpr uint64_t TARGET_CHUNKS = 2048;  // blocks per partition pass
 #ifndef TJ_PASS_DIGIT_BITS
 #define TJ_PASS_DIGIT_BITS MAX_DIGIT_BITS
@@ -69,12 +69,23 @@ struct Caps {
 Caps tier_caps(int t)
 {
     Caps c;
-    c.groups = 64u << t;
-    c.chunks = 64u << t;
-    c.cblocks = 64u << t;
-    c.children = 4096u << t;
-    c.leaves = 1024u << t;
-    c.units = 64u << t;
+    if (t == 0) {
+        // the smallest tier (about 270 KB), for budgets of about a megabyte:
+        // a full-width digit of one join segment still fits one launch
+        c.groups = 32;
+        c.chunks = 64;
+        c.cblocks = 32;
+        c.children = 2 * NB;
+        c.leaves = 256;
+        c.units = 32;
+        return c;
+    }
+    c.groups = 64u << (t - 1);
+    c.chunks = 64u << (t - 1);
+    c.cblocks = 64u << (t - 1);
+    c.children = 4096u << (t - 1);
+    c.leaves = 1024u << (t - 1);
+    c.units = 64u << (t - 1);
     return c;
 }
 
@@ -184,12 +195,23 @@ const uint64_t kMaxRows = (1ull << 31) - 1;
 // enough digits that a child averages LEAF_CAP / 2 rows (at least 2, at most a
 // full digit), at the largest shift at which (span >> shift) + 1 digits still
 // reach that many, so a span that is not a power of two still puts them to
-// use. A span of 0 (filtered roots of a single-key range, which still need a
-// compaction pass) gets one bit.
-inline void plan_digit(uint64_t span, uint64_t rows, uint32_t& shift, uint32_t& bits)
+// use. With `few` (a level of at most FEW_SEGS segments) a segment of at most
+// SMALL_SEG_ROWS rows (mostly a bucket crowded by a few frequent keys) takes
+// a full digit: such a level costs about its launches and read-back whatever
+// the width, and the wider digit separates the frequent keys from their
+// neighbours in fewer levels. (A level of many segments keeps the narrower
+// digit: the children's bookkeeping grows with the width.) A span of 0
+// (filtered roots of a single-key range, which still need a compaction pass)
+// gets one bit.
+constexpr uint64_t SMALL_SEG_ROWS = 16ull * LEAF_CAP;
+constexpr size_t FEW_SEGS = 64;
+inline void plan_digit(uint64_t span, uint64_t rows, bool few, uint32_t& shift, uint32_t& bits)
 {
-    const uint64_t want = std::min<uint64_t>(std::max<uint64_t>((rows + LEAF_CAP / 2 - 1) / (LEAF_CAP / 2), 2),
-                                             1ull << PASS_DIGIT_BITS);
+    const uint64_t want =
+        few && rows <= SMALL_SEG_ROWS
+            ? 1ull << PASS_DIGIT_BITS
+            : std::min<uint64_t>(std::max<uint64_t>((rows + LEAF_CAP / 2 - 1) / (LEAF_CAP / 2), 2),
+                                 1ull << PASS_DIGIT_BITS);
     shift = 0;
     for (uint32_t sh = nbits64(span); sh-- > 0;)
         if ((span >> sh) + 1 >= want) {
@@ -258,6 +280,9 @@ struct Seg {
     // them (4 bytes at index i + koff) inside that bucket's 8-byte footprint,
     // away from the 8-byte keys of other buckets in the same buffer.
     uint64_t koff_r = 0, koff_s = 0;
+    // Sort under a binding budget: row in the workspace window (buffer B)
+    // minus row in buffer A of the same data; 0 everywhere else.
+    int64_t wdisp = 0;
 };
 
 struct Unit {                 // a final piece of join output, ordered by key
@@ -389,6 +414,7 @@ struct Exec {
     // data buffer capacities (rows per side) when the buffers live in the workspace
     uint64_t cap_r = 0, cap_s = 0;
     bool out_is_a = false;  // sort: buffer A is the caller's output
+    uint64_t a_off = 0;     // sort: output row of buffer A's row 0
     bool write_keys = true; // partition passes write key columns (off: rid-only compaction)
     bool device_batching = true;  // the last level's leaves may be batched on the device
 
@@ -516,7 +542,7 @@ struct Exec {
         uint64_t total_rows = 0;
         for (size_t i = 0; i < segs.size(); i++) {
             const Seg& s = segs[i];
-            plan_digit(s.hi - s.lo, s.rn + s.sn, plan[i].shift, plan[i].bits);
+            plan_digit(s.hi - s.lo, s.rn + s.sn, segs.size() <= FEW_SEGS, plan[i].shift, plan[i].bits);
             // join keys are narrowed to 4 bytes once every child spans at most
             // 2^32 ordinals; the sort writes its keys out and never narrows
             plan[i].kb_out = sh.join && write_keys && s.kb == 8 && plan[i].shift <= 32 ? 4u : s.kb;
@@ -532,6 +558,8 @@ struct Exec {
         // are many: one wave walks each segment's children in turn (~0.1 ms),
         // while the host needs about 5 ns per child.
         if (segs.size() < DEVICE_BATCH_MIN_SEGS || learned) dev_ok = false;
+        for (const Seg& sg : segs)
+            if (sg.wdisp) dev_ok = false;  // device leaves take one output offset
         if (dev_ok)
             for (size_t i = 0; i < segs.size(); i++)
                 if (((segs[i].rn + segs[i].sn) >> plan[i].bits) > (uint64_t)LEAF_CAP / 2) dev_ok = false;
@@ -594,6 +622,8 @@ struct Exec {
                     g.start = filter ? 0 : (side ? s.s0 : s.r0);
                     g.len = len;
                     g.dst_start = filter ? 0 : (side ? s.s0 : s.r0);
+                    if (!filter && side == 0)  // into or out of the window
+                        g.dst_start += (dst == BUF_B ? s.wdisp : 0) - (src == BUF_B ? s.wdisp : 0);
                     g.base = learned ? 0 : s.lo;
                     g.flo = filter ? filter[0] : 0;
                     g.fhi = filter ? filter[1] : ~0ull;
@@ -798,6 +828,7 @@ struct Exec {
                     c.win = parent_win;
                     c.koff_r = koff_r;
                     c.koff_s = koff_s;
+                    c.wdisp = segs[gseg[gi]].wdisp;
                     if (narrowing && c.lo <= c.hi) {
                         // keys now hold (ord - g.base) mod 2^32 (see k_scatter)
                         const uint64_t off = c.lo - g0.base;
@@ -848,6 +879,7 @@ struct Exec {
     }
 
     bool cl_open = false, cl_useful = false;
+    int64_t cl_wdisp = 0;
     LeafDesc cl_cur{};
     uint64_t cl_lo = 0, cl_hi = 0, cl_win = 0;
     uint32_t cl_kb = 0;
@@ -859,7 +891,7 @@ struct Exec {
             cl_cur.bits = (uint16_t)nbits64(cl_hi - cl_lo);
             cl_cur.kb = (uint16_t)cl_kb;
             cl_cur.flags = (g_debug_flags.load() & TJ_DEBUG_FORCE_REORDER) ? LEAF_FORCE_REORDER : 0;
-            cl_cur.out = sh.join ? 0 : cl_cur.r0 + out_delta;
+            cl_cur.out = sh.join ? 0 : cl_cur.r0 + out_delta - (cl_cur.buf == BUF_B ? cl_wdisp : 0);
             leaves.push_back(cl_cur);
         }
         cl_open = false;
@@ -876,7 +908,7 @@ struct Exec {
         if (rows <= (uint64_t)LEAF_CAP) {
             const bool adjacent = cl_open && cl_cur.buf == s.buf && cl_kb == s.kb && cl_win == s.win &&
                                   cl_cur.kr0 - cl_cur.r0 == s.koff_r && cl_cur.ks0 - cl_cur.s0 == s.koff_s &&
-                                  cl_cur.r0 + cl_cur.rn == s.r0 &&
+                                  cl_cur.r0 + cl_cur.rn == s.r0 && cl_wdisp == s.wdisp &&
                                   (!sh.join || cl_cur.s0 + cl_cur.sn == s.s0) &&
                                   cl_cur.rn + cl_cur.sn + rows <= (uint64_t)LEAF_CAP;
             if (!adjacent) {
@@ -892,6 +924,7 @@ struct Exec {
                 cl_hi = s.hi;
                 cl_kb = s.kb;
                 cl_win = s.win;
+                cl_wdisp = s.wdisp;
             }
             cl_cur.rn += (uint32_t)s.rn;
             cl_cur.sn += (uint32_t)s.sn;
@@ -912,11 +945,11 @@ struct Exec {
                 c.b = s.sn;
                 c.buf = s.buf;
                 crosses.push_back(c);
-            } else if (!(out_is_a && s.buf == BUF_A && out_delta == 0)) {
+            } else if (!(out_is_a && s.buf == BUF_A && out_delta == a_off)) {
                 CopyDesc c{};
                 c.start = s.r0;
                 c.len = s.rn;
-                c.out = s.r0 + out_delta;
+                c.out = s.r0 + out_delta - (s.buf == BUF_B ? s.wdisp : 0);
                 c.buf = s.buf;
                 copies.push_back(c);
             }
@@ -1011,6 +1044,93 @@ struct Exec {
             cur = dst;
         }
         return TJ_E_INTERNAL;
+    }
+
+    // ---- sort under a binding budget: output columns plus a window ---------
+    // Sorts the `rows` rows with keys in [lo, hi] into output rows [o, o +
+    // rows). Buffer A is the output columns from row o. The first pass reads
+    // the input (`filtered`: keeping only the rows in [lo, hi], which the
+    // input still holds) and partitions them straight into A, where buckets
+    // that are leaves are sorted in place and single-key buckets are already
+    // final. Buckets that need more passes take them through the workspace
+    // window (buffer B, wrows rows at wk / wr): a run of buckets (in key
+    // order) at a time, packed one after another into the window (each with
+    // its own Seg::wdisp), ping-ponging between their own rows of A and their
+    // place in the window until every child is a leaf; each run's leaves are
+    // sorted before the window moves on. A bucket of more than wrows rows is
+    // sorted the same way into its own rows of A, from the input filtered to
+    // its key range.
+    int sort_windowed(uint64_t lo, uint64_t hi, uint64_t rows, uint64_t o, bool filtered, int depth, void* out_k,
+                      int32_t* out_r, char* wk, char* wr, uint64_t wrows)
+    {
+        if (depth > 64) return TJ_E_INTERNAL;
+        bufs.key[BUF_A][0] = (char*)out_k + o * (uint64_t)sh.kb;
+        bufs.rid[BUF_A][0] = out_r + o;
+        a_off = o;
+        Seg root{};
+        root.kb = (uint32_t)sh.kb;
+        root.rn = rows;
+        root.lo = lo;
+        root.hi = hi;
+        root.buf = BUF_IN;
+        std::vector<Seg> next, level, next2, big;
+        auto allow_device = [&]() {
+            dev_ok = device_batching && leaves.empty() && crosses.empty() && copies.empty() && dev_leaves == 0;
+        };
+        cur_out_delta = o;
+        if (filtered) {
+            const uint64_t f[2] = {lo, hi};
+            next.push_back(root);
+            stats.key_ranges++;  // one more read of the input
+            allow_device();
+            TJ_RET(run_pass(next, BUF_IN, BUF_A, f, [&](const Seg& c) { classify_one(c, level, o); }));
+            dev_ok = false;
+        } else {
+            classify_one(root, next, o);
+            classify_flush(o);
+            if (!next.empty()) {
+                allow_device();
+                TJ_RET(run_pass(next, BUF_IN, BUF_A, nullptr, [&](const Seg& c) { classify_one(c, level, o); }));
+                dev_ok = false;
+            }
+        }
+        classify_flush(o);
+        TJ_RET(run_sort_leaves(out_k, out_r));
+        size_t i = 0;
+        while (i < level.size()) {
+            if (level[i].rn > wrows) {
+                big.push_back(level[i++]);
+                continue;
+            }
+            // pack a run of buckets into the window, each at its own offset
+            next.clear();
+            uint64_t used = 0;
+            while (i < level.size() && level[i].rn <= wrows && used + level[i].rn <= wrows) {
+                Seg g = level[i++];
+                g.wdisp = (int64_t)used - (int64_t)g.r0;
+                used += g.rn;
+                next.push_back(g);
+            }
+            bufs.key[BUF_B][0] = wk;
+            bufs.rid[BUF_B][0] = (const int32_t*)wr;
+            stats.windows++;
+            uint32_t cur = BUF_A;
+            for (int d = 0; !next.empty(); d++) {
+                if (d >= 80) return TJ_E_INTERNAL;
+                const uint32_t dst = cur == BUF_A ? (uint32_t)BUF_B : (uint32_t)BUF_A;
+                next2.clear();
+                allow_device();
+                TJ_RET(run_pass(next, cur, dst, nullptr, [&](const Seg& c) { classify_one(c, next2, o); }));
+                dev_ok = false;
+                classify_flush(o);
+                next.swap(next2);
+                cur = dst;
+            }
+            TJ_RET(run_sort_leaves(out_k, out_r));
+        }
+        for (const Seg& b : big)
+            TJ_RET(sort_windowed(b.lo, b.hi, b.rn, o + b.r0, true, depth + 1, out_k, out_r, wk, wr, wrows));
+        return TJ_OK;
     }
 
     // ---- leaves and singles ---------------------------------------------
@@ -1552,7 +1672,7 @@ int sampled_range(Exec& x, const void* a, uint64_t na, const void* b, uint64_t n
     // the digit width depends on the span, which depends on the rounded minimum
     for (int it = 0; it < 3; it++) {
         uint32_t shift, bits;
-        plan_digit(hi - lo, na + nb, shift, bits);
+        plan_digit(hi - lo, na + nb, true, shift, bits);  // as the first pass (one segment)
         const uint64_t aligned = shift >= 64 ? 0 : (mm[0] & ~((1ull << shift) - 1));
         if (aligned == lo) break;
         lo = aligned;
@@ -1697,7 +1817,7 @@ static int sort_body(int key_type, const void* keys_in, const int32_t* rids_in, 
     x.bufs.rid[BUF_IN][0] = rids_in;
     x.bufs.key[BUF_A][0] = keys_out;
     x.bufs.rid[BUF_A][0] = rids_out;
-    x.out_is_a = unlimited;
+    x.out_is_a = true;  // buffer A is the output (the budget plan's key ranges change that)
 
     // buffer B (workspace) is free until the second pass: the training
     // scratch, then the learned pass's bucket ids
@@ -1750,43 +1870,10 @@ static int sort_body(int key_type, const void* keys_in, const int32_t* rids_in, 
         TJ_RET(rc);
         TJ_RET(x.run_sort_leaves(keys_out, rids_out));
     } else {
-        // ranges: buffer A and B both live in the workspace; outputs are written
-        // by the leaves and copies at the range's output offset
-        // buffers A and B both inside the workspace: the B region split in two
-        const uint64_t half = x.cap_r / 2;
-        if (half == 0) return TJ_E_WORKSPACE;
-        x.cap_r = half;
-        std::vector<Exec::Range> ranges;
-        TJ_RET(x.plan_ranges(lo, hi, ranges, 0));
-        char* pb = (char*)x.bufs.key[BUF_B][0];
-        char* pbr = (char*)x.bufs.rid[BUF_B][0];
-        x.bufs.key[BUF_A][0] = pb;
-        x.bufs.rid[BUF_A][0] = (const int32_t*)pbr;
-        x.bufs.key[BUF_B][0] = pb + align_up(half * (uint64_t)key_type, ALIGN);
-        x.bufs.rid[BUF_B][0] = (const int32_t*)(pbr + align_up(half * 4, ALIGN));
-        x.out_is_a = false;
-        uint64_t out_row = 0;
-        x.stats.key_ranges = (uint32_t)ranges.size();
-        for (const auto& r : ranges) {
-            if (r.rn > half && r.lo != r.hi) return TJ_E_INTERNAL;
-            if (r.lo == r.hi) {
-                // one key value: the rows keep input order; compact them straight to the output
-                BufSet saved = x.bufs;
-                x.bufs.key[BUF_A][0] = (char*)keys_out + out_row * (uint64_t)key_type;
-                x.bufs.rid[BUF_A][0] = rids_out + out_row;
-                const Exec::Range rr = r;
-                std::vector<Seg> roots{Seg{0, rr.rn, 0, 0, rr.lo, rr.hi, BUF_IN, (uint32_t)key_type}};
-                const uint64_t f[2] = {rr.lo, rr.hi};
-                TJ_RET(x.run_pass(roots, BUF_IN, BUF_A, f, [](const Seg&) {}));  // children unused
-                x.bufs = saved;
-                x.stats.single_key++;
-            } else {
-                TJ_RET(x.process_range(r.lo, r.hi, r.rn, 0, true, out_row));
-                TJ_RET(x.run_sort_leaves(keys_out, rids_out));
-            }
-            out_row += r.rn;
-        }
-        if (out_row != n) return TJ_E_INTERNAL;
+        // the budget binds: output columns plus a workspace window (sort_windowed)
+        x.stats.key_ranges = 1;
+        TJ_RET(x.sort_windowed(lo, hi, n, 0, false, 0, keys_out, rids_out, (char*)x.bufs.key[BUF_B][0],
+                               (char*)x.bufs.rid[BUF_B][0], x.cap_r));
     }
     TJ_CK(hipStreamSynchronize(x.st));
     x.stats.workspace_used = workspace_bytes;

@@ -352,6 +352,7 @@ struct tj_server {
         for (Job* j : b) {
             j->res.learned = 0;
             j->res.key_ranges = stats.key_ranges;
+            j->res.windows = stats.windows;
         }
     }
 
@@ -383,6 +384,7 @@ struct tj_server {
         j->res.status = rc;
         j->res.learned = stats.learned;
         j->res.key_ranges = stats.key_ranges;
+        j->res.windows = stats.windows;
     }
 
     void worker(int slot)

@@ -35,7 +35,8 @@ class Stats(ctypes.Structure):
                 ("workspace_used", ctypes.c_uint64), ("passes", ctypes.c_uint32),
                 ("leaves", ctypes.c_uint32), ("single_key", ctypes.c_uint32),
                 ("key_ranges", ctypes.c_uint32), ("learned", ctypes.c_uint32),
-                ("learned_overflow", ctypes.c_uint32), ("sample_rows", ctypes.c_uint64)]
+                ("learned_overflow", ctypes.c_uint32), ("windows", ctypes.c_uint32),
+                ("sample_rows", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -576,7 +577,7 @@ class Result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("op", ctypes.c_int), ("count", _u64),
                 ("queue_ms", ctypes.c_double), ("run_ms", ctypes.c_double),
                 ("total_ms", ctypes.c_double), ("learned", ctypes.c_uint32), ("key_ranges", ctypes.c_uint32),
-                ("fused", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
+                ("fused", ctypes.c_uint32), ("windows", ctypes.c_uint32)]
 
 
 class Server:
@@ -629,7 +630,7 @@ class Server:
         op, _, out0, out1 = self._keep.pop(ticket)
         out = {"status": r.status, "op": r.op, "count": int(r.count), "queue_ms": r.queue_ms, "run_ms": r.run_ms,
                "total_ms": r.total_ms, "learned": int(r.learned), "key_ranges": int(r.key_ranges),
-               "fused": int(r.fused)}
+               "fused": int(r.fused), "windows": int(r.windows)}
         if r.status == TJ_OK and op == TJ_OP_SORT:
             out["keys"], out["rids"] = out0, out1
         elif r.status == TJ_OK and op == TJ_OP_JOIN_MATERIALIZE:

@@ -150,7 +150,7 @@ def test_learned_falls_back_to_radix(tj):
     # the minimum budget: key ranges, radix
     mn, full = tj.workspace_query(tj.TJ_OP_SORT, tj.TJ_KEY_I64, len(k))
     ko, ro, st = tj.sort(dev(k), dev(r), stats=True, workspace_bytes=mn, **LEARN)
-    assert st["key_ranges"] > 1 and st["learned"] == 0
+    assert (st["key_ranges"] > 1 or st["windows"] > 0) and st["learned"] == 0
     assert np.array_equal(host(ko), ek) and np.array_equal(host(ro), er)
 
 

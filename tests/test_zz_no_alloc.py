@@ -58,9 +58,9 @@ def test_static_sort_equals_tj_sort(tj, kind, n1, n2):
         assert free1 == free0, "free device memory changed across the call: %d -> %d" % (free0, free1)
         assert torch.equal(ko, ek) and torch.equal(ro, er), "tj_sort_static differs from tj_sort"
         if call == 0:
-            assert st["key_ranges"] > 1, st  # the budget binds inside the scratch
+            assert st["key_ranges"] > 1 or st["windows"] > 0, st  # the budget binds inside the scratch
         else:
-            assert st["key_ranges"] == 1, st
+            assert st["key_ranges"] == 1 and st["windows"] == 0, st
         # a sample of positions against the oracle (the full oracle sort is slow at 2.5e7 rows)
         xk, xr = oracle.sort(k, r) if n <= (1 << 21) else (None, None)
         if xk is not None:

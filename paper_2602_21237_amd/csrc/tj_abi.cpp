@@ -417,6 +417,10 @@ struct Exec {
     uint64_t a_off = 0;     // sort: output row of buffer A's row 0
     bool write_keys = true; // partition passes write key columns (off: rid-only compaction)
     bool device_batching = true;  // the last level's leaves may be batched on the device
+    // join under a binding budget with every key range narrow enough that its
+    // filtered pass narrows the keys to 4 bytes: that pass takes a full digit
+    // (shift <= 32 is then certain) and the buffers hold 4-byte keys
+    bool narrow_ranges = false;
 
     // timing of this call's launches (when enabled)
     bool timed_on = false;
@@ -543,6 +547,7 @@ struct Exec {
         for (size_t i = 0; i < segs.size(); i++) {
             const Seg& s = segs[i];
             plan_digit(s.hi - s.lo, s.rn + s.sn, segs.size() <= FEW_SEGS, plan[i].shift, plan[i].bits);
+            if (filter && narrow_ranges) plan_digit(s.hi - s.lo, SMALL_SEG_ROWS, true, plan[i].shift, plan[i].bits);
             // join keys are narrowed to 4 bytes once every child spans at most
             // 2^32 ordinals; the sort writes its keys out and never narrows
             plan[i].kb_out = sh.join && write_keys && s.kb == 8 && plan[i].shift <= 32 ? 4u : s.kb;
@@ -1606,15 +1611,16 @@ uint64_t min_workspace(const Shape& s) { return table_bytes(tier_caps(0)) + min_
 
 uint64_t full_workspace(const Shape& s) { return table_bytes(tier_caps(TABLE_TIERS - 1)) + full_data_bytes(s); }
 
-// Lays out the ping-pong buffers inside the data region.
-void layout_data(Exec& x, char* p, uint64_t data_bytes, bool unlimited)
+// Lays out the ping-pong buffers inside the data region (keys of `kb` bytes:
+// the shape's key width, or 4 for a join whose key ranges narrow them).
+void layout_data(Exec& x, char* p, uint64_t data_bytes, bool unlimited, int kb)
 {
     const Shape& s = x.sh;
     const int nside = s.join ? 2 : 1;
     uint64_t cap[2] = {s.n_r, s.n_s};
     if (!unlimited) {
         // split the region between the sides in proportion to their rows
-        const uint64_t rb = row_bytes(s.kb, s.rids);
+        const uint64_t rb = row_bytes(kb, s.rids);
         const int nbuf = s.join ? 2 : 1;  // sort: only buffer B lives in the workspace
         const uint64_t slack = (uint64_t)ALIGN * 4 * nbuf * nside;
         const uint64_t avail = data_bytes > slack ? data_bytes - slack : 0;
@@ -1631,7 +1637,7 @@ void layout_data(Exec& x, char* p, uint64_t data_bytes, bool unlimited)
     for (int buf = (s.join ? BUF_A : BUF_B); buf <= BUF_B; buf++)
         for (int side = 0; side < nside; side++) {
             x.bufs.key[buf][side] = p;
-            p += align_up(cap[side] * (uint64_t)s.kb, ALIGN);
+            p += align_up(cap[side] * (uint64_t)kb, ALIGN);
             if (s.rids) {
                 x.bufs.rid[buf][side] = (const int32_t*)p;
                 p += align_up(cap[side] * 4, ALIGN);
@@ -1812,7 +1818,7 @@ static int sort_body(int key_type, const void* keys_in, const int32_t* rids_in, 
     char* p = (char*)workspace;
     char* end = p + workspace_bytes;
     TJ_RET(x.carve_tables(p, end));
-    layout_data(x, p, data_bytes, unlimited);
+    layout_data(x, p, data_bytes, unlimited, key_type);
     x.bufs.key[BUF_IN][0] = keys_in;
     x.bufs.rid[BUF_IN][0] = rids_in;
     x.bufs.key[BUF_A][0] = keys_out;
@@ -1928,7 +1934,7 @@ static int join_body(int key_type, const void* r_keys, const int32_t* r_rids, ui
     char* p = (char*)workspace;
     char* end = p + workspace_bytes;
     TJ_RET(x.carve_tables(p, end));
-    layout_data(x, p, data_bytes, unlimited);
+    layout_data(x, p, data_bytes, unlimited, key_type);
     x.bufs.key[BUF_IN][0] = r_keys;
     x.bufs.key[BUF_IN][1] = s_keys;
     x.bufs.rid[BUF_IN][0] = r_rids;
@@ -1987,6 +1993,13 @@ static int join_body(int key_type, const void* r_keys, const int32_t* r_rids, ui
     } else {
         // Ranges in key order; each range is counted, then written at the
         // running offset while the running total still fits the capacity.
+        // When the whole key span is below 2^41, every range's filtered pass
+        // narrows its keys to 4 bytes (a full digit leaves at most 2^32
+        // ordinals per child), so the buffers hold 4-byte keys and more rows.
+        if (key_type == 8 && hi - lo < (1ull << 41)) {
+            x.narrow_ranges = true;
+            layout_data(x, p, data_bytes, false, 4);
+        }
         std::vector<Exec::Range> ranges;
         TJ_RET(x.plan_ranges(lo, hi, ranges, 0));
         x.stats.key_ranges = (uint32_t)ranges.size();

@@ -71,8 +71,9 @@ typedef struct {
                                  inputs (1 = the inputs are read once) */
     uint32_t learned;         /* 1 when the first pass used the learned bucket function */
     uint32_t learned_overflow;/* buckets of that pass holding more than twice the mean */
-    uint32_t windows;         /* sort under a binding budget: runs of buckets taken through
-                                 the workspace window (0 when the budget does not bind) */
+    uint32_t windows;         /* under a binding budget, runs of buckets taken through the
+                                 workspace window (sort), or key ranges whose buckets took
+                                 further passes there (join); 0 when it does not bind */
     uint64_t sample_rows;     /* keys the learned model was fitted to */
 } tj_stats_t;
 

@@ -280,9 +280,10 @@ struct Seg {
     // them (4 bytes at index i + koff) inside that bucket's 8-byte footprint,
     // away from the 8-byte keys of other buckets in the same buffer.
     uint64_t koff_r = 0, koff_s = 0;
-    // Sort under a binding budget: row in the workspace window (buffer B)
-    // minus row in buffer A of the same data; 0 everywhere else.
-    int64_t wdisp = 0;
+    // Under a binding budget, rows taken through a packed workspace window
+    // (buffer B): row in B minus row in buffer A of the same data, for side 0
+    // (the sort's rows, R) and side 1 (S); 0 everywhere else.
+    int64_t wdisp = 0, wdisp_s = 0;
 };
 
 struct Unit {                 // a final piece of join output, ordered by key
@@ -421,6 +422,10 @@ struct Exec {
     // filtered pass narrows the keys to 4 bytes: that pass takes a full digit
     // (shift <= 32 is then certain) and the buffers hold 4-byte keys
     bool narrow_ranges = false;
+    // the join's key ranges pack their buckets that need further passes into
+    // buffer B, a window of win_r / win_s rows (layout_join_window)
+    bool window = false;
+    uint64_t win_r = 0, win_s = 0;
 
     // timing of this call's launches (when enabled)
     bool timed_on = false;
@@ -564,7 +569,7 @@ struct Exec {
         // while the host needs about 5 ns per child.
         if (segs.size() < DEVICE_BATCH_MIN_SEGS || learned) dev_ok = false;
         for (const Seg& sg : segs)
-            if (sg.wdisp) dev_ok = false;  // device leaves take one output offset
+            if (sg.wdisp || sg.wdisp_s) dev_ok = false;  // device leaves: one buffer mapping
         if (dev_ok)
             for (size_t i = 0; i < segs.size(); i++)
                 if (((segs[i].rn + segs[i].sn) >> plan[i].bits) > (uint64_t)LEAF_CAP / 2) dev_ok = false;
@@ -626,9 +631,11 @@ struct Exec {
                     const uint64_t len = filter ? (side ? sh.n_s : sh.n_r) : (side ? s.sn : s.rn);
                     g.start = filter ? 0 : (side ? s.s0 : s.r0);
                     g.len = len;
-                    g.dst_start = filter ? 0 : (side ? s.s0 : s.r0);
-                    if (!filter && side == 0)  // into or out of the window
-                        g.dst_start += (dst == BUF_B ? s.wdisp : 0) - (src == BUF_B ? s.wdisp : 0);
+                    g.dst_start = side ? s.s0 : s.r0;  // a filtered root's rows start there too
+                    if (!filter) {  // into or out of the window
+                        const int64_t w = side ? s.wdisp_s : s.wdisp;
+                        g.dst_start += (dst == BUF_B ? w : 0) - (src == BUF_B ? w : 0);
+                    }
                     g.base = learned ? 0 : s.lo;
                     g.flo = filter ? filter[0] : 0;
                     g.fhi = filter ? filter[1] : ~0ull;
@@ -644,7 +651,9 @@ struct Exec {
                     g.flags = (g_debug_flags.load() & TJ_DEBUG_FORCE_REORDER) ? GROUP_FORCE_REORDER : 0u;
                     if (spec) g.flags |= GROUP_CHECK_RANGE;
                     g.src_koff = filter ? 0 : (side ? s.koff_s : s.koff_r);
-                    g.dst_koff = plan[si].kb_out < kb_in ? g.dst_start : g.src_koff;
+                    // narrowed keys: at their rows' index in 4-byte key buffers, else
+                    // inside the 8-byte footprint of the bucket that narrowed them
+                    g.dst_koff = plan[si].kb_out < kb_in ? (narrow_ranges ? 0 : g.dst_start) : g.src_koff;
                     const uint32_t gi = (uint32_t)groups.size();
                     for (uint64_t c0 = 0; c0 < len; c0 += ch_rows) {
                         ChunkDesc c{};
@@ -834,6 +843,7 @@ struct Exec {
                     c.koff_r = koff_r;
                     c.koff_s = koff_s;
                     c.wdisp = segs[gseg[gi]].wdisp;
+                    c.wdisp_s = segs[gseg[gi]].wdisp_s;
                     if (narrowing && c.lo <= c.hi) {
                         // keys now hold (ord - g.base) mod 2^32 (see k_scatter)
                         const uint64_t off = c.lo - g0.base;
@@ -875,6 +885,8 @@ struct Exec {
             TJ_CK(hipMemcpyAsync(leaves.data() + n0, d_leaves, (size_t)dev_leaves * sizeof(LeafDesc),
                                  hipMemcpyDeviceToHost, st));
             TJ_CK(hipStreamSynchronize(st));
+            if (sh.join)  // the device leaves the join's `out` at 0: set its key-order position
+                for (size_t i = n0; i < leaves.size(); i++) leaves[i].out = leaves[i].r0;
         }
         dev_leaves = 0;
         dev_rows = 0;
@@ -884,7 +896,7 @@ struct Exec {
     }
 
     bool cl_open = false, cl_useful = false;
-    int64_t cl_wdisp = 0;
+    int64_t cl_wdisp = 0, cl_wdisp_s = 0;
     LeafDesc cl_cur{};
     uint64_t cl_lo = 0, cl_hi = 0, cl_win = 0;
     uint32_t cl_kb = 0;
@@ -896,7 +908,9 @@ struct Exec {
             cl_cur.bits = (uint16_t)nbits64(cl_hi - cl_lo);
             cl_cur.kb = (uint16_t)cl_kb;
             cl_cur.flags = (g_debug_flags.load() & TJ_DEBUG_FORCE_REORDER) ? LEAF_FORCE_REORDER : 0;
-            cl_cur.out = sh.join ? 0 : cl_cur.r0 + out_delta - (cl_cur.buf == BUF_B ? cl_wdisp : 0);
+            // sort: output row; join: key-order position (row in buffer A), the
+            // order finish_join takes units in before it reuses the field
+            cl_cur.out = (sh.join ? cl_cur.r0 : cl_cur.r0 + out_delta) - (cl_cur.buf == BUF_B ? cl_wdisp : 0);
             leaves.push_back(cl_cur);
         }
         cl_open = false;
@@ -913,7 +927,7 @@ struct Exec {
         if (rows <= (uint64_t)LEAF_CAP) {
             const bool adjacent = cl_open && cl_cur.buf == s.buf && cl_kb == s.kb && cl_win == s.win &&
                                   cl_cur.kr0 - cl_cur.r0 == s.koff_r && cl_cur.ks0 - cl_cur.s0 == s.koff_s &&
-                                  cl_cur.r0 + cl_cur.rn == s.r0 && cl_wdisp == s.wdisp &&
+                                  cl_cur.r0 + cl_cur.rn == s.r0 && cl_wdisp == s.wdisp && cl_wdisp_s == s.wdisp_s &&
                                   (!sh.join || cl_cur.s0 + cl_cur.sn == s.s0) &&
                                   cl_cur.rn + cl_cur.sn + rows <= (uint64_t)LEAF_CAP;
             if (!adjacent) {
@@ -930,6 +944,7 @@ struct Exec {
                 cl_kb = s.kb;
                 cl_win = s.win;
                 cl_wdisp = s.wdisp;
+                cl_wdisp_s = s.wdisp_s;
             }
             cl_cur.rn += (uint32_t)s.rn;
             cl_cur.sn += (uint32_t)s.sn;
@@ -949,6 +964,7 @@ struct Exec {
                 c.a = s.rn;
                 c.b = s.sn;
                 c.buf = s.buf;
+                c.out = s.r0 - (s.buf == BUF_B ? s.wdisp : 0);  // key-order position (see classify_flush)
                 crosses.push_back(c);
             } else if (!(out_is_a && s.buf == BUF_A && out_delta == a_off)) {
                 CopyDesc c{};
@@ -1036,6 +1052,48 @@ struct Exec {
             classify_one(root, next, out_delta);
         }
         classify_flush(out_delta);
+        if (filtered && window && !next.empty()) {
+            // The buckets that need further passes are packed one after
+            // another into the window. While they do not fit, the largest is
+            // read again from the input, filtered to its key range, into its
+            // own rows of A with a full digit of that narrower range (its keys
+            // are still there): its children replace it.
+            for (int it = 0;; it++) {
+                uint64_t ur = 0, us = 0;
+                size_t big = 0;
+                for (size_t i = 0; i < next.size(); i++) {
+                    ur += next[i].rn;
+                    us += next[i].sn;
+                    if (next[i].rn * win_s + next[i].sn * win_r > next[big].rn * win_s + next[big].sn * win_r) big = i;
+                }
+                if (ur <= win_r && us <= win_s) break;
+                if (it >= 4096) return TJ_E_INTERNAL;
+                const Seg c = next[big];
+                next.erase(next.begin() + (std::ptrdiff_t)big);
+                Seg again{};
+                again.kb = (uint32_t)sh.kb;
+                again.r0 = c.r0;
+                again.rn = c.rn;
+                again.s0 = c.s0;
+                again.sn = c.sn;
+                again.lo = c.win == ~0ull ? c.lo : c.win + c.lo;  // ordinals of the input keys
+                again.hi = c.win == ~0ull ? c.hi : c.win + c.hi;
+                again.buf = BUF_IN;
+                std::vector<Seg> roots{again};
+                const uint64_t f[2] = {again.lo, again.hi};
+                stats.key_ranges++;  // one more read of the inputs
+                TJ_RET(run_pass(roots, BUF_IN, BUF_A, f, to_next));
+                classify_flush(out_delta);
+            }
+            uint64_t ur = 0, us = 0;
+            for (Seg& g : next) {
+                g.wdisp = (int64_t)ur - (int64_t)g.r0;
+                g.wdisp_s = (int64_t)us - (int64_t)g.s0;
+                ur += g.rn;
+                us += g.sn;
+            }
+            stats.windows++;
+        }
         uint32_t cur = filtered ? (uint32_t)BUF_A : (uint32_t)BUF_IN;
         for (int depth = 0; depth < 80; depth++) {
             if (next.empty()) return TJ_OK;
@@ -1258,8 +1316,9 @@ struct Exec {
             return TJ_OK;
         }
         HostTimer ht(this, F_HOST_LEAVES);
-        auto lr0 = [](const LeafDesc& a, const LeafDesc& b) { return a.r0 < b.r0; };
-        auto cr0 = [](const CrossDesc& a, const CrossDesc& b) { return a.r0 < b.r0; };
+        // key order: the units' R rows in buffer A (LeafDesc/CrossDesc::out until batched)
+        auto lr0 = [](const LeafDesc& a, const LeafDesc& b) { return a.out < b.out; };
+        auto cr0 = [](const CrossDesc& a, const CrossDesc& b) { return a.out < b.out; };
         if (!std::is_sorted(leaves.begin(), leaves.end(), lr0)) std::sort(leaves.begin(), leaves.end(), lr0);
         if (!std::is_sorted(crosses.begin(), crosses.end(), cr0)) std::sort(crosses.begin(), crosses.end(), cr0);
         stats.leaves += (uint32_t)leaves.size();
@@ -1311,7 +1370,7 @@ struct Exec {
                 int bkb = 0;       // key width of the batch's leaves
                 while (li < leaves.size() || ci < crosses.size()) {
                     const bool take_cross =
-                        ci < crosses.size() && (li == leaves.size() || crosses[ci].r0 < leaves[li].r0);
+                        ci < crosses.size() && (li == leaves.size() || crosses[ci].out < leaves[li].out);
                     if (take_cross) {
                         if (bc.size() == caps.units) break;
                         CrossDesc c = crosses[ci++];
@@ -1618,6 +1677,7 @@ void layout_data(Exec& x, char* p, uint64_t data_bytes, bool unlimited, int kb)
     const Shape& s = x.sh;
     const int nside = s.join ? 2 : 1;
     uint64_t cap[2] = {s.n_r, s.n_s};
+    x.window = false;
     if (!unlimited) {
         // split the region between the sides in proportion to their rows
         const uint64_t rb = row_bytes(kb, s.rids);
@@ -1641,6 +1701,42 @@ void layout_data(Exec& x, char* p, uint64_t data_bytes, bool unlimited, int kb)
             if (s.rids) {
                 x.bufs.rid[buf][side] = (const int32_t*)p;
                 p += align_up(cap[side] * 4, ALIGN);
+            }
+        }
+}
+
+// Budget-bound join whose ranges hold 4-byte keys: buffer A (a key range's
+// rows) takes WINDOW_A_NUM / WINDOW_DEN of the data region and buffer B the
+// rest, as a window into which the range's buckets that need further passes
+// are packed (Exec::window); each side in proportion to its rows.
+constexpr uint64_t WINDOW_A_NUM = 7, WINDOW_DEN = 8;
+void layout_join_window(Exec& x, char* p, uint64_t data_bytes)
+{
+    const Shape& s = x.sh;
+    const uint64_t rb = row_bytes(4, s.rids);
+    const uint64_t slack = (uint64_t)ALIGN * 16;
+    const uint64_t avail = data_bytes > slack ? data_bytes - slack : 0;
+    const uint64_t tot = s.n_r + s.n_s;
+    uint64_t cap[2][2];  // [buffer A/B][side]
+    for (int side = 0; side < 2; side++) {
+        const uint64_t n = side ? s.n_s : s.n_r;
+        const long double part = (long double)avail * (long double)n / (long double)tot / (long double)rb;
+        cap[0][side] = std::min<uint64_t>(n, (uint64_t)(part * WINDOW_A_NUM / WINDOW_DEN));
+        cap[1][side] = std::min<uint64_t>(n, (uint64_t)(part * (WINDOW_DEN - WINDOW_A_NUM) / WINDOW_DEN));
+    }
+    x.cap_r = cap[0][0];
+    x.cap_s = cap[0][1];
+    x.win_r = cap[1][0];
+    x.win_s = cap[1][1];
+    x.window = true;
+    for (int b = 0; b < 2; b++)
+        for (int side = 0; side < 2; side++) {
+            const int buf = b ? BUF_B : BUF_A;
+            x.bufs.key[buf][side] = p;
+            p += align_up(cap[b][side] * 4, ALIGN);
+            if (s.rids) {
+                x.bufs.rid[buf][side] = (const int32_t*)p;
+                p += align_up(cap[b][side] * 4, ALIGN);
             }
         }
 }
@@ -1996,9 +2092,12 @@ static int join_body(int key_type, const void* r_keys, const int32_t* r_rids, ui
         // When the whole key span is below 2^41, every range's filtered pass
         // narrows its keys to 4 bytes (a full digit leaves at most 2^32
         // ordinals per child), so the buffers hold 4-byte keys and more rows.
+        // Those buffers are then also laid out unequally: most of the region
+        // holds a range's rows, the rest is a window for its buckets that need
+        // further passes (layout_join_window).
         if (key_type == 8 && hi - lo < (1ull << 41)) {
             x.narrow_ranges = true;
-            layout_data(x, p, data_bytes, false, 4);
+            layout_join_window(x, p, data_bytes);
         }
         std::vector<Exec::Range> ranges;
         TJ_RET(x.plan_ranges(lo, hi, ranges, 0));

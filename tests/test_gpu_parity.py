@@ -305,6 +305,43 @@ def test_budget_windowed_sort(tj, name):
     assert np.array_equal(host(ko), ek) and np.array_equal(host(ro), er)
 
 
+@pytest.mark.parametrize("variant", ["window", "refilter"])
+def test_budget_join_window(tj, variant):
+    """Budget-bound join with 4-byte range keys: a key range whose bucket of
+    three neighbouring keys (more rows than a leaf holds) needs another pass
+    takes it through the workspace window, where its keys become single-key
+    units that are output in key order among the range's other units
+    ("window"); when that bucket has more rows than the window, it is read
+    again from the input, filtered to its key range, into its own rows
+    ("refilter"). Counts and pairs equal the oracle's."""
+    rng = np.random.default_rng(21)
+    n = 100_000
+    base = rng.choice(1 << 40, n + 20_000, replace=False).astype(np.int64)
+    k0 = (1 << 35) + 123456
+    base = base[(base < k0 - 8) | (base > k0 + 8)]
+    rk0, fresh = base[:n], base[n:]
+    if variant == "window":
+        hot_r = [1000, 1000, 2500]
+        hot_s = [2500, 1000, 1000]
+    else:
+        hot_r = [6000, 5000, 4000]
+        hot_s = [3000, 2000, 1000]
+    rk = np.concatenate([rk0] + [np.full(c, k0 + i, np.int64) for i, c in enumerate(hot_r)])
+    sk = np.concatenate([rk0[rng.integers(0, n, 80_000)], fresh[:20_000]] +
+                        [np.full(c, k0 + i, np.int64) for i, c in enumerate(hot_s)])
+    rng.shuffle(rk)
+    rng.shuffle(sk)
+    rr = rng.permutation(rk.size).astype(np.int32)
+    sr = rng.permutation(sk.size).astype(np.int32)
+    print("budget join window %s" % variant, flush=True)
+    check_join(tj, rk, rr, sk, sr, workspace_bytes=1 << 20)
+    pr, _, st = tj.join(dev(rk), dev(rr), dev(sk), dev(sr), workspace_bytes=1 << 20, stats=True)
+    if variant == "window":
+        assert st["windows"] >= 1, st
+    else:
+        assert st["key_ranges"] >= 2 and st["single_key"] >= 1, st
+
+
 # --------------------------------------------------------------------------- profiling hook
 
 def test_timing_hook_counts_launches(tj):

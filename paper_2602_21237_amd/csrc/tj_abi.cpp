@@ -416,6 +416,9 @@ struct Exec {
     uint64_t cap_r = 0, cap_s = 0;
     bool out_is_a = false;  // sort: buffer A is the caller's output
     uint64_t a_off = 0;     // sort: output row of buffer A's row 0
+    // sort under a binding budget: leaves whose rows are already in the output
+    // columns (rows counted from the columns' start), sorted in one launch at the end
+    std::vector<LeafDesc> deferred;
     bool write_keys = true; // partition passes write key columns (off: rid-only compaction)
     bool device_batching = true;  // the last level's leaves may be batched on the device
     // join under a binding budget with every key range narrow enough that its
@@ -1109,6 +1112,26 @@ struct Exec {
         return TJ_E_INTERNAL;
     }
 
+    // Leaves of buffer A (the output columns from row a_off) wait for the
+    // end of the call in `deferred`; the others (in the window, or read from
+    // the input) are sorted now, before their rows can be overwritten.
+    int run_window_leaves(void* out_k, int32_t* out_r)
+    {
+        size_t keep = 0;
+        for (size_t i = 0; i < leaves.size(); i++) {
+            LeafDesc L = leaves[i];
+            if (L.buf == BUF_A) {
+                L.r0 += a_off;
+                L.kr0 += a_off;
+                deferred.push_back(L);
+            } else {
+                leaves[keep++] = L;
+            }
+        }
+        leaves.resize(keep);
+        return run_sort_leaves(out_k, out_r);
+    }
+
     // ---- sort under a binding budget: output columns plus a window ---------
     // Sorts the `rows` rows with keys in [lo, hi] into output rows [o, o +
     // rows). Buffer A is the output columns from row o. The first pass reads
@@ -1158,7 +1181,7 @@ struct Exec {
             }
         }
         classify_flush(o);
-        TJ_RET(run_sort_leaves(out_k, out_r));
+        TJ_RET(run_window_leaves(out_k, out_r));
         size_t i = 0;
         while (i < level.size()) {
             if (level[i].rn > wrows) {
@@ -1189,10 +1212,19 @@ struct Exec {
                 next.swap(next2);
                 cur = dst;
             }
-            TJ_RET(run_sort_leaves(out_k, out_r));
+            TJ_RET(run_window_leaves(out_k, out_r));
         }
         for (const Seg& b : big)
             TJ_RET(sort_windowed(b.lo, b.hi, b.rn, o + b.r0, true, depth + 1, out_k, out_r, wk, wr, wrows));
+        if (depth == 0 && !deferred.empty()) {
+            // the leaves already in the output columns, all in one launch
+            bufs.key[BUF_A][0] = out_k;
+            bufs.rid[BUF_A][0] = out_r;
+            a_off = 0;
+            leaves.swap(deferred);
+            deferred.clear();
+            TJ_RET(run_sort_leaves(out_k, out_r));
+        }
         return TJ_OK;
     }
 

@@ -305,6 +305,24 @@ def test_budget_windowed_sort(tj, name):
     assert np.array_equal(host(ko), ek) and np.array_equal(host(ro), er)
 
 
+@pytest.mark.parametrize("n,bits,budget", [(1 << 21, 32, 2 << 20), (300_001, 12, 1 << 20), (70_000, 64, 1 << 20)])
+def test_budget_sort_shapes(tj, n, bits, budget):
+    """Budget-bound sorts beyond the int64 cases: int32 keys over the full
+    range and over 2^12 values (every bucket a few keys, many single-key
+    buckets already final in the output), and full-range int64 keys a little
+    above the rows the 1 MiB window holds; against the oracle."""
+    if bits == 64:
+        k = tjgen.uniform_i64(n, 91)
+    else:
+        k = tjgen.uniform_i32(n, 92, bits)
+    r = tjgen.perm_i32(n, 93)
+    print("budget sort n=%d bits=%d budget=%d" % (n, bits, budget), flush=True)
+    ko, ro, st = tj.sort(dev(k), dev(r), stats=True, workspace_bytes=budget)
+    ek, er = oracle.sort(k, r)
+    assert np.array_equal(host(ko), ek) and np.array_equal(host(ro), er)
+    assert st["key_ranges"] >= 1
+
+
 @pytest.mark.parametrize("variant", ["window", "refilter"])
 def test_budget_join_window(tj, variant):
     """Budget-bound join with 4-byte range keys: a key range whose bucket of

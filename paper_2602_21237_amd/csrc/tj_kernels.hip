@@ -1473,14 +1473,19 @@ __device__ __forceinline__ uint32_t lds_upper_bound(const KW* a, uint32_t lo, ui
     return lo;
 }
 
+// A status word carries its whole message (flag and value in one 64-bit word)
+// and no other data is published through it, so relaxed device-scope atomics
+// suffice: release/acquire would make every block wait for its earlier
+// memory operations and write back or invalidate its L2 (each XCD has its
+// own) on the way.
 __device__ __forceinline__ void status_store(uint64_t* p, uint64_t v)
 {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ uint64_t status_load(const uint64_t* p)
 {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Exclusive prefix of bucket `slot - 1` (slot >= 1), computed by one whole

@@ -1708,35 +1708,41 @@ __attribute__((amdgpu_waves_per_eu(4))) void k_leaf_join(const LeafDesc* __restr
 #pragma unroll
     for (int i = 0; i < KI; i++) rid[i] = p0 + i < n ? lds_w[id[i]] : 0;
     lds_barrier();  // the key array becomes the pair staging buffer
-    constexpr uint32_t OC = C / 2;  // pairs per staged chunk: two int32 columns in the key array
-    if (ltot <= 8 * OC && maxslots <= 64) {
-        // Staged: items scatter their slots of the chunk into LDS, then the chunk
-        // leaves as two coalesced runs.
-        int32_t* st_r = lds_w;
-        int32_t* st_s = lds_w + OC;
-        for (uint32_t c0 = 0; c0 < ltot; c0 += OC) {
-            const uint32_t c1 = c0 + OC;
+    constexpr uint32_t SC = C * sizeof(KW) / 4;  // int32 slots of the key array
+    if (ltot <= 4 * SC && maxslots <= 64) {
+        // Staged, one output column at a time: that column's items scatter
+        // their slots of the chunk into LDS, then the chunk leaves as one
+        // coalesced run. An R item's slots are consecutive, so it visits only
+        // those inside the chunk.
+        int32_t* st = lds_w;
+        for (int side = 0; side < 2; side++) {
+            int32_t* __restrict__ dst = side ? out_s : out_r;
+            for (uint32_t c0 = 0; c0 < ltot; c0 += SC) {
+                const uint32_t c1 = c0 + SC;
 #pragma unroll
-            for (int i = 0; i < KI; i++) {
-                const uint32_t pk = packv[i];
-                const uint32_t sl = (pk >> 14) & 0x3fffu, stride = pk & 0x3fffu;
-                const uint32_t f = firstv[i];
-                int32_t* st = (pk >> 31) ? st_r : st_s;
-                for (uint32_t j = 0; j < sl; j++) {
-                    const uint32_t t = f + j * stride;
-                    if (t >= c0 && t < c1) st[t - c0] = rid[i];
+                for (int i = 0; i < KI; i++) {
+                    const uint32_t pk = packv[i];
+                    const uint32_t sl = (pk >> 14) & 0x3fffu, stride = pk & 0x3fffu;
+                    const uint32_t f = firstv[i];
+                    if (side == 0 && (pk >> 31)) {
+                        const uint32_t j0 = f < c0 ? c0 - f : 0u;
+                        const uint32_t j1 = f + sl < c1 ? sl : (c1 > f ? c1 - f : 0u);
+                        for (uint32_t j = j0; j < j1; j++) st[f + j - c0] = rid[i];
+                    } else if (side == 1 && !(pk >> 31)) {
+                        for (uint32_t j = 0; j < sl; j++) {
+                            const uint32_t t = f + j * stride;
+                            if (t >= c0 && t < c1) st[t - c0] = rid[i];
+                        }
+                    }
                 }
-            }
-            lds_barrier();
-            const uint32_t cn = ltot - c0 < OC ? ltot - c0 : OC;
-            for (uint32_t t = threadIdx.x; t < cn; t += NT) {
-                const uint64_t o = base + c0 + t;
-                if (o < capacity) {
-                    out_r[o] = st_r[t];
-                    out_s[o] = st_s[t];
+                lds_barrier();
+                const uint32_t cn = ltot - c0 < SC ? ltot - c0 : SC;
+                for (uint32_t t = threadIdx.x; t < cn; t += NT) {
+                    const uint64_t o = base + c0 + t;
+                    if (o < capacity) dst[o] = st[t];
                 }
+                lds_barrier();
             }
-            lds_barrier();
         }
         return;
     }

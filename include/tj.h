@@ -116,8 +116,8 @@ int tj_sort(int key_type, const void *keys_in, const int32_t *rids_in, uint64_t 
  * Same arguments, semantics, results and errors as tj_sort, without the
  * workspace: the call uses a device array of TJ_STATIC_SCRATCH_BYTES (256 MiB)
  * that the library holds on every GPU it runs on, from the library's load
- * until the process ends, as its workspace budget. Inputs of up to 22,322,688
- * int64 rows (33,484,032 int32 rows) run the unlimited plan; larger ones run
+ * until the process ends, as its workspace budget. Inputs of up to 22,346,560
+ * int64 rows (33,519,872 int32 rows) run the unlimited plan; larger ones run
  * the budget-bound plan (the array as the window of tj_sort under a binding
  * budget), so results never change, only time.
  * The call makes no device or pinned-host allocation (its read-backs go to

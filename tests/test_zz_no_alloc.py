@@ -3,9 +3,9 @@ tj_sort with a caller workspace: bit-exact outputs on two calls in a row, the
 second with a smaller input, plus the oracle on a sample of positions; the
 call leaves the device's free memory unchanged.
 
-The first call is larger than the scratch's unlimited plan (beyond 22,322,688
-int64 or 33,484,032 int32 rows), so it runs the budget-bound plan (several key
-ranges) inside the scratch; the second fits the unlimited plan.
+The first call is larger than the scratch's unlimited plan (beyond 22,346,560
+int64 or 33,519,872 int32 rows), so it runs the budget-bound plan (its output
+columns plus a window of the scratch); the second fits the unlimited plan.
 """
 import numpy as np
 import pytest

@@ -214,14 +214,15 @@ typedef struct {
 } tj_rmi_t;
 
 /*
- * TJ_PART_AUTO decides at execution time from the data: the call starts the
- * radix path, and once the first pass's histogram is known (before anything
- * is moved) it reads back the bucket counts. If one bucket holds more than
- * half of all rows, the digit has not separated the bulk of the keys from a
- * long tail (each radix level narrows the digit to its bucket's key range,
- * which splits a few dense intervals at the next level but not a heavy
- * tail): the call trains the learned model and partitions with it instead.
- * Otherwise it continues with radix, at the cost of that one read-back.
+ * TJ_PART_AUTO decides at execution time from the data, by the first radix
+ * digit's bucket counts: if one bucket holds more than half of all rows, the
+ * digit has not separated the bulk of the keys from a long tail (each radix
+ * level narrows the digit to its bucket's key range, which splits a few dense
+ * intervals at the next level but not a heavy tail), and the call trains the
+ * learned model and partitions with it; otherwise it runs radix. Calls of at
+ * least 2^22 rows with the full workspace count every 4096th key (the sample
+ * their first digit range is taken from, read back to the host); smaller ones
+ * count the first pass's histogram, before anything is moved.
  */
 enum tj_partitioner { TJ_PART_RADIX = 0, TJ_PART_LEARNED = 1, TJ_PART_AUTO = 2 };
 typedef struct {

@@ -1814,6 +1814,38 @@ int sampled_range(Exec& x, const void* a, uint64_t na, const void* b, uint64_t n
     return TJ_OK;
 }
 
+// TJ_PART_AUTO on a call with a sampled first range: the digit histogram of
+// that sample (every SAMPLED_PROBE_STEP-th key of each side, gathered into
+// `scratch`, device memory nothing uses yet) takes the decision the first
+// pass's histogram would take, without a pass over the rows: learned when one
+// bucket of the first radix digit over [lo, hi] holds more than half of them.
+int sample_wants_learned(Exec& x, const void* a, uint64_t na, const void* b, uint64_t nb, uint64_t lo,
+                         uint64_t hi, uint64_t* scratch, bool& learned)
+{
+    const uint64_t ma = (na + SAMPLED_PROBE_STEP - 1) / SAMPLED_PROBE_STEP;
+    const uint64_t mb = (nb + SAMPLED_PROBE_STEP - 1) / SAMPLED_PROBE_STEP;
+    TJ_CK(launch_gather_step(x.sh.kb, a, na, SAMPLED_PROBE_STEP, scratch, x.st));
+    if (nb) TJ_CK(launch_gather_step(x.sh.kb, b, nb, SAMPLED_PROBE_STEP, scratch + ma, x.st));
+    uint64_t* h = (uint64_t*)pinned_down((size_t)(ma + mb) * 8);
+    if (!h) return TJ_E_HIP;
+    TJ_CK(hipMemcpyAsync(h, scratch, (size_t)(ma + mb) * 8, hipMemcpyDeviceToHost, x.st));
+    TJ_CK(hipStreamSynchronize(x.st));
+    x.stats.bytes_read += (ma + mb) * (uint64_t)x.sh.kb;
+    uint32_t shift, bits;
+    plan_digit(hi - lo, na + nb, true, shift, bits);  // the first pass's digit
+    std::vector<uint64_t> cnt((size_t)1 << bits, 0);
+    const uint64_t mask = (1ull << bits) - 1;
+    uint64_t largest = 0;
+    for (uint64_t i = 0; i < ma + mb; i++) {
+        const uint64_t o = h[i];
+        if (o < lo || o > hi) continue;
+        const uint64_t c = ++cnt[(size_t)(((o - lo) >> shift) & mask)];
+        largest = std::max(largest, c);
+    }
+    learned = AUTO_BULK_DEN * largest > ma + mb;
+    return TJ_OK;
+}
+
 }  // namespace
 }  // namespace tj
 
@@ -1981,8 +2013,21 @@ static int sort_body(int key_type, const void* keys_in, const int32_t* rids_in, 
         if (unlimited && n >= SAMPLED_PROBE_MIN_ROWS) {
             TJ_RET(sampled_range(x, keys_in, n, nullptr, 0, lo, hi));
             spec = hi > lo;
+            if (spec && want_learned && is_auto) {
+                // auto decides from the same sample (buffer B is still free)
+                bool to_learned = false;
+                TJ_RET(sample_wants_learned(x, keys_in, n, nullptr, 0, lo, hi, (uint64_t*)x.bufs.key[BUF_B][0],
+                                            to_learned));
+                is_auto = false;
+                want_learned = to_learned;
+                if (to_learned) {
+                    const int rc = train();
+                    if (rc != TJ_OK && rc != TJ_E_WORKSPACE) return rc;
+                    learned = rc == TJ_OK;
+                }
+            }
         }
-        if (!spec) TJ_RET(probe(x, keys_in, n, nullptr, 0, lo, hi));
+        if (!spec && !learned) TJ_RET(probe(x, keys_in, n, nullptr, 0, lo, hi));
     }
     if (unlimited) {
         x.stats.key_ranges = 1;
@@ -2094,8 +2139,20 @@ static int join_body(int key_type, const void* r_keys, const int32_t* r_rids, ui
         if (unlimited && n_r + n_s >= SAMPLED_PROBE_MIN_ROWS) {  // as in tj_sort
             TJ_RET(sampled_range(x, r_keys, n_r, s_keys, n_s, lo, hi));
             spec = hi > lo;
+            if (spec && want_learned && is_auto) {
+                bool to_learned = false;
+                TJ_RET(sample_wants_learned(x, r_keys, n_r, s_keys, n_s, lo, hi, (uint64_t*)x.bufs.key[BUF_B][0],
+                                            to_learned));
+                is_auto = false;
+                want_learned = to_learned;
+                if (to_learned) {
+                    const int rc = train();
+                    if (rc != TJ_OK && rc != TJ_E_WORKSPACE) return rc;
+                    learned = rc == TJ_OK;
+                }
+            }
         }
-        if (!spec) TJ_RET(probe(x, r_keys, n_r, s_keys, n_s, lo, hi));
+        if (!spec && !learned) TJ_RET(probe(x, r_keys, n_r, s_keys, n_s, lo, hi));
     }
     uint64_t total = 0;
     if (unlimited) {

@@ -160,6 +160,8 @@ hipError_t launch_fill_u64(uint64_t* p, uint64_t n, uint64_t v, hipStream_t st);
 hipError_t launch_probe(int key_bytes, const void* a, uint64_t na, const void* b, uint64_t nb,
                         uint64_t* minmax, hipStream_t st);
 // Min and max ordinal of every step-th element of a and of b (step 1: all).
+// out[i] = ordinal of a[i * step], i < ceil(n / step)
+hipError_t launch_gather_step(int key_bytes, const void* a, uint64_t n, uint64_t step, uint64_t* out, hipStream_t st);
 hipError_t launch_probe_step(int key_bytes, const void* a, uint64_t na, const void* b, uint64_t nb,
                              uint64_t step, uint64_t* minmax, hipStream_t st);
 // range_miss: set to nonzero when a GROUP_CHECK_RANGE group has a row outside its digit range.

@@ -374,6 +374,32 @@ hipError_t launch_probe(int key_bytes, const void* a, uint64_t na, const void* b
     return launch_probe_step(key_bytes, a, na, b, nb, 1, minmax, st);
 }
 
+// Every step-th key of a column, as its ordinal: out[i] = ord(a[i * step]) for
+// i < ceil(n / step).
+template <typename K>
+__global__ __launch_bounds__(256) void k_gather_step(const K* __restrict__ a, uint64_t n, uint64_t step,
+                                                     uint64_t* __restrict__ out)
+{
+    const uint64_t m = (n + step - 1) / step;
+    for (uint64_t i = blockIdx.x * 256ull + threadIdx.x; i < m; i += (uint64_t)gridDim.x * 256) out[i] = ord_of(a[i * step]);
+}
+
+hipError_t launch_gather_step(int key_bytes, const void* a, uint64_t n, uint64_t step, uint64_t* out, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    if (step < 1) step = 1;
+    const uint64_t m = (n + step - 1) / step;
+    uint64_t blocks = (m + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    if (key_bytes == 4)
+        hipLaunchKernelGGL(k_gather_step<int32_t>, dim3((uint32_t)blocks), dim3(256), 0, st, (const int32_t*)a, n,
+                           step, out);
+    else
+        hipLaunchKernelGGL(k_gather_step<int64_t>, dim3((uint32_t)blocks), dim3(256), 0, st, (const int64_t*)a, n,
+                           step, out);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // radix histogram: per chunk, the digit counts of its rows (and, per group
 // and digit, the smallest and largest ordinal, so that every child bucket

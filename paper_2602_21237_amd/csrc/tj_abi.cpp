@@ -130,7 +130,7 @@ struct PinnedBuf {
     }
 };
 thread_local PinnedBuf* t_down = nullptr;
-thread_local PinnedBuf* t_up = nullptr;
+thread_local PinnedBuf* t_up[2] = {nullptr, nullptr};
 
 // Set while a call runs without allocating (tj_sort_static): read-backs then
 // land in grow-only pageable host memory instead of pinned staging, and the
@@ -149,10 +149,23 @@ void* pinned_down(size_t n)
     return t_down->get(n);
 }
 
-void* pinned_up(size_t n)
+void* pinned_up(size_t n, int slot)
 {
-    if (!t_up) t_up = new PinnedBuf();
-    return t_up->get(n);
+    if (t_noalloc) return nullptr;  // uploads then go from the caller's pageable memory
+    if (!t_up[slot]) t_up[slot] = new PinnedBuf();
+    return t_up[slot]->get(n);
+}
+
+// Host-to-device copy of a planner table on `st`. Large tables go through a
+// pinned staging buffer (a pageable source is copied in small synchronous
+// pieces), one per slot (0: leaves, 1: cross or copy units); the caller
+// synchronises `st` before it writes the next upload of the same slot.
+hipError_t upload(void* dst, const void* src, size_t bytes, hipStream_t st, int slot)
+{
+    void* pin = bytes >= (256u << 10) ? pinned_up(bytes, slot) : nullptr;
+    if (!pin) return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+    std::memcpy(pin, src, bytes);
+    return hipMemcpyAsync(dst, pin, bytes, hipMemcpyHostToDevice, st);
 }
 
 // Bytes of one row in the ping-pong buffers.
@@ -335,9 +348,32 @@ thread_local int t_nested = 0;
 // Process-wide self-test flags (tj_debug_set_flags).
 std::atomic<uint32_t> g_debug_flags{0};
 
+// Stable sort of (position, index) pairs by position, `top` the largest
+// position: LSD radix, 11 bits a pass (planner tables hold 10^5 entries).
+void radix_order(std::vector<std::pair<uint64_t, uint32_t>>& a, std::vector<std::pair<uint64_t, uint32_t>>& t,
+                 uint64_t top)
+{
+    constexpr int D = 11;
+    uint32_t cnt[1u << D];
+    t.resize(a.size());
+    for (int sh = 0; sh < 64 && (top >> sh); sh += D) {
+        std::fill(cnt, cnt + (1u << D), 0u);
+        for (const auto& p : a) cnt[(p.first >> sh) & ((1u << D) - 1)]++;
+        uint32_t sum = 0;
+        for (uint32_t& c : cnt) {
+            const uint32_t k = c;
+            c = sum;
+            sum += k;
+        }
+        for (const auto& p : a) t[cnt[(p.first >> sh) & ((1u << D) - 1)]++] = p;
+        a.swap(t);
+    }
+}
+
 // Host-side lists of one call (see Exec::hv).
 struct HostVecs {
     std::vector<LeafDesc> leaves, batch_leaves;
+    std::vector<std::pair<uint64_t, uint32_t>> order, order_tmp;
     std::vector<CrossDesc> crosses, batch_crosses;
     std::vector<CopyDesc> copies;
     bool busy = false;
@@ -1256,7 +1292,7 @@ struct Exec {
             ht.stop();
             for (size_t i = 0; i < sel.size(); i += caps.leaves) {
                 const uint32_t n = (uint32_t)std::min<size_t>(caps.leaves, sel.size() - i);
-                TJ_CK(hipMemcpyAsync(d_leaves, sel.data() + i, n * sizeof(LeafDesc), hipMemcpyHostToDevice, st));
+                TJ_CK(upload(d_leaves, sel.data() + i, n * sizeof(LeafDesc), st, 0));
                 uint64_t rows = 0;
                 for (uint32_t k = 0; k < n; k++) rows += sel[i + k].rn;
                 TJ_CK(timed(F_LEAF_SORT, rows * row_bytes(sh.kb, true) * 2, [&] {
@@ -1348,11 +1384,6 @@ struct Exec {
             return TJ_OK;
         }
         HostTimer ht(this, F_HOST_LEAVES);
-        // key order: the units' R rows in buffer A (LeafDesc/CrossDesc::out until batched)
-        auto lr0 = [](const LeafDesc& a, const LeafDesc& b) { return a.out < b.out; };
-        auto cr0 = [](const CrossDesc& a, const CrossDesc& b) { return a.out < b.out; };
-        if (!std::is_sorted(leaves.begin(), leaves.end(), lr0)) std::sort(leaves.begin(), leaves.end(), lr0);
-        if (!std::is_sorted(crosses.begin(), crosses.end(), cr0)) std::sort(crosses.begin(), crosses.end(), cr0);
         stats.leaves += (uint32_t)leaves.size();
         uint64_t* d_total = d_probe + 2;
         uint32_t* d_ticket = (uint32_t*)(d_probe + 3);
@@ -1376,7 +1407,7 @@ struct Exec {
                         rows += sel[i + k].rn + sel[i + k].sn;
                         wide = wide || sel[i + k].bits > 32;
                     }
-                    TJ_CK(hipMemcpyAsync(d_leaves, sel.data() + i, n * sizeof(LeafDesc), hipMemcpyHostToDevice, st));
+                    TJ_CK(upload(d_leaves, sel.data() + i, n * sizeof(LeafDesc), st, 0));
                     TJ_CK(timed(F_LEAF_COUNT, rows * kb, [&] {
                         return launch_leaf_join(kb, wide, false, d_leaves, n, bufs, d_status, d_ticket, d_total,
                                                 d_err, nullptr, nullptr, 0, st);
@@ -1391,6 +1422,26 @@ struct Exec {
             TJ_CK(hipStreamSynchronize(st));
             *total_out = t + cross_pairs;
         } else {
+            // Key order of the units is the order of their R rows in buffer A
+            // (LeafDesc/CrossDesc::out until batched). Leaves of a level are
+            // appended in that order, deeper levels after: order (position,
+            // index) pairs, a stable LSD radix sort, and read the leaves through them.
+            const std::vector<std::pair<uint64_t, uint32_t>>* ord = nullptr;
+            if (!std::is_sorted(leaves.begin(), leaves.end(),
+                                [](const LeafDesc& a, const LeafDesc& b) { return a.out < b.out; })) {
+                auto& o = hv.order;
+                o.resize(leaves.size());
+                uint64_t top = 0;
+                for (size_t i = 0; i < leaves.size(); i++) {
+                    o[i] = {leaves[i].out, (uint32_t)i};
+                    top = std::max(top, leaves[i].out);
+                }
+                radix_order(o, hv.order_tmp, top);
+                ord = &o;
+            }
+            auto leaf_at = [&](size_t i) -> const LeafDesc& { return ord ? leaves[(*ord)[i].second] : leaves[i]; };
+            auto cr0 = [](const CrossDesc& a, const CrossDesc& b) { return a.out < b.out; };
+            if (!std::is_sorted(crosses.begin(), crosses.end(), cr0)) std::sort(crosses.begin(), crosses.end(), cr0);
             uint64_t carry = base;
             size_t li = 0, ci = 0;
             std::vector<LeafDesc>& bl = hv.batch_leaves;
@@ -1402,7 +1453,7 @@ struct Exec {
                 int bkb = 0;       // key width of the batch's leaves
                 while (li < leaves.size() || ci < crosses.size()) {
                     const bool take_cross =
-                        ci < crosses.size() && (li == leaves.size() || crosses[ci].out < leaves[li].out);
+                        ci < crosses.size() && (li == leaves.size() || crosses[ci].out < leaf_at(li).out);
                     if (take_cross) {
                         if (bc.size() == caps.units) break;
                         CrossDesc c = crosses[ci++];
@@ -1413,9 +1464,9 @@ struct Exec {
                         bc.push_back(c);
                     } else {
                         if (bl.size() == caps.leaves) break;
-                        if (bkb != 0 && leaves[li].kb != bkb) break;  // one launch, one key width
-                        bkb = leaves[li].kb;
-                        LeafDesc L = leaves[li++];
+                        if (bkb != 0 && leaf_at(li).kb != bkb) break;  // one launch, one key width
+                        bkb = leaf_at(li).kb;
+                        LeafDesc L = leaf_at(li++);
                         L.out = pre;
                         bl.push_back(L);
                     }
@@ -1434,7 +1485,7 @@ struct Exec {
                         wide = wide || L.bits > 32;
                     }
                     leaf_timer = pending.size();
-                    TJ_CK(hipMemcpyAsync(d_leaves, bl.data(), nl * sizeof(LeafDesc), hipMemcpyHostToDevice, st));
+                    TJ_CK(upload(d_leaves, bl.data(), nl * sizeof(LeafDesc), st, 0));
                     TJ_CK(timed(F_LEAF_MAT, rows * row_bytes(bkb, true), [&] {
                         return launch_leaf_join(bkb, wide, true, d_leaves, nl, bufs, d_status, d_ticket,
                                                 d_total, d_err, out_r, out_s, capacity, st);
@@ -1448,7 +1499,7 @@ struct Exec {
                         t += c.a * c.b;
                         in_rows += c.a + c.b;
                     }
-                    TJ_CK(hipMemcpyAsync(d_units, bc.data(), nc * sizeof(CrossDesc), hipMemcpyHostToDevice, st));
+                    TJ_CK(upload(d_units, bc.data(), nc * sizeof(CrossDesc), st, 1));
                     TJ_CK(timed(F_CROSS, t * 8 + in_rows * 4, [&] {
                         return launch_cross((const CrossDesc*)d_units, nc, t, bufs, d_status, out_r, out_s,
                                             capacity, st);

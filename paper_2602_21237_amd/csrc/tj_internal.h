@@ -18,7 +18,7 @@ namespace tj {
 constexpr int MAX_DIGIT_BITS = 9;             // widest partition digit
 constexpr int NB = 1 << MAX_DIGIT_BITS;       // digit bins per group (table stride)
 constexpr int PART_THREADS = 1024;            // histogram block
-constexpr int PART_TILE = 8192;               // rows per scatter tile (chunks are multiples)
+constexpr int PART_TILE = 9216;               // rows per scatter tile (chunks are multiples)
 constexpr int CBLOCK = 32;                    // chunks per first-level scan block
 
 enum Buf : uint32_t { BUF_IN = 0, BUF_A = 1, BUF_B = 2 };

@@ -822,7 +822,7 @@ hipError_t launch_scan(const CBlockDesc* cblocks, uint32_t ncblocks, const Group
 // so inside a child (and among children of one window) the narrowed keys
 // order as the originals.
 // ---------------------------------------------------------------------------
-constexpr int SC_NT = 512, SC_KI = 16, SC_NW = SC_NT / 64, SC_TILE = SC_NT * SC_KI;
+constexpr int SC_NT = 512, SC_KI = 18, SC_NW = SC_NT / 64, SC_TILE = SC_NT * SC_KI;
 constexpr int SC_STRIDE = NB + 1;
 static_assert(SC_TILE == PART_TILE, "chunk sizes are planned in scatter tiles");
 

@@ -102,7 +102,7 @@ def test_sort_uniform_64bit_keys(tj):
     check_sort(tj, w["keys"], w["rids"])
 
 
-@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 4095, 4096, 4097, 8191, 8192, 8193, 16383, 16385, 20_000])
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 4095, 4096, 4097, 8191, 8192, 8193, 9215, 9216, 9217, 16383, 16385, 18433, 20_000])
 def test_sort_sizes(tj, n):
     rng = np.random.default_rng(n)
     k = rng.integers(-1000, 1000, n).astype(np.int64)

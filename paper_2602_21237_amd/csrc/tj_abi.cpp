@@ -869,6 +869,7 @@ struct Exec {
                 const uint64_t koff_r = g0.dst_koff, koff_s = nside == 2 ? groups[gi + 1].dst_koff : 0;
                 uint64_t r0 = g0.dst_start, s0 = nside == 2 ? groups[gi + 1].dst_start : 0;
                 for (uint32_t d = 0; d < nbins; d++) {
+                    if (cr[d].rn == 0 && cr[d].sn == 0) continue;  // no rows: every sink ignores it
                     Seg c;
                     c.buf = dst;
                     c.kb = seg_kb;

@@ -404,6 +404,27 @@ HostVecs& borrow_host_vecs(HostVecs*& owned)
     return *owned;
 }
 
+// Frees the calling thread's staging buffers and host lists (see
+// tj::release_thread_staging).
+void free_thread_staging()
+{
+    auto drop = [](PinnedBuf*& b) {
+        if (!b) return;
+        if (b->p) (void)hipHostFree(b->p);
+        delete b;
+        b = nullptr;
+    };
+    drop(t_down);
+    drop(t_up[0]);
+    drop(t_up[1]);
+    delete t_pageable;
+    t_pageable = nullptr;
+    if (t_host_vecs && !t_host_vecs->busy) {
+        delete t_host_vecs;
+        t_host_vecs = nullptr;
+    }
+}
+
 void return_host_vecs(HostVecs& hv, HostVecs* owned)
 {
     hv.clear();
@@ -2309,6 +2330,12 @@ int sort_noalloc(int key_type, const void* keys_in, const int32_t* rids_in, uint
     return sort_impl(key_type, keys_in, rids_in, n, keys_out, rids_out, workspace, workspace_bytes, stream,
                      nullptr, stats);
 }
+
+// Frees the calling thread's pinned staging and host lists. For a thread that
+// made calls and is about to end (a server worker): it runs in ordinary code,
+// not in a thread-exit destructor, and a later call on the same thread would
+// simply allocate them again.
+void release_thread_staging() { free_thread_staging(); }
 }  // namespace tj
 
 extern "C" {

@@ -23,6 +23,10 @@
 
 #include "tj_internal.h"
 
+namespace tj {
+void release_thread_staging();  // frees the calling thread's pinned staging (tj_abi.cpp)
+}
+
 namespace {
 
 constexpr uint64_t kAlign = 256;
@@ -396,7 +400,11 @@ struct tj_server {
         for (;;) {
             bool got = false;
             cv_work.wait(lk, [&] { return (got = admit(batch)) || (stopping && fresh.empty()); });
-            if (!got) return;
+            if (!got) {
+                lk.unlock();
+                tj::release_thread_staging();  // the thread ends: its pinned staging goes with it
+                return;
+            }
             const auto start = Clock::now();
             for (Job* j : batch) {
                 j->admitted = start;

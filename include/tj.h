@@ -74,6 +74,8 @@ typedef struct {
     uint32_t windows;         /* under a binding budget, runs of buckets taken through the
                                  workspace window (sort), or key ranges whose buckets took
                                  further passes there (join); 0 when it does not bind */
+    uint32_t pivots;          /* crowded buckets split three ways around a sampled frequent
+                                 key (below, equal, above) instead of by a radix digit */
     uint64_t sample_rows;     /* keys the learned model was fitted to */
 } tj_stats_t;
 

@@ -218,6 +218,11 @@ const uint64_t kMaxRows = (1ull << 31) - 1;
 // gets one bit.
 constexpr uint64_t SMALL_SEG_ROWS = 16ull * LEAF_CAP;
 constexpr size_t FEW_SEGS = 64;
+// A child bucket is crowded (Seg::skew) when it holds more than SKEW_FACTOR
+// times the rows its parent's digit gave each bucket on average; at most
+// MAX_PIVOT_SEGS crowded buckets of a level are sampled for a pivot key.
+constexpr uint64_t SKEW_FACTOR = 2;
+constexpr size_t MAX_PIVOT_SEGS = 4096;
 inline void plan_digit(uint64_t span, uint64_t rows, bool few, uint32_t& shift, uint32_t& bits)
 {
     const uint64_t want =
@@ -297,6 +302,9 @@ struct Seg {
     // (buffer B): row in B minus row in buffer A of the same data, for side 0
     // (the sort's rows, R) and side 1 (S); 0 everywhere else.
     int64_t wdisp = 0, wdisp_s = 0;
+    // Far more rows than its radix digit gave each bucket of its parent on
+    // average: likely crowded by one frequent key (see Exec::pick_pivots).
+    bool skew = false;
 };
 
 struct Unit {                 // a final piece of join output, ordered by key
@@ -486,6 +494,8 @@ struct Exec {
     // buffer B, a window of win_r / win_s rows (layout_join_window)
     bool window = false;
     uint64_t win_r = 0, win_s = 0;
+    // crowded buckets may split three ways around a frequent key (unlimited plans)
+    bool pivots = false;
 
     // timing of this call's launches (when enabled)
     bool timed_on = false;
@@ -606,11 +616,21 @@ struct Exec {
         // per segment digit choice
         struct Plan {
             uint32_t shift, bits, kb_out;
+            bool pivot;
+            uint64_t key;  // the pivot's ordinal
         };
         std::vector<Plan> plan(segs.size());
+        if (pivots && !filter && !learned) TJ_RET(pick_pivots(segs, plan));
         uint64_t total_rows = 0;
         for (size_t i = 0; i < segs.size(); i++) {
             const Seg& s = segs[i];
+            if (plan[i].pivot) {  // three children: below, equal to, above the pivot; keys keep their width
+                plan[i].shift = 0;
+                plan[i].bits = 2;
+                plan[i].kb_out = s.kb;
+                total_rows += s.rn + s.sn;
+                continue;
+            }
             plan_digit(s.hi - s.lo, s.rn + s.sn, segs.size() <= FEW_SEGS, plan[i].shift, plan[i].bits);
             if (filter && narrow_ranges) plan_digit(s.hi - s.lo, SMALL_SEG_ROWS, true, plan[i].shift, plan[i].bits);
             // join keys are narrowed to 4 bytes once every child spans at most
@@ -696,7 +716,7 @@ struct Exec {
                         const int64_t w = side ? s.wdisp_s : s.wdisp;
                         g.dst_start += (dst == BUF_B ? w : 0) - (src == BUF_B ? w : 0);
                     }
-                    g.base = learned ? 0 : s.lo;
+                    g.base = learned ? 0 : plan[si].pivot ? plan[si].key : s.lo;
                     g.flo = filter ? filter[0] : 0;
                     g.fhi = filter ? filter[1] : ~0ull;
                     g.shift = plan[si].shift;
@@ -710,6 +730,7 @@ struct Exec {
                     child += 1u << g.bits;
                     g.flags = (g_debug_flags.load() & TJ_DEBUG_FORCE_REORDER) ? GROUP_FORCE_REORDER : 0u;
                     if (spec) g.flags |= GROUP_CHECK_RANGE;
+                    if (plan[si].pivot) g.flags |= GROUP_PIVOT;
                     g.src_koff = filter ? 0 : (side ? s.koff_s : s.koff_r);
                     // narrowed keys: at their rows' index in 4-byte key buffers, else
                     // inside the 8-byte footprint of the bucket that narrowed them
@@ -889,6 +910,12 @@ struct Exec {
                 const bool narrowing = seg_kb < kb_in;
                 const uint64_t koff_r = g0.dst_koff, koff_s = nside == 2 ? groups[gi + 1].dst_koff : 0;
                 uint64_t r0 = g0.dst_start, s0 = nside == 2 ? groups[gi + 1].dst_start : 0;
+                // a child with more than SKEW_FACTOR times its share of the
+                // parent's rows under this digit (and more than a leaf holds)
+                // is crowded; children of a pivot split never are (they go radix)
+                const Seg& par = segs[gseg[gi]];
+                const uint64_t share = (par.rn + par.sn) >> g0.bits;
+                const bool may_skew = !(g0.flags & GROUP_PIVOT);
                 for (uint32_t d = 0; d < nbins; d++) {
                     if (cr[d].rn == 0 && cr[d].sn == 0) continue;  // no rows: every sink ignores it
                     Seg c;
@@ -905,6 +932,8 @@ struct Exec {
                     c.koff_s = koff_s;
                     c.wdisp = segs[gseg[gi]].wdisp;
                     c.wdisp_s = segs[gseg[gi]].wdisp_s;
+                    const uint64_t rows = c.rn + c.sn;
+                    c.skew = may_skew && c.lo < c.hi && rows > (uint64_t)LEAF_CAP && rows > SKEW_FACTOR * share;
                     if (narrowing && c.lo <= c.hi) {
                         // keys now hold (ord - g.base) mod 2^32 (see k_scatter)
                         const uint64_t off = c.lo - g0.base;
@@ -918,6 +947,57 @@ struct Exec {
                 }
             }
             stats.bytes_written += written;
+        }
+        return TJ_OK;
+    }
+
+    // ---- pivot choice for crowded buckets ----------------------------------
+    // A crowded bucket (Seg::skew) is usually crowded by one frequent key. A
+    // radix digit separates that key from its neighbours only as fast as the
+    // digit narrows the key range, one level at a time; a split around the key
+    // itself (GROUP_PIVOT: below, equal, above) isolates it in one pass as a
+    // single-key bucket. The key is taken when at least two of three rows
+    // sampled at the start, middle and end of the bucket's larger side hold it;
+    // otherwise the bucket takes its radix digit. Either way the result is the
+    // same: the split only changes how many passes the bucket takes.
+    template <class PlanVec>
+    int pick_pivots(const std::vector<Seg>& segs, PlanVec& plan)
+    {
+        std::vector<size_t> who;
+        const size_t most = std::min<size_t>(MAX_PIVOT_SEGS, caps.children / 3);
+        for (size_t i = 0; i < segs.size() && who.size() < most; i++) {
+            plan[i].pivot = false;
+            const Seg& s = segs[i];
+            if (s.skew && !s.wdisp && !s.wdisp_s && s.buf != BUF_IN) who.push_back(i);
+        }
+        if (who.empty()) return TJ_OK;
+        std::vector<KeyRef> refs(3 * who.size());
+        for (size_t j = 0; j < who.size(); j++) {
+            const Seg& s = segs[who[j]];
+            const int side = s.sn > s.rn ? 1 : 0;
+            const uint64_t r0 = side ? s.s0 : s.r0, n = side ? s.sn : s.rn;
+            const uint64_t koff = side ? s.koff_s : s.koff_r;
+            const char* keys = (const char*)bufs.key[s.buf][side];
+            const uint64_t at[3] = {0, n / 2, n - 1};
+            for (int t = 0; t < 3; t++) refs[3 * j + t] = KeyRef{keys + (r0 + at[t] + koff) * s.kb, s.kb, 0};
+        }
+        // the child records' table is free between passes
+        const uint32_t m = (uint32_t)refs.size();
+        KeyRef* d_refs = (KeyRef*)d_crec;
+        uint64_t* d_out = (uint64_t*)(d_refs + m);
+        uint64_t* got = (uint64_t*)pinned_down((size_t)m * 8);
+        if (!got) return TJ_E_HIP;
+        TJ_CK(upload(d_refs, refs.data(), (size_t)m * sizeof(KeyRef), st, 1));
+        TJ_CK(launch_read_ords(d_refs, m, d_out, st));
+        TJ_CK(hipMemcpyAsync(got, d_out, (size_t)m * 8, hipMemcpyDeviceToHost, st));
+        TJ_CK(hipStreamSynchronize(st));
+        for (size_t j = 0; j < who.size(); j++) {
+            const uint64_t a = got[3 * j], b = got[3 * j + 1], c = got[3 * j + 2];
+            const bool ab = a == b, ac = a == c, bc = b == c;
+            if (!(ab || ac || bc)) continue;
+            plan[who[j]].pivot = true;
+            plan[who[j]].key = ab || ac ? a : b;
+            stats.pivots++;
         }
         return TJ_OK;
     }
@@ -2104,6 +2184,7 @@ static int sort_body(int key_type, const void* keys_in, const int32_t* rids_in, 
     }
     if (unlimited) {
         x.stats.key_ranges = 1;
+        x.pivots = true;
         x.auto_probe = want_learned && is_auto;
         x.spec_range = spec;
         int rc = learned ? x.process_range(0, ~0ull, n, 0, false, 0) : x.process_range(lo, hi, n, 0, false, 0);
@@ -2230,6 +2311,7 @@ static int join_body(int key_type, const void* r_keys, const int32_t* r_rids, ui
     uint64_t total = 0;
     if (unlimited) {
         x.stats.key_ranges = 1;
+        x.pivots = true;
         x.auto_probe = want_learned && is_auto;
         x.spec_range = spec;
         int rc = learned ? x.process_range(0, ~0ull, n_r, n_s, false, 0) : x.process_range(lo, hi, n_r, n_s, false, 0);

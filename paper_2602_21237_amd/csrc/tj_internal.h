@@ -51,6 +51,10 @@ constexpr uint32_t GROUP_WIDE = 2u;
 // GroupDesc::flags: the group's digit range comes from a sampled probe; the
 // histogram flags any row outside [base, base + (nbins << shift)).
 constexpr uint32_t GROUP_CHECK_RANGE = 4u;
+// The group splits three ways around one key instead of by a radix digit:
+// digit 0, 1, 2 for ord < base, ord == base, ord > base (bits = 2, shift 0;
+// keys keep their width).
+constexpr uint32_t GROUP_PIVOT = 8u;
 
 struct GroupDesc {
     uint64_t start;      // first row scanned in the source array
@@ -58,7 +62,7 @@ struct GroupDesc {
     uint64_t dst_start;  // first row of the group in the destination array
     uint64_t base;       // ordinal subtracted before the shift
     uint64_t flo, fhi;   // only rows with flo <= ord <= fhi take part
-    uint32_t shift;      // digit = (ord - base) >> shift
+    uint32_t shift;      // digit = (ord - base) >> shift (GROUP_PIVOT: the side of base)
     uint32_t bits;       // digit width, nbins = 1 << bits
     uint32_t side;       // column set: 0 = R / sorted relation, 1 = S
     uint32_t src, dst;   // buffers
@@ -149,6 +153,12 @@ struct BktSet {
     uint16_t* b[2];
 };
 
+// One key to read back: its address in a buffer and its width (4 or 8 bytes).
+struct KeyRef {
+    const void* p;
+    uint32_t kb, pad;
+};
+
 // Rows per leaf block (the block shape depends on the key word, see the kernels).
 constexpr int LEAF_CAP = 8192;
 
@@ -162,6 +172,8 @@ hipError_t launch_probe(int key_bytes, const void* a, uint64_t na, const void* b
 // Min and max ordinal of every step-th element of a and of b (step 1: all).
 // out[i] = ordinal of a[i * step], i < ceil(n / step)
 hipError_t launch_gather_step(int key_bytes, const void* a, uint64_t n, uint64_t step, uint64_t* out, hipStream_t st);
+// out[i] = ordinal of the key at refs[i] (one 4- or 8-byte key each).
+hipError_t launch_read_ords(const KeyRef* refs, uint32_t n, uint64_t* out, hipStream_t st);
 hipError_t launch_probe_step(int key_bytes, const void* a, uint64_t na, const void* b, uint64_t nb,
                              uint64_t step, uint64_t* minmax, hipStream_t st);
 // range_miss: set to nonzero when a GROUP_CHECK_RANGE group has a row outside its digit range.

@@ -400,6 +400,32 @@ hipError_t launch_gather_step(int key_bytes, const void* a, uint64_t n, uint64_t
     return hipGetLastError();
 }
 
+// Ordinals of single keys anywhere in the buffers: out[i] = ord of the key at
+// refs[i] (4 or 8 bytes). Used to sample a few rows of crowded buckets.
+__global__ __launch_bounds__(256) void k_read_ords(const KeyRef* __restrict__ refs, uint32_t n,
+                                                   uint64_t* __restrict__ out)
+{
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i >= n) return;
+    const KeyRef r = refs[i];
+    out[i] = r.kb == 8 ? ord_of(*(const int64_t*)r.p) : ord_of(*(const int32_t*)r.p);
+}
+
+hipError_t launch_read_ords(const KeyRef* refs, uint32_t n, uint64_t* out, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_read_ords, dim3((n + 255) / 256), dim3(256), 0, st, refs, n, out);
+    return hipGetLastError();
+}
+
+// Digit of ordinal o in a group: its radix digit, or in a pivot group
+// (GROUP_PIVOT) its side of the pivot key `base`: 0 below, 1 equal, 2 above.
+__device__ __forceinline__ uint32_t group_digit(uint64_t o, uint64_t base, uint32_t shift, uint32_t mask,
+                                                bool pivot)
+{
+    return pivot ? (uint32_t)(o >= base) + (uint32_t)(o > base) : (uint32_t)((o - base) >> shift) & mask;
+}
+
 // ---------------------------------------------------------------------------
 // radix histogram: per chunk, the digit counts of its rows (and, per group
 // and digit, the smallest and largest ordinal, so that every child bucket
@@ -438,6 +464,7 @@ __global__ __launch_bounds__(NT) void k_hist(const ChunkDesc* __restrict__ chunk
     // [base, base + nbins << shift) would take a wrong digit, so it is flagged
     // (the planner then probes the exact range and repeats the pass).
     const bool check = !LEARNED && (g.flags & GROUP_CHECK_RANGE) != 0;
+    const bool pivot = (g.flags & GROUP_PIVOT) != 0;
     bool miss = false;
     // Rows are counted with LDS atomics. When every valid row of a wave's round
     // falls in one bin (skewed inputs: buckets dominated by one key), the wave
@@ -471,7 +498,7 @@ __global__ __launch_bounds__(NT) void k_hist(const ChunkDesc* __restrict__ chunk
             const bool valid = q < ch.len && o >= g.flo && o <= g.fhi;
             uint32_t d;
             if (LEARNED) d = valid ? lb[LEARNED ? u : 0] : 0u;
-            else d = valid ? (uint32_t)((o - g.base) >> g.shift) & (nbins - 1u) : 0u;
+            else d = valid ? group_digit(o, g.base, g.shift, nbins - 1u, pivot) : 0u;
             if (check) miss = miss || (valid && (o < g.base || ((o - g.base) >> g.shift) >= nbins));
             const uint64_t vm = ballot(valid);
             if (vm == 0) continue;
@@ -859,7 +886,8 @@ __global__ __launch_bounds__(SC_NT) void k_scatter(const ChunkDesc* __restrict__
     const uint32_t w = threadIdx.x / 64, l = threadIdx.x & 63;
     const bool force_reorder = (g.flags & GROUP_FORCE_REORDER) != 0;
 
-    auto digit_of = [&](K k) { return (uint32_t)((ord_of(k) - g.base) >> g.shift) & mask; };
+    const bool pivot = (g.flags & GROUP_PIVOT) != 0;
+    auto digit_of = [&](K k) { return group_digit(ord_of(k), g.base, g.shift, mask, pivot); };
     // a narrowing launch may hold groups that keep their 8-byte keys (uniform per block)
     const bool wide = sizeof(KO) < sizeof(K) && (g.flags & GROUP_WIDE) != 0;
     K* __restrict__ dst_kw = (K*)bufs.key[g.dst][g.side] + g.dst_koff;
@@ -895,7 +923,7 @@ __global__ __launch_bounds__(SC_NT) void k_scatter(const ChunkDesc* __restrict__
             const uint64_t o = ord_of(key[r]);
             val[r] = q < ch.len && o >= g.flo && o <= g.fhi;
             if (DIGIN) dig[r] = val[r] ? bin[DIGIN ? r : 0] & mask : 0u;
-            else dig[r] = val[r] ? (uint32_t)((o - g.base) >> g.shift) & mask : 0u;
+            else dig[r] = val[r] ? group_digit(o, g.base, g.shift, mask, pivot) : 0u;
         }
         for (uint32_t i = l; i < NB; i += 64) cnt[w * SC_STRIDE + i] = 0;
         // Rank inside the wave: one LDS atomic per row on the wave's own
@@ -973,7 +1001,7 @@ __global__ __launch_bounds__(SC_NT) void k_scatter(const ChunkDesc* __restrict__
                 r2[r] = RIDS && q < ch.len ? src_r[q] : 0;
                 const uint64_t o = ord_of(k2[r]);
                 val[r] = q < ch.len && o >= g.flo && o <= g.fhi;
-                dig[r] = val[r] ? (uint32_t)((o - g.base) >> g.shift) & mask : 0u;
+                dig[r] = val[r] ? group_digit(o, g.base, g.shift, mask, pivot) : 0u;
             }
             for (uint32_t i = l; i < NB; i += 64) cnt[w * SC_STRIDE + i] = 0;
 #pragma unroll

@@ -36,7 +36,7 @@ class Stats(ctypes.Structure):
                 ("leaves", ctypes.c_uint32), ("single_key", ctypes.c_uint32),
                 ("key_ranges", ctypes.c_uint32), ("learned", ctypes.c_uint32),
                 ("learned_overflow", ctypes.c_uint32), ("windows", ctypes.c_uint32),
-                ("sample_rows", ctypes.c_uint64)]
+                ("pivots", ctypes.c_uint32), ("sample_rows", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

@@ -677,13 +677,18 @@ hipError_t launch_children(const GroupDesc* groups, uint32_t ngroups, int nside,
 // ---------------------------------------------------------------------------
 // Leaf batching of a level on the device, for the common last level where
 // every child fits one LDS block: the host then reads back three words instead
-// of one record per child. One wave per segment stages the segment's child
-// records in LDS and its first lane batches adjacent children greedily into
-// leaves of at most LEAF_CAP rows (a child whose keys were narrowed into
-// another 2^32 window starts a new leaf), as the host planner does. A child
-// over LEAF_CAP sets BATCH_NEEDS_HOST and the host redoes the level. Pass 0
-// counts the leaves of each segment; pass 1 writes them after the leaves of
-// the earlier segments of the batch.
+// of one record per child. One wave per segment. Adjacent children are batched
+// greedily into leaves of at most LEAF_CAP rows (a child whose keys were
+// narrowed into another 2^32 window starts a new leaf), as the host planner
+// does; a child over LEAF_CAP sets BATCH_NEEDS_HOST and the host redoes the
+// level. The greedy choice is the only sequential part: a uniform loop over
+// the children's row counts marks where leaves start (a 512-bit mask in
+// scalar registers). Everything else is per child, across the lanes:
+// exclusive prefix sums of the rows give each leaf its first rows and sizes,
+// the last non-empty child before the next start gives its largest key, and a
+// prefix count of children with rows on both sides tells whether a join leaf
+// can produce pairs. Pass 0 counts the useful leaves of each segment; pass 1
+// writes them after the leaves of the earlier segments of the batch.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_batch_leaves(const GroupDesc* __restrict__ groups,
                                                      const ChildRec* __restrict__ crec, BatchArgs a,
@@ -691,125 +696,160 @@ __global__ __launch_bounds__(64) void k_batch_leaves(const GroupDesc* __restrict
                                                      LeafDesc* __restrict__ leaves,
                                                      unsigned long long* __restrict__ summary, int pass)
 {
-    constexpr int RPL = NB / 64;  // child records held per lane
+    constexpr int RPL = NB / 64;  // children per lane: child d = j*64 + lane
+    __shared__ uint32_t s_rpre[NB + 1], s_spre[NB + 1], s_both[NB + 1];  // exclusive prefixes
+    __shared__ uint32_t s_last[NB];  // last non-empty child at or before d
+    __shared__ uint64_t s_hi[NB];
     const uint32_t sgi = blockIdx.x, l = threadIdx.x;
     const GroupDesc g0 = groups[sgi * a.nside];
     const uint64_t s_start = a.nside == 2 ? groups[sgi * 2 + 1].dst_start : 0;
     const uint64_t koff_s = a.nside == 2 ? groups[sgi * 2 + 1].dst_koff : 0;
     const uint32_t nb = 1u << g0.bits;
     const ChildRec* cr = crec + g0.child0 / a.nside;
-    // child d = j*64 + lane sits in lane (d mod 64), slot j; the batching loop
-    // below reads it with readlane, so it runs on wave-uniform values without
-    // a memory round trip per child
-    uint32_t rrn[RPL], rsn[RPL], rlo0[RPL], rlo1[RPL], rhi0[RPL], rhi1[RPL];
+    uint32_t rows[RPL], win[RPL];
+    uint64_t lo[RPL];
+    bool big = false;
+    uint32_t rc = 0, sc = 0, bc = 0, lastc = 0;  // carries of the prefixes across slots
 #pragma unroll
     for (int j = 0; j < RPL; j++) {
         const uint32_t d = j * 64 + l;
-        const ChildRec c = d < nb ? cr[d] : ChildRec{0, 0, 0, 0};
-        rrn[j] = c.rn;
-        rsn[j] = c.sn;
-        rlo0[j] = (uint32_t)c.lo;
-        rlo1[j] = (uint32_t)(c.lo >> 32);
-        rhi0[j] = (uint32_t)c.hi;
-        rhi1[j] = (uint32_t)(c.hi >> 32);
-    }
-    uint64_t before = 0;
-    if (pass == 1) {
-        for (uint32_t i = l; i < sgi; i += 64) before += seg_count[i];
-        before = wave_sum64(before);
-    }
-    uint32_t nleaf = 0;
-    uint64_t rows_all = 0, fl = 0;
-    bool open = false, useful = false;
-    uint64_t r0 = g0.dst_start, s0 = s_start, lr0 = 0, ls0 = 0, lrn = 0, lsn = 0, llo = 0, lhi = 0, lwin = 0;
-    auto flush = [&]() {
-        if (open && useful) {
-            if (pass == 1) {
-                const uint64_t slot = a.leaf_base + before + nleaf;
-                if (slot < a.leaf_cap) {
-                    const uint64_t span = lhi - llo;
-                    const uint32_t bits = span ? 64u - (uint32_t)__clzll((long long)span) : 0u;
-                    if (l == 0) {
-                        LeafDesc L;
-                        L.r0 = lr0;
-                        L.s0 = ls0;
-                        L.kr0 = lr0 + g0.dst_koff;
-                        L.ks0 = ls0 + koff_s;
-                        L.base = llo;
-                        L.out = a.join ? 0 : lr0 + a.out_delta;
-                        L.rn = (uint32_t)lrn;
-                        L.sn = (uint32_t)lsn;
-                        L.bits = (uint16_t)bits;
-                        L.kb = (uint16_t)a.kb;
-                        L.buf = (uint16_t)a.buf;
-                        L.flags = (uint16_t)a.flags;
-                        leaves[slot] = L;
-                    }
-                    if (bits > 32) fl |= BATCH_WIDE;
-                } else {
-                    fl |= BATCH_OVERFLOW;
-                }
-                rows_all += lrn + lsn;
-            }
-            nleaf++;
+        const ChildRec c = d < nb ? cr[d] : ChildRec{0, 0, ~0ull, 0};
+        rows[j] = c.rn + c.sn;
+        big = big || rows[j] > (uint32_t)LEAF_CAP;
+        uint64_t clo = c.lo, chi = c.hi;
+        win[j] = 0;
+        if (a.narrowing && rows[j]) {
+            const uint64_t off = clo - g0.base;
+            win[j] = (uint32_t)(off >> 32);
+            clo = off & 0xffffffffull;
+            chi = (chi - g0.base) & 0xffffffffull;
         }
-        open = false;
-        useful = false;
-    };
+        lo[j] = clo;
+        const uint32_t both = c.rn > 0 && c.sn > 0 ? 1u : 0u;
+        const uint32_t ri = wave_incl_scan(c.rn), si = wave_incl_scan(c.sn), bi = wave_incl_scan(both);
+        const uint32_t li = wave_incl_max(rows[j] ? d + 1 : 0u);  // 1 + last non-empty child so far
+        if (d < nb) {
+            s_rpre[d] = rc + ri - c.rn;
+            s_spre[d] = sc + si - c.sn;
+            s_both[d] = bc + bi - both;
+            const uint32_t lst = li > lastc ? li : lastc;
+            s_last[d] = lst ? lst - 1 : 0u;
+            s_hi[d] = chi;
+        }
+        rc += (uint32_t)__shfl((int)ri, 63, 64);
+        sc += (uint32_t)__shfl((int)si, 63, 64);
+        bc += (uint32_t)__shfl((int)bi, 63, 64);
+        const uint32_t lm = (uint32_t)__shfl((int)li, 63, 64);
+        lastc = lm > lastc ? lm : lastc;
+    }
+    if (l == 0) {
+        s_rpre[nb] = rc;
+        s_spre[nb] = sc;
+        s_both[nb] = bc;
+    }
+    if (ballot(big)) {  // the host plans this level
+        if (l == 0) atomicOr(&summary[2], (unsigned long long)BATCH_NEEDS_HOST);
+        return;
+    }
+    // greedy batching: bit d of start[] marks a child that opens a leaf
+    uint64_t start[RPL];
+    {
+        bool open = false;
+        uint32_t acc = 0, lwin = 0;
+#pragma unroll
+        for (int j = 0; j < RPL; j++) {
+            uint64_t m = 0;
+            const uint64_t ne = ballot(rows[j] > 0);
+            uint64_t todo = ne;
+            while (todo) {
+                const uint32_t ln = (uint32_t)__builtin_ctzll(todo);
+                todo &= todo - 1;
+                const uint32_t r = (uint32_t)__builtin_amdgcn_readlane((int)rows[j], (int)ln);
+                const uint32_t w = (uint32_t)__builtin_amdgcn_readlane((int)win[j], (int)ln);
+                if (!open || w != lwin || acc + r > (uint32_t)LEAF_CAP) {
+                    m |= 1ull << ln;
+                    open = true;
+                    lwin = w;
+                    acc = 0;
+                }
+                acc += r;
+            }
+            start[j] = m;
+        }
+    }
+    lds_barrier();  // the prefix tables are complete
+    // per leaf (its starting child): extent, sizes, key range, usefulness
+    uint32_t useful[RPL], e_of[RPL];
 #pragma unroll
     for (int j = 0; j < RPL; j++) {
-        for (uint32_t ln = 0; ln < 64 && j * 64 + ln < nb; ln++) {
-            const uint32_t rn = (uint32_t)__builtin_amdgcn_readlane((int)rrn[j], (int)ln);
-            const uint32_t sn = (uint32_t)__builtin_amdgcn_readlane((int)rsn[j], (int)ln);
-            const uint64_t rows = (uint64_t)rn + sn;
-            if (rows == 0) continue;  // occupies no rows: does not break adjacency
-            if (rows > (uint64_t)LEAF_CAP) {
-                fl |= BATCH_NEEDS_HOST;
-                flush();
-                r0 += rn;
-                s0 += sn;
-                continue;
-            }
-            uint64_t lo = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)rlo0[j], (int)ln) |
-                          ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)rlo1[j], (int)ln) << 32);
-            uint64_t hi = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)rhi0[j], (int)ln) |
-                          ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)rhi1[j], (int)ln) << 32);
-            uint64_t win = 0;
-            if (a.narrowing) {
-                const uint64_t off = lo - g0.base;
-                win = off >> 32;
-                lo = off & 0xffffffffull;
-                hi = (hi - g0.base) & 0xffffffffull;
-            }
-            if (!(open && win == lwin && lrn + lsn + rows <= (uint64_t)LEAF_CAP)) {
-                flush();
-                open = true;
-                lr0 = r0;
-                ls0 = s0;
-                lrn = lsn = 0;
-                llo = lo;
-                lhi = hi;
-                lwin = win;
-            }
-            lrn += rn;
-            lsn += sn;
-            llo = lo < llo ? lo : llo;
-            lhi = hi > lhi ? hi : lhi;
-            useful = useful || !a.join || (rn > 0 && sn > 0);
-            r0 += rn;
-            s0 += sn;
+        const uint32_t d = j * 64 + l;
+        const bool st = (start[j] >> l) & 1ull;
+        // next start after d, else the end of the segment's children
+        uint32_t e = nb;
+        const uint64_t above = l == 63 ? 0ull : start[j] & (~0ull << (l + 1));
+        if (above) {
+            e = j * 64 + (uint32_t)__builtin_ctzll(above);
+        } else {
+#pragma unroll
+            for (int k = j + 1; k < RPL; k++)
+                if (e == nb && start[k]) e = k * 64 + (uint32_t)__builtin_ctzll(start[k]);
         }
+        e_of[j] = e;
+        useful[j] = st && (!a.join || s_both[e] - s_both[d] > 0) ? 1u : 0u;
     }
-    flush();
-    if (l != 0) return;
+    // emission order: useful leaves in child order
+    uint32_t idx[RPL], nleaf = 0;
+#pragma unroll
+    for (int j = 0; j < RPL; j++) {
+        const uint64_t um = ballot(useful[j] != 0);
+        idx[j] = nleaf + mbcnt(um);
+        nleaf += (uint32_t)__popcll(um);
+    }
     if (pass == 0) {
-        seg_count[sgi] = nleaf;
-        if (fl) atomicOr(&summary[2], (unsigned long long)fl);
-    } else {
-        atomicAdd(&summary[0], (unsigned long long)nleaf);
-        atomicAdd(&summary[1], (unsigned long long)rows_all);
-        if (fl) atomicOr(&summary[2], (unsigned long long)fl);
+        if (l == 0) seg_count[sgi] = nleaf;
+        return;
     }
+    uint64_t before = 0;
+    for (uint32_t i = l; i < sgi; i += 64) before += seg_count[i];
+    before = wave_sum64(before);
+    uint64_t rows_all = 0;
+    bool wide = false, over = false;
+#pragma unroll
+    for (int j = 0; j < RPL; j++) {
+        if (!useful[j]) continue;
+        const uint32_t d = j * 64 + l, e = e_of[j];
+        const uint32_t rn = s_rpre[e] - s_rpre[d], sn = s_spre[e] - s_spre[d];
+        rows_all += (uint64_t)rn + sn;
+        const uint64_t slot = a.leaf_base + before + idx[j];
+        if (slot >= a.leaf_cap) {
+            over = true;
+            continue;
+        }
+        const uint64_t llo = lo[j], lhi = s_hi[s_last[e - 1]];
+        const uint64_t span = lhi - llo;
+        const uint32_t bits = span ? 64u - (uint32_t)__clzll((long long)span) : 0u;
+        wide = wide || bits > 32;
+        LeafDesc L;
+        L.r0 = g0.dst_start + s_rpre[d];
+        L.s0 = s_start + s_spre[d];
+        L.kr0 = L.r0 + g0.dst_koff;
+        L.ks0 = L.s0 + koff_s;
+        L.base = llo;
+        L.out = a.join ? 0 : L.r0 + a.out_delta;
+        L.rn = rn;
+        L.sn = sn;
+        L.bits = (uint16_t)bits;
+        L.kb = (uint16_t)a.kb;
+        L.buf = (uint16_t)a.buf;
+        L.flags = (uint16_t)a.flags;
+        leaves[slot] = L;
+    }
+    rows_all = wave_sum64(rows_all);
+    const uint64_t fl = (ballot(wide) ? BATCH_WIDE : 0ull) | (ballot(over) ? BATCH_OVERFLOW : 0ull);
+    if (l != 0) return;
+    atomicAdd(&summary[0], (unsigned long long)nleaf);
+    atomicAdd(&summary[1], (unsigned long long)rows_all);
+    if (fl) atomicOr(&summary[2], (unsigned long long)fl);
 }
 
 hipError_t launch_batch_leaves(const GroupDesc* groups, const ChildRec* crec, const BatchArgs& a,

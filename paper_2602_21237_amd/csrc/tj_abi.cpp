@@ -414,6 +414,39 @@ HostVecs& borrow_host_vecs(HostVecs*& owned)
 
 // Frees the calling thread's staging buffers and host lists (see
 // tj::release_thread_staging).
+// Timing events are reused from a per-thread pool (creating and destroying
+// two events per timed launch cost more host time than the launch itself).
+// Each entry remembers the device it was created on.
+thread_local std::vector<std::pair<int, hipEvent_t>>* t_events = nullptr;
+
+hipEvent_t take_event()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    if (t_events)
+        for (size_t i = t_events->size(); i-- > 0;)
+            if ((*t_events)[i].first == dev) {
+                const hipEvent_t e = (*t_events)[i].second;
+                (*t_events)[i] = t_events->back();
+                t_events->pop_back();
+                return e;
+            }
+    hipEvent_t e = nullptr;
+    return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+}
+
+void give_event(hipEvent_t e)
+{
+    if (!e) return;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipEventDestroy(e);
+        return;
+    }
+    if (!t_events) t_events = new std::vector<std::pair<int, hipEvent_t>>();
+    t_events->push_back({dev, e});
+}
+
 void free_thread_staging()
 {
     auto drop = [](PinnedBuf*& b) {
@@ -430,6 +463,11 @@ void free_thread_staging()
     if (t_host_vecs && !t_host_vecs->busy) {
         delete t_host_vecs;
         t_host_vecs = nullptr;
+    }
+    if (t_events) {
+        for (auto& pe : *t_events) (void)hipEventDestroy(pe.second);
+        delete t_events;
+        t_events = nullptr;
     }
 }
 
@@ -505,8 +543,12 @@ struct Exec {
     hipError_t timed(int fam, uint64_t bytes, F&& f)
     {
         if (!timed_on) return f();
-        Pending p{fam, nullptr, nullptr, bytes};
-        if (hipEventCreate(&p.a) != hipSuccess || hipEventCreate(&p.b) != hipSuccess) return hipErrorUnknown;
+        Pending p{fam, take_event(), take_event(), bytes};
+        if (!p.a || !p.b) {
+            give_event(p.a);
+            give_event(p.b);
+            return hipErrorUnknown;
+        }
         hipError_t e = hipEventRecord(p.a, st);
         if (e == hipSuccess) e = f();
         if (e == hipSuccess) e = hipEventRecord(p.b, st);
@@ -522,13 +564,16 @@ struct Exec {
         std::lock_guard<std::mutex> g(t.mu);
         for (Pending& p : pending) {
             float ms = 0;
-            if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            // (the call has synchronised its stream; an error path may not have)
+            hipError_t r = hipEventElapsedTime(&ms, p.a, p.b);
+            if (r == hipErrorNotReady && hipEventSynchronize(p.b) == hipSuccess) r = hipEventElapsedTime(&ms, p.a, p.b);
+            if (r == hipSuccess) {
                 t.launches[p.fam]++;
                 t.bytes[p.fam] += p.bytes;
                 t.ms[p.fam] += ms;
             }
-            (void)hipEventDestroy(p.a);
-            (void)hipEventDestroy(p.b);
+            give_event(p.a);
+            give_event(p.b);
         }
         pending.clear();
     }

@@ -382,6 +382,7 @@ void radix_order(std::vector<std::pair<uint64_t, uint32_t>>& a, std::vector<std:
 struct HostVecs {
     std::vector<LeafDesc> leaves, batch_leaves;
     std::vector<std::pair<uint64_t, uint32_t>> order, order_tmp;
+    std::vector<BigChild> big;
     std::vector<CrossDesc> crosses, batch_crosses;
     std::vector<CopyDesc> copies;
     bool busy = false;
@@ -689,15 +690,13 @@ struct Exec {
             }
             total_rows += filter ? (uint64_t)(i == 0 ? sh.n_r + sh.n_s : 0) : s.rn + s.sn;
         }
-        // Device batching pays where the children are expected to be leaves and
-        // are many: one wave walks each segment's children in turn (~0.1 ms),
-        // while the host needs about 5 ns per child.
+        // Device batching pays where the children are many: one wave per
+        // segment batches them (tens of microseconds for a level), while the
+        // host needs about 5 ns per child. Children too large for a leaf are
+        // listed for the host, which plans only those.
         if (segs.size() < DEVICE_BATCH_MIN_SEGS || learned) dev_ok = false;
         for (const Seg& sg : segs)
             if (sg.wdisp || sg.wdisp_s) dev_ok = false;  // device leaves: one buffer mapping
-        if (dev_ok)
-            for (size_t i = 0; i < segs.size(); i++)
-                if (((segs[i].rn + segs[i].sn) >> plan[i].bits) > (uint64_t)LEAF_CAP / 2) dev_ok = false;
         uint64_t ch_rows = align_up((total_rows + TARGET_CHUNKS - 1) / TARGET_CHUNKS, PART_TILE);
         if (ch_rows < PART_TILE) ch_rows = PART_TILE;
         // make sure the largest group fits the chunk table
@@ -898,11 +897,47 @@ struct Exec {
             }
             // one compact record per child (both sides folded)
             const uint32_t nrec = child / (uint32_t)nside;
+            // Child d of the segment whose first group is gi, with rows [r0, ..) and
+            // [s0, ..) in the destination: a Seg for the sink. Its keys may have been
+            // narrowed by this pass; a child with more than SKEW_FACTOR times its
+            // share of the parent's rows under this digit (and more than a leaf
+            // holds) is crowded, except below a pivot split (those go radix).
+            auto emit_child = [&](uint32_t gi, const ChildRec& cr, uint64_t r0, uint64_t s0) {
+                const GroupDesc& g0 = groups[gi];
+                const Seg& par = segs[gseg[gi]];
+                const uint32_t seg_kb = plan[gseg[gi]].kb_out;
+                Seg c;
+                c.buf = dst;
+                c.kb = seg_kb;
+                c.r0 = r0;
+                c.rn = cr.rn;
+                c.s0 = s0;
+                c.sn = cr.sn;
+                c.lo = cr.lo;
+                c.hi = cr.hi;
+                c.win = par.win;
+                c.koff_r = g0.dst_koff;
+                c.koff_s = nside == 2 ? groups[gi + 1].dst_koff : 0;
+                c.wdisp = par.wdisp;
+                c.wdisp_s = par.wdisp_s;
+                const uint64_t rows = c.rn + c.sn, share = (par.rn + par.sn) >> g0.bits;
+                c.skew = !(g0.flags & GROUP_PIVOT) && c.lo < c.hi && rows > (uint64_t)LEAF_CAP &&
+                         rows > SKEW_FACTOR * share;
+                if (seg_kb < kb_in && c.lo <= c.hi) {
+                    // keys now hold (ord - g.base) mod 2^32 (see k_scatter)
+                    const uint64_t off = c.lo - g0.base;
+                    c.win = g0.base + (off & ~0xffffffffull);
+                    c.lo = off & 0xffffffffull;
+                    c.hi = (c.hi - g0.base) & 0xffffffffull;
+                }
+                sink(c);
+            };
             TJ_CK(launch_children(d_groups, ng, nside, d_ccount, d_gmin, d_gmax, d_crec, st));
             // device leaves of a range share one key width (one leaf launch)
             if (dev_ok && (mixed || (dev_leaves && dev_kb != kb_out))) TJ_RET(demote_device_leaves());
             if (dev_ok) {
-                // batch the children into leaves on the device; the host reads three words
+                // Batch the children into leaves on the device; the host reads back
+                // four summary words and the children too large for a leaf.
                 BatchArgs ba{};
                 ba.nseg = ng / (uint32_t)nside;
                 ba.nside = (uint32_t)nside;
@@ -914,20 +949,44 @@ struct Exec {
                 ba.leaf_base = dev_leaves;
                 ba.leaf_cap = caps.leaves;
                 ba.out_delta = cur_out_delta;
-                uint64_t* d_sum = d_probe + 4;
-                TJ_CK(launch_fill_u64(d_sum, 3, 0, st));
+                uint64_t* d_sum = d_probe + 4;  // [3] (the range-miss word) is cleared with them
+                TJ_CK(launch_fill_u64(d_sum, 5, 0, st));
                 TJ_CK(launch_batch_leaves(d_groups, d_crec, ba, d_segcount, d_leaves, d_sum, 0, st));
                 TJ_CK(launch_batch_leaves(d_groups, d_crec, ba, d_segcount, d_leaves, d_sum, 1, st));
-                uint64_t* sum = (uint64_t*)pinned_down(3 * sizeof(uint64_t));
-                if (!sum) return TJ_E_HIP;
-                TJ_CK(hipMemcpyAsync(sum, d_sum, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+                uint64_t* pin = (uint64_t*)pinned_down(5 * sizeof(uint64_t));
+                if (!pin) return TJ_E_HIP;
+                TJ_CK(hipMemcpyAsync(pin, d_sum, 5 * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
                 TJ_CK(hipStreamSynchronize(st));
-                if (!(sum[2] & (BATCH_NEEDS_HOST | BATCH_OVERFLOW))) {
+                const uint64_t sum[5] = {pin[0], pin[1], pin[2], pin[3], pin[4]};
+                const uint64_t nbig = sum[4];
+                if (!(sum[2] & BATCH_OVERFLOW) && dev_leaves + sum[0] + nbig <= caps.leaves) {
                     stats.bytes_written += written;
                     dev_leaves += (uint32_t)sum[0];
                     dev_rows += sum[1];
                     dev_wide = dev_wide || (sum[2] & BATCH_WIDE);
                     dev_kb = kb_out;
+                    if (nbig == 0) continue;
+                    // The listed children (slot caps.leaves - 1 - k for the k-th)
+                    // go to the sink; the leaves batched so far move to the host
+                    // list first, which later levels then extend.
+                    BigChild* big = (BigChild*)pinned_down((size_t)nbig * sizeof(LeafDesc));
+                    if (!big) return TJ_E_HIP;
+                    TJ_CK(hipMemcpyAsync(big, d_leaves + (caps.leaves - nbig), (size_t)nbig * sizeof(LeafDesc),
+                                         hipMemcpyDeviceToHost, st));
+                    TJ_CK(hipStreamSynchronize(st));
+                    std::vector<BigChild>& bl = hv.big;
+                    bl.resize(nbig);
+                    for (uint64_t k = 0; k < nbig; k++)
+                        bl[k] = *(const BigChild*)((const LeafDesc*)big + (nbig - 1 - k));
+                    TJ_RET(demote_device_leaves());
+                    HostTimer ht(this, F_HOST_CLASSIFY);
+                    for (const BigChild& b : bl) {
+                        const uint32_t gi = b.seg * (uint32_t)nside;
+                        if (b.seg >= ng / (uint32_t)nside) return TJ_E_INTERNAL;
+                        const ChildRec cr{b.rn, b.sn, b.lo, b.hi};
+                        emit_child(gi, cr, groups[gi].dst_start + b.r_off,
+                                   nside == 2 ? groups[gi + 1].dst_start + b.s_off : 0);
+                    }
                     continue;
                 }
                 TJ_RET(demote_device_leaves());  // this level needs the host planner
@@ -950,45 +1009,12 @@ struct Exec {
                 const GroupDesc& g0 = groups[gi];
                 const uint32_t nbins = 1u << g0.bits;
                 const ChildRec* cr = rec + g0.child0 / (uint32_t)nside;
-                const uint64_t parent_win = segs[gseg[gi]].win;
-                const uint32_t seg_kb = plan[gseg[gi]].kb_out;
-                const bool narrowing = seg_kb < kb_in;
-                const uint64_t koff_r = g0.dst_koff, koff_s = nside == 2 ? groups[gi + 1].dst_koff : 0;
                 uint64_t r0 = g0.dst_start, s0 = nside == 2 ? groups[gi + 1].dst_start : 0;
-                // a child with more than SKEW_FACTOR times its share of the
-                // parent's rows under this digit (and more than a leaf holds)
-                // is crowded; children of a pivot split never are (they go radix)
-                const Seg& par = segs[gseg[gi]];
-                const uint64_t share = (par.rn + par.sn) >> g0.bits;
-                const bool may_skew = !(g0.flags & GROUP_PIVOT);
                 for (uint32_t d = 0; d < nbins; d++) {
                     if (cr[d].rn == 0 && cr[d].sn == 0) continue;  // no rows: every sink ignores it
-                    Seg c;
-                    c.buf = dst;
-                    c.kb = seg_kb;
-                    c.r0 = r0;
-                    c.rn = cr[d].rn;
-                    c.s0 = s0;
-                    c.sn = cr[d].sn;
-                    c.lo = cr[d].lo;
-                    c.hi = cr[d].hi;
-                    c.win = parent_win;
-                    c.koff_r = koff_r;
-                    c.koff_s = koff_s;
-                    c.wdisp = segs[gseg[gi]].wdisp;
-                    c.wdisp_s = segs[gseg[gi]].wdisp_s;
-                    const uint64_t rows = c.rn + c.sn;
-                    c.skew = may_skew && c.lo < c.hi && rows > (uint64_t)LEAF_CAP && rows > SKEW_FACTOR * share;
-                    if (narrowing && c.lo <= c.hi) {
-                        // keys now hold (ord - g.base) mod 2^32 (see k_scatter)
-                        const uint64_t off = c.lo - g0.base;
-                        c.win = g0.base + (off & ~0xffffffffull);
-                        c.lo = off & 0xffffffffull;
-                        c.hi = (c.hi - g0.base) & 0xffffffffull;
-                    }
-                    r0 += c.rn;
-                    s0 += c.sn;
-                    sink(c);
+                    emit_child(gi, cr[d], r0, s0);
+                    r0 += cr[d].rn;
+                    s0 += cr[d].sn;
                 }
             }
             stats.bytes_written += written;

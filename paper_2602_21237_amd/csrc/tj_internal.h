@@ -137,10 +137,21 @@ struct BatchArgs {
     uint32_t pad;
     uint64_t out_delta;   // sort: output row of buffer row 0
 };
-// Summary words written by k_batch_leaves (pass 1): leaves, rows, flags.
-constexpr uint64_t BATCH_NEEDS_HOST = 1;  // a child needs another pass or is a large single key
+// Summary words written by k_batch_leaves (pass 1): [0] leaves, [1] rows,
+// [2] flags, [4] children listed for the host ([3] is not touched).
 constexpr uint64_t BATCH_WIDE = 2;        // a leaf spans more than 32 key bits
 constexpr uint64_t BATCH_OVERFLOW = 4;    // the leaf slots ran out
+
+// A child too large for one leaf (it needs another pass, or is a single key),
+// listed by k_batch_leaves for the host planner in the top slots of the leaf
+// table: the k-th listed child of a batch sits in slot leaf_cap - 1 - k.
+struct BigChild {
+    uint32_t seg, child;    // segment of the batch, digit
+    uint32_t r_off, s_off;  // rows of the segment's sides before this child
+    uint32_t rn, sn;
+    uint64_t lo, hi;        // as in ChildRec
+};
+static_assert(sizeof(BigChild) <= sizeof(LeafDesc), "a listed child takes one leaf slot");
 
 struct BufSet {
     const void* key[3][2];

@@ -680,15 +680,20 @@ hipError_t launch_children(const GroupDesc* groups, uint32_t ngroups, int nside,
 // of one record per child. One wave per segment. Adjacent children are batched
 // greedily into leaves of at most LEAF_CAP rows (a child whose keys were
 // narrowed into another 2^32 window starts a new leaf), as the host planner
-// does; a child over LEAF_CAP sets BATCH_NEEDS_HOST and the host redoes the
-// level. The greedy choice is the only sequential part: a uniform loop over
-// the children's row counts marks where leaves start (a 512-bit mask in
-// scalar registers). Everything else is per child, across the lanes:
-// exclusive prefix sums of the rows give each leaf its first rows and sizes,
-// the last non-empty child before the next start gives its largest key, and a
-// prefix count of children with rows on both sides tells whether a join leaf
-// can produce pairs. Pass 0 counts the useful leaves of each segment; pass 1
-// writes them after the leaves of the earlier segments of the batch.
+// does. A child over LEAF_CAP closes the open leaf and is listed for the host
+// (BigChild records at the top of the leaf table, counted in summary[4]): the
+// host plans only those. The greedy choice is the only sequential part: a
+// uniform loop over the children's row counts marks where leaves start (a
+// 512-bit mask in scalar registers). Everything else is per child, across the
+// lanes: exclusive prefix sums of the rows give each leaf its first rows and
+// sizes, the last non-empty child before the leaf's end gives its largest key,
+// and a prefix count of children with rows on both sides tells whether a join
+// leaf can produce pairs. Pass 0 counts the useful leaves and the listed
+// children of each segment; pass 1 writes them after those of the earlier
+// segments of the batch (leaves upwards from leaf_base, listed children
+// downwards from the top of the table; a slot below leaf_base sets
+// BATCH_OVERFLOW, and so does a collision, which the host detects from the
+// totals).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_batch_leaves(const GroupDesc* __restrict__ groups,
                                                      const ChildRec* __restrict__ crec, BatchArgs a,
@@ -708,14 +713,14 @@ __global__ __launch_bounds__(64) void k_batch_leaves(const GroupDesc* __restrict
     const ChildRec* cr = crec + g0.child0 / a.nside;
     uint32_t rows[RPL], win[RPL];
     uint64_t lo[RPL];
-    bool big = false;
+    uint64_t bigm[RPL];  // children over LEAF_CAP, one bit each
     uint32_t rc = 0, sc = 0, bc = 0, lastc = 0;  // carries of the prefixes across slots
 #pragma unroll
     for (int j = 0; j < RPL; j++) {
         const uint32_t d = j * 64 + l;
         const ChildRec c = d < nb ? cr[d] : ChildRec{0, 0, ~0ull, 0};
         rows[j] = c.rn + c.sn;
-        big = big || rows[j] > (uint32_t)LEAF_CAP;
+        bigm[j] = ballot(rows[j] > (uint32_t)LEAF_CAP);
         uint64_t clo = c.lo, chi = c.hi;
         win[j] = 0;
         if (a.narrowing && rows[j]) {
@@ -747,10 +752,6 @@ __global__ __launch_bounds__(64) void k_batch_leaves(const GroupDesc* __restrict
         s_spre[nb] = sc;
         s_both[nb] = bc;
     }
-    if (ballot(big)) {  // the host plans this level
-        if (l == 0) atomicOr(&summary[2], (unsigned long long)BATCH_NEEDS_HOST);
-        return;
-    }
     // greedy batching: bit d of start[] marks a child that opens a leaf
     uint64_t start[RPL];
     {
@@ -765,6 +766,10 @@ __global__ __launch_bounds__(64) void k_batch_leaves(const GroupDesc* __restrict
                 const uint32_t ln = (uint32_t)__builtin_ctzll(todo);
                 todo &= todo - 1;
                 const uint32_t r = (uint32_t)__builtin_amdgcn_readlane((int)rows[j], (int)ln);
+                if (r > (uint32_t)LEAF_CAP) {  // listed for the host; the next child opens a leaf
+                    open = false;
+                    continue;
+                }
                 const uint32_t w = (uint32_t)__builtin_amdgcn_readlane((int)win[j], (int)ln);
                 if (!open || w != lwin || acc + r > (uint32_t)LEAF_CAP) {
                     m |= 1ull << ln;
@@ -784,36 +789,64 @@ __global__ __launch_bounds__(64) void k_batch_leaves(const GroupDesc* __restrict
     for (int j = 0; j < RPL; j++) {
         const uint32_t d = j * 64 + l;
         const bool st = (start[j] >> l) & 1ull;
-        // next start after d, else the end of the segment's children
+        // the leaf ends at the next start or listed child after d, else at
+        // the end of the segment's children
         uint32_t e = nb;
-        const uint64_t above = l == 63 ? 0ull : start[j] & (~0ull << (l + 1));
+        const uint64_t above = l == 63 ? 0ull : (start[j] | bigm[j]) & (~0ull << (l + 1));
         if (above) {
             e = j * 64 + (uint32_t)__builtin_ctzll(above);
         } else {
 #pragma unroll
             for (int k = j + 1; k < RPL; k++)
-                if (e == nb && start[k]) e = k * 64 + (uint32_t)__builtin_ctzll(start[k]);
+                if (e == nb && (start[k] | bigm[k])) e = k * 64 + (uint32_t)__builtin_ctzll(start[k] | bigm[k]);
         }
         e_of[j] = e;
         useful[j] = st && (!a.join || s_both[e] - s_both[d] > 0) ? 1u : 0u;
     }
-    // emission order: useful leaves in child order
-    uint32_t idx[RPL], nleaf = 0;
+    // emission order: useful leaves, and listed children, in child order
+    uint32_t idx[RPL], bidx[RPL], nleaf = 0, nbig = 0;
 #pragma unroll
     for (int j = 0; j < RPL; j++) {
         const uint64_t um = ballot(useful[j] != 0);
         idx[j] = nleaf + mbcnt(um);
         nleaf += (uint32_t)__popcll(um);
+        bidx[j] = nbig + mbcnt(bigm[j]);
+        nbig += (uint32_t)__popcll(bigm[j]);
     }
     if (pass == 0) {
-        if (l == 0) seg_count[sgi] = nleaf;
+        if (l == 0) seg_count[sgi] = nleaf | (nbig << 16);
         return;
     }
-    uint64_t before = 0;
-    for (uint32_t i = l; i < sgi; i += 64) before += seg_count[i];
+    uint64_t before = 0, before_big = 0;
+    for (uint32_t i = l; i < sgi; i += 64) {
+        before += seg_count[i] & 0xffffu;
+        before_big += seg_count[i] >> 16;
+    }
     before = wave_sum64(before);
+    before_big = wave_sum64(before_big);
     uint64_t rows_all = 0;
     bool wide = false, over = false;
+#pragma unroll
+    for (int j = 0; j < RPL; j++) {
+        if (!((bigm[j] >> l) & 1ull)) continue;
+        const uint32_t d = j * 64 + l;
+        const uint64_t k = before_big + bidx[j];
+        if (a.leaf_base + k + 1 > a.leaf_cap) {
+            over = true;
+            continue;
+        }
+        const ChildRec c = cr[d];
+        BigChild b;
+        b.seg = sgi;
+        b.child = d;
+        b.r_off = s_rpre[d];
+        b.s_off = s_spre[d];
+        b.rn = c.rn;
+        b.sn = c.sn;
+        b.lo = c.lo;
+        b.hi = c.hi;
+        *(BigChild*)(leaves + (a.leaf_cap - 1 - k)) = b;
+    }
 #pragma unroll
     for (int j = 0; j < RPL; j++) {
         if (!useful[j]) continue;
@@ -850,6 +883,7 @@ __global__ __launch_bounds__(64) void k_batch_leaves(const GroupDesc* __restrict
     atomicAdd(&summary[0], (unsigned long long)nleaf);
     atomicAdd(&summary[1], (unsigned long long)rows_all);
     if (fl) atomicOr(&summary[2], (unsigned long long)fl);
+    if (nbig) atomicAdd(&summary[4], (unsigned long long)nbig);
 }
 
 hipError_t launch_batch_leaves(const GroupDesc* groups, const ChildRec* crec, const BatchArgs& a,

@@ -136,3 +136,61 @@ def test_pivot_under_budget_is_not_used(tj):
     ko, ro, st = tj.sort(dev(k), dev(r), stats=True, workspace_bytes=1 << 20)
     assert np.array_equal(ko.cpu().numpy(), ek) and np.array_equal(ro.cpu().numpy(), er)
     assert st["pivots"] == 0
+
+
+def _smallest_unlimited_budget(probe):
+    """Smallest workspace (in 64 KiB steps) that still runs the one-range,
+    window-free plan: the full data buffers with the smallest planner tables
+    (256 leaf slots, 1024 children per launch)."""
+    lo, hi = 1 << 16, 1 << 33
+    while hi - lo > (1 << 16):
+        mid = (lo + hi) // 2 // (1 << 16) * (1 << 16)
+        st = probe(mid)
+        if st is not None and st["key_ranges"] == 1 and st["windows"] == 0:
+            hi = mid
+        else:
+            lo = mid
+    return hi
+
+
+def test_small_tables_list_large_children(tj):
+    """Unlimited plans on the smallest planner tables: the device batching of a
+    level overflows its 256 leaf slots, or lists children too large for a leaf
+    next to the leaves it batched, many launches per level; the host plans the
+    rest. Sort and join equal the oracle."""
+    rng = np.random.default_rng(17)
+    hot = [(int(rng.integers(0, 1 << 40)), c) for c in (40_000, 20_000, 15_000, 9_000)]
+    k = _hot_sort_keys(rng, 600_000, hot)
+    r = tjgen.perm_i32(k.size, 8)
+    dk, dr = dev(k), dev(r)
+
+    def probe_sort(ws):
+        try:
+            return tj.sort(dk, dr, workspace_bytes=ws, stats=True)[2]
+        except tj.TjError:
+            return None
+
+    ws = _smallest_unlimited_budget(probe_sort)
+    ek, er = oracle.sort(k, r)
+    ko, ro, st = tj.sort(dk, dr, workspace_bytes=ws, stats=True)
+    assert st["key_ranges"] == 1 and st["windows"] == 0 and st["pivots"] >= 1, st
+    assert np.array_equal(ko.cpu().numpy(), ek) and np.array_equal(ro.cpu().numpy(), er)
+
+    rk = rng.choice(1 << 40, 200_000, replace=False).astype(np.int64)
+    sk = np.concatenate([rk[rng.integers(0, rk.size, 400_000)], np.repeat(rk[:3], [30_000, 12_000, 9_000])])
+    rng.shuffle(sk)
+    rr = rng.permutation(rk.size).astype(np.int32)
+    sr = rng.permutation(sk.size).astype(np.int32)
+    drk, dsk, drr, dsr = dev(rk), dev(sk), dev(rr), dev(sr)
+    exp_r, exp_s, cnt = oracle.join_pairs(rk, rr, sk, sr)
+
+    def probe_join(ws):
+        try:
+            return tj.join(drk, drr, dsk, dsr, capacity=cnt, workspace_bytes=ws, stats=True)[2]
+        except tj.TjError:
+            return None
+
+    ws = _smallest_unlimited_budget(probe_join)
+    pr, ps, st = tj.join(drk, drr, dsk, dsr, capacity=cnt, workspace_bytes=ws, stats=True)
+    assert st["key_ranges"] == 1 and st["windows"] == 0, st
+    assert np.array_equal(pr.cpu().numpy(), exp_r) and np.array_equal(ps.cpu().numpy(), exp_s)

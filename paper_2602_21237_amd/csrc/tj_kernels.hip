@@ -675,9 +675,10 @@ hipError_t launch_children(const GroupDesc* groups, uint32_t ngroups, int nside,
 }
 
 // ---------------------------------------------------------------------------
-// Leaf batching of a level on the device, for the common last level where
-// every child fits one LDS block: the host then reads back three words instead
-// of one record per child. One wave per segment. Adjacent children are batched
+// Leaf batching of a level on the device, for levels of many segments whose
+// children mostly fit one LDS block: the host then reads back four summary
+// words and the few children too large for a leaf instead of one record per
+// child. One wave per segment. Adjacent children are batched
 // greedily into leaves of at most LEAF_CAP rows (a child whose keys were
 // narrowed into another 2^32 window starts a new leaf), as the host planner
 // does. A child over LEAF_CAP closes the open leaf and is listed for the host

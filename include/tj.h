@@ -99,11 +99,11 @@ int tj_workspace_query(int op, int key_type, uint64_t n_r, uint64_t n_s,
  *   keys_in [n] (int32 or int64 per key_type), rids_in [n] int32: inputs.
  *   keys_out[n], rids_out[n]: outputs (device, caller-owned, no overlap).
  * n = 0 is allowed and does nothing.
- * With the full workspace, a bucket crowded by one frequent key (it holds
- * more than twice the rows its parent's digit gave each bucket, and three
- * sampled rows mostly agree on a key) is split below / equal / above that
- * key in its next pass instead of by a radix digit (tj_stats_t.pivots); the
- * output does not depend on it.
+ * A bucket crowded by one frequent key (it holds more than twice the rows
+ * its parent's digit gave each bucket, and three sampled rows mostly agree
+ * on a key) is split below / equal / above that key in its next unfiltered
+ * pass instead of by a radix digit (tj_stats_t.pivots); the output does not
+ * depend on it.
  * Under a binding budget (workspace_bytes below tj_workspace_query's
  * full_bytes) the first partition pass still reads the input once and writes
  * every row into keys_out/rids_out, where leaf buckets are then sorted in

@@ -533,8 +533,8 @@ struct Exec {
     // buffer B, a window of win_r / win_s rows (layout_join_window)
     bool window = false;
     uint64_t win_r = 0, win_s = 0;
-    // crowded buckets may split three ways around a frequent key (unlimited plans)
-    bool pivots = false;
+    // crowded buckets may split three ways around a frequent key
+    bool pivots = true;
 
     // timing of this call's launches (when enabled)
     bool timed_on = false;
@@ -1039,7 +1039,8 @@ struct Exec {
         for (size_t i = 0; i < segs.size() && who.size() < most; i++) {
             plan[i].pivot = false;
             const Seg& s = segs[i];
-            if (s.skew && !s.wdisp && !s.wdisp_s && s.buf != BUF_IN) who.push_back(i);
+            // (a Seg's rows sit at r0 / s0 of its own buffer, window or not)
+            if (s.skew && s.buf != BUF_IN) who.push_back(i);
         }
         if (who.empty()) return TJ_OK;
         std::vector<KeyRef> refs(3 * who.size());
@@ -2255,7 +2256,6 @@ static int sort_body(int key_type, const void* keys_in, const int32_t* rids_in, 
     }
     if (unlimited) {
         x.stats.key_ranges = 1;
-        x.pivots = true;
         x.auto_probe = want_learned && is_auto;
         x.spec_range = spec;
         int rc = learned ? x.process_range(0, ~0ull, n, 0, false, 0) : x.process_range(lo, hi, n, 0, false, 0);
@@ -2382,7 +2382,6 @@ static int join_body(int key_type, const void* r_keys, const int32_t* r_rids, ui
     uint64_t total = 0;
     if (unlimited) {
         x.stats.key_ranges = 1;
-        x.pivots = true;
         x.auto_probe = want_learned && is_auto;
         x.spec_range = spec;
         int rc = learned ? x.process_range(0, ~0ull, n_r, n_s, false, 0) : x.process_range(lo, hi, n_r, n_s, false, 0);

@@ -126,16 +126,26 @@ def test_join_zipf_paper_shaped_with_pivots(tj):
     check_join(tj, w["r_keys"], rr, w["s_keys"], w["s_rids"], lambda p: p >= 1)
 
 
-def test_pivot_under_budget_is_not_used(tj):
-    """Budget-bound plans keep radix digits (pivots apply to unlimited plans)."""
+@pytest.mark.parametrize("budget", [1 << 20, 4 << 20])
+def test_pivot_under_budget(tj, budget):
+    """Budget-bound plans split crowded buckets too, inside the workspace
+    window (rows packed at other offsets than in the output columns) and on
+    the join's 4-byte range keys."""
     rng = np.random.default_rng(16)
-    hot = [(int(rng.integers(0, 1 << 40)), c) for c in (60_000, 30_000)]
+    hot = [(int(rng.integers(0, 1 << 40)), c) for c in (60_000, 30_000, 12_000)]
     k = _hot_sort_keys(rng, 300_000, hot)
     r = tjgen.perm_i32(k.size, 7)
     ek, er = oracle.sort(k, r)
-    ko, ro, st = tj.sort(dev(k), dev(r), stats=True, workspace_bytes=1 << 20)
+    ko, ro, st = tj.sort(dev(k), dev(r), stats=True, workspace_bytes=budget)
     assert np.array_equal(ko.cpu().numpy(), ek) and np.array_equal(ro.cpu().numpy(), er)
-    assert st["pivots"] == 0
+    assert st["windows"] >= 1 and st["pivots"] >= 1, st
+    w = tjgen.hbm_scale(0.99, n_r=1 << 17, n_s=1 << 19, hot=1 << 10)
+    rr = tjgen.perm_i32(1 << 17, 10)
+    exp_r, exp_s, cnt = oracle.join_pairs(w["r_keys"], rr, w["s_keys"], w["s_rids"])
+    pr, ps, st = tj.join(dev(w["r_keys"]), dev(rr), dev(w["s_keys"]), dev(w["s_rids"]), capacity=cnt,
+                         workspace_bytes=budget, stats=True)
+    assert st["key_ranges"] > 1 or st["windows"] >= 1, st
+    assert np.array_equal(pr.cpu().numpy(), exp_r) and np.array_equal(ps.cpu().numpy(), exp_s)
 
 
 def _smallest_unlimited_budget(probe):

@@ -46,6 +46,7 @@ and tuples/s, every result compared with the same request run alone.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -62,6 +63,19 @@ METRIC = "join input tuples/s + sort keys/s (%HBM peak); P50/P99 latency; learne
 
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+class no_gc:
+    """Python's cyclic collector off while a timed loop runs: a collection
+    inside a timed call (several ms with torch loaded) is not the library's
+    time."""
+
+    def __enter__(self):
+        gc.collect()
+        gc.disable()
+
+    def __exit__(self, *exc):
+        gc.enable()
 
 
 def kernel_source_digest() -> str:
@@ -595,13 +609,14 @@ def c1_small(tj, torch, repeats: int = 100, warmup: int = 10):
     res = {"rows_per_side": 10 ** 5, "join_count": count, "repeats": repeats}
     for op, f in ops.items():
         times = []
-        for i in range(warmup + repeats):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            f()
-            torch.cuda.synchronize()
-            if i >= warmup:
-                times.append((time.perf_counter() - t0) * 1e3)
+        with no_gc():
+            for i in range(warmup + repeats):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                f()
+                torch.cuda.synchronize()
+                if i >= warmup:
+                    times.append((time.perf_counter() - t0) * 1e3)
         # kernel time of one call (HIP events of every launch), in separate
         # calls so that the event records do not shift the latency above
         tj.timing(True)
@@ -653,18 +668,19 @@ def hbm_variants(tj, torch, steps: int):
     torch.cuda.synchronize()
     tj.timing(True)
     t_sort, t_join = [], []
-    for i in range(steps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sts = sort()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        cnt, stj = join()
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        t_sort.append(t1 - t0)
-        t_join.append(t2 - t1)
-        log("hbm zipf step %d: sort %.2f ms, join %.2f ms" % (i, (t1 - t0) * 1e3, (t2 - t1) * 1e3))
+    with no_gc():
+        for i in range(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sts = sort()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            cnt, stj = join()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            t_sort.append(t1 - t0)
+            t_join.append(t2 - t1)
+            log("hbm zipf step %d: sort %.2f ms, join %.2f ms" % (i, (t1 - t0) * 1e3, (t2 - t1) * 1e3))
     tj.timing(False)
     fams = tj.timing_read()
     assert cnt == expected, "zipf join count %d != closed form %d" % (cnt, expected)
@@ -894,20 +910,21 @@ def main():
     tj.timing(True)
     torch.cuda.synchronize()
     times, t_sort, t_join = [], [], []
-    for i in range(args.steps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, _, sts = tj.sort(d_sk, d_sr, keys_out=ko, rids_out=ro, workspace=ws_sort, stats=True)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        pr, _, stj = tj.join(d_rk, d_rr, d_skj, d_srj, capacity=cap, out_r=out_r, out_s=out_s,
-                             workspace=ws_join, stats=True)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        times.append(t2 - t0)
-        t_sort.append(t1 - t0)
-        t_join.append(t2 - t1)
-        log("step %d: sort %.2f ms, join %.2f ms" % (i, (t1 - t0) * 1e3, (t2 - t1) * 1e3))
+    with no_gc():
+        for i in range(args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, sts = tj.sort(d_sk, d_sr, keys_out=ko, rids_out=ro, workspace=ws_sort, stats=True)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            pr, _, stj = tj.join(d_rk, d_rr, d_skj, d_srj, capacity=cap, out_r=out_r, out_s=out_s,
+                                 workspace=ws_join, stats=True)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            times.append(t2 - t0)
+            t_sort.append(t1 - t0)
+            t_join.append(t2 - t1)
+            log("step %d: sort %.2f ms, join %.2f ms" % (i, (t1 - t0) * 1e3, (t2 - t1) * 1e3))
     tj.timing(False)
     fams = tj.timing_read()
     # properties of the last step's results that hold at any size

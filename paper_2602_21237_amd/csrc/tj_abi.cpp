@@ -581,6 +581,10 @@ struct Exec {
 
     ~Exec()
     {
+        // A call that failed half way may leave copies from the thread's pinned
+        // staging queued on its stream: they must not read what the next call
+        // stages there.
+        if (hipStreamQuery(st) == hipErrorNotReady) (void)hipStreamSynchronize(st);
         flush_timing();
         return_host_vecs(hv, hv_owned);
     }
@@ -815,9 +819,27 @@ struct Exec {
                     groups[gi].flags |= GROUP_WIDE;
                     mixed = true;
                 }
-            TJ_CK(hipMemcpyAsync(d_groups, groups.data(), ng * sizeof(GroupDesc), hipMemcpyHostToDevice, st));
-            TJ_CK(hipMemcpyAsync(d_chunks, chunks.data(), nc * sizeof(ChunkDesc), hipMemcpyHostToDevice, st));
-            TJ_CK(hipMemcpyAsync(d_cblocks, cblocks.data(), ncb * sizeof(CBlockDesc), hipMemcpyHostToDevice, st));
+            {
+                // the three tables go out from one pinned staging buffer (a copy
+                // from pageable memory would block the host until it is done)
+                const size_t gb = ng * sizeof(GroupDesc), cb = nc * sizeof(ChunkDesc),
+                             bb = ncb * sizeof(CBlockDesc);
+                char* pin = (char*)pinned_up(gb + cb + bb, 0);
+                const char* hg = (const char*)groups.data();
+                const char* hc = (const char*)chunks.data();
+                const char* hb = (const char*)cblocks.data();
+                if (pin) {
+                    std::memcpy(pin, hg, gb);
+                    std::memcpy(pin + gb, hc, cb);
+                    std::memcpy(pin + gb + cb, hb, bb);
+                    hg = pin;
+                    hc = pin + gb;
+                    hb = pin + gb + cb;
+                }
+                TJ_CK(hipMemcpyAsync(d_groups, hg, gb, hipMemcpyHostToDevice, st));
+                TJ_CK(hipMemcpyAsync(d_chunks, hc, cb, hipMemcpyHostToDevice, st));
+                TJ_CK(hipMemcpyAsync(d_cblocks, hb, bb, hipMemcpyHostToDevice, st));
+            }
             TJ_CK(launch_fill_u64(d_gmin, child, ~0ull, st));
             TJ_CK(launch_fill_u64(d_gmax, child, 0ull, st));
             uint64_t scanned = 0, written = 0;  // rows read; bytes written

@@ -111,6 +111,28 @@ def test_sort_sizes(tj, n):
     check_sort(tj, k.astype(np.int32), r)
 
 
+@pytest.mark.parametrize("n", [4095, 4096, 4097, 8191, 8192, 8193, 12289, 40_000])
+def test_sort_wide_key_leaf_sizes(tj, n):
+    """Keys over the full 64-bit range (leaves span more than 32 bits), at
+    sizes around one and two leaf blocks; also duplicated keys."""
+    rng = np.random.default_rng(n + 7)
+    k = rng.integers(I64.min, I64.max, n, dtype=np.int64)
+    k[rng.integers(0, n, n // 16)] = k[rng.integers(0, n, n // 16)]
+    check_sort(tj, k, rng.permutation(n).astype(np.int32))
+
+
+def test_sort_wide_key_uneven_buckets(tj):
+    """A multi-pass sort of 64-bit keys whose buckets differ widely in size:
+    one dense region of the range gets buckets of thousands of rows next to
+    buckets of a few hundred."""
+    rng = np.random.default_rng(99)
+    sparse = rng.integers(I64.min, I64.max, 300_000, dtype=np.int64)
+    dense = rng.integers(-(1 << 50), 1 << 50, 400_000, dtype=np.int64)
+    k = np.concatenate([sparse, dense])
+    rng.shuffle(k)
+    check_sort(tj, k, rng.permutation(k.size).astype(np.int32))
+
+
 def test_sort_edge_distributions(tj):
     rng = np.random.default_rng(42)
     n = 50_000

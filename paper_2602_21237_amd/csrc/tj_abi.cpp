@@ -670,7 +670,9 @@ struct Exec {
             uint64_t key;  // the pivot's ordinal
         };
         std::vector<Plan> plan(segs.size());
-        if (pivots && !filter && !learned) TJ_RET(pick_pivots(segs, plan));
+        // (calls that may not allocate keep their radix digits: their launches
+        // stay the ones checked for an unchanged device memory footprint)
+        if (pivots && !filter && !learned && !t_noalloc) TJ_RET(pick_pivots(segs, plan));
         uint64_t total_rows = 0;
         for (size_t i = 0; i < segs.size(); i++) {
             const Seg& s = segs[i];

@@ -1964,21 +1964,77 @@ __global__ __launch_bounds__(CROSS_THREADS) void k_cross(const CrossDesc* __rest
     uint64_t t = t0 + threadIdx.x;
     if (t >= t1) return;
     uint32_t u = find_unit(pfx, stride, n, t);
-    CrossDesc U = units[u];
-    uint64_t base = U.out + (status[U.leaf_before] & ST_VAL);
-    for (; t < t1; t += CROSS_THREADS) {
-        while (t >= U.pfx + U.a * U.b) {
-            U = units[++u];
-            base = U.out + (status[U.leaf_before] & ST_VAL);
-        }
+    CrossDesc U;
+    uint64_t base = 0, end = 0, i = 0, j = 0;
+    uint32_t qi = 0, qj = 0;  // a step of CROSS_THREADS pairs moves (i, j) by (qi, qj), then carries
+    // pair loc = t - pfx of the unit is (R row i, S row j) with loc = i*b + j;
+    // only a thread's first pair of a unit divides, later pairs step
+    auto enter = [&]() {
+        U = units[u];
+        base = U.out + (status[U.leaf_before] & ST_VAL);
+        end = U.pfx + U.a * U.b;
         const uint64_t loc = t - U.pfx;
-        uint64_t i = (uint64_t)((double)loc / (double)U.b);
+        i = (uint64_t)((double)loc / (double)U.b);
         while (i * U.b > loc) i--;
         while ((i + 1) * U.b <= loc) i++;
-        const uint64_t j = loc - i * U.b;
-        if (base + loc < capacity) {
-            out_r[base + loc] = bufs.rid[U.buf][0][U.r0 + i];
-            out_s[base + loc] = bufs.rid[U.buf][1][U.s0 + j];
+        j = loc - i * U.b;
+        qi = U.b > CROSS_THREADS ? 0u : (uint32_t)(CROSS_THREADS / U.b);
+        qj = (uint32_t)(CROSS_THREADS - (uint64_t)qi * U.b);
+    };
+    auto step = [&](uint64_t& si, uint64_t& sj) {
+        si += qi;
+        sj += qj;
+        if (sj >= U.b) {
+            sj -= U.b;
+            si++;
+        }
+    };
+    constexpr int UNR = 4;  // pairs per thread whose row-id loads are issued together
+    enter();
+    while (t < t1) {
+        if (t >= end) {
+            do ++u; while (t >= units[u].pfx + units[u].a * units[u].b);
+            enter();
+        }
+        const int32_t* __restrict__ rr = bufs.rid[U.buf][0] + U.r0;
+        const int32_t* __restrict__ sr = bufs.rid[U.buf][1] + U.s0;
+        const uint64_t last = t + (UNR - 1) * (uint64_t)CROSS_THREADS;
+        if (last < end && last < t1) {
+            uint64_t ii[UNR], jj[UNR];
+            ii[0] = i;
+            jj[0] = j;
+#pragma unroll
+            for (int k = 1; k < UNR; k++) {
+                ii[k] = ii[k - 1];
+                jj[k] = jj[k - 1];
+                step(ii[k], jj[k]);
+            }
+            int32_t vr[UNR], vs[UNR];
+#pragma unroll
+            for (int k = 0; k < UNR; k++) {
+                vr[k] = rr[ii[k]];
+                vs[k] = sr[jj[k]];
+            }
+#pragma unroll
+            for (int k = 0; k < UNR; k++) {
+                const uint64_t o = base + (t + k * (uint64_t)CROSS_THREADS - U.pfx);
+                if (o < capacity) {
+                    out_r[o] = vr[k];
+                    out_s[o] = vs[k];
+                }
+            }
+            i = ii[UNR - 1];
+            j = jj[UNR - 1];
+            step(i, j);
+            t += UNR * (uint64_t)CROSS_THREADS;
+        } else {
+            const uint64_t o = base + (t - U.pfx);
+            if (o < capacity) {
+                out_r[o] = rr[i];
+                out_s[o] = sr[j];
+            }
+            step(i, j);
+            t += CROSS_THREADS;
         }
     }
 }
